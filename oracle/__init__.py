@@ -1,0 +1,222 @@
+"""CPU oracle for the interface hot path (TEST INFRASTRUCTURE ONLY).
+
+A plain, single-threaded FP64 implementation in C (``vof_oracle.c``) plus a
+numpy reference of the bracket network (``mlp_ref``).  Only the tests, the
+smoke check and the bench's CPU-baseline leg use this package; the product
+library never imports, links or calls it, and the two share no code.
+
+Functions here take :class:`synth.Mesh`-like objects (any object with the CSR
+attributes) and numpy arrays, and return numpy arrays.  Vector fields are
+structure-of-arrays ``[3, N]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vof_oracle.c")
+_SO = os.path.join(_HERE, "_vof_oracle.so")
+
+OK, NOT_MIXED, LEARNED_FALLBACK, DEGENERATE, MAX_ITER, G_SINGULAR, BAD_INPUT, NO_ROOT = range(8)
+
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle in place with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _CMesh(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", ctypes.c_int64), ("n_faces", ctypes.c_int64), ("n_verts", ctypes.c_int64),
+        ("cell_face_off", ctypes.c_void_p), ("cell_face", ctypes.c_void_p),
+        ("face_vert_off", ctypes.c_void_p), ("face_vert", ctypes.c_void_p),
+        ("face_owner", ctypes.c_void_p), ("face_neigh", ctypes.c_void_p),
+        ("face_bc", ctypes.c_void_p), ("vert_xyz", ctypes.c_void_p),
+    ]
+
+
+class _COpts(ctypes.Structure):
+    _fields_ = [
+        ("eps_mixed", ctypes.c_double), ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int),
+        ("vertex_mode", ctypes.c_int), ("fixed_iso", ctypes.c_int), ("iso", ctypes.c_double),
+    ]
+
+
+@lru_cache(maxsize=1)
+def _lib():
+    build()
+    lib = ctypes.CDLL(_SO)
+    P = ctypes.c_void_p
+    lib.orc_face_geometry.argtypes = [P, P, P]
+    lib.orc_cell_geometry.argtypes = [P, P, P]
+    lib.orc_vertex_field.argtypes = [P, P, P, ctypes.c_int, P]
+    lib.orc_cut_cell.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_double, P]
+    lib.orc_grad.argtypes = [P, P, P, P, P, ctypes.c_double, P, ctypes.c_int, ctypes.c_int, P, P]
+    lib.orc_reconstruct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_mass_transfer.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, P, P]
+    for f in ("orc_face_geometry", "orc_cell_geometry", "orc_vertex_field", "orc_cut_cell",
+              "orc_grad", "orc_reconstruct", "orc_mass_transfer"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OMesh:
+    """Holds contiguous copies of a mesh's arrays and the C view onto them."""
+
+    def __init__(self, mesh):
+        self.n_cells = int(mesh.n_cells)
+        self.n_faces = int(mesh.n_faces)
+        self.n_verts = int(mesh.n_verts)
+        self._keep = dict(
+            cfo=np.ascontiguousarray(mesh.cell_face_off, np.int64),
+            cf=np.ascontiguousarray(mesh.cell_face, np.int32),
+            fvo=np.ascontiguousarray(mesh.face_vert_off, np.int64),
+            fv=np.ascontiguousarray(mesh.face_vert, np.int32),
+            ow=np.ascontiguousarray(mesh.face_owner, np.int32),
+            ne=np.ascontiguousarray(mesh.face_neigh, np.int32),
+            bc=np.ascontiguousarray(mesh.face_bc, np.int8),
+            xyz=np.ascontiguousarray(mesh.vert_xyz, np.float64).reshape(3, -1),
+        )
+        k = self._keep
+        self.c = _CMesh(self.n_cells, self.n_faces, self.n_verts, _p(k["cfo"]), _p(k["cf"]), _p(k["fvo"]),
+                        _p(k["fv"]), _p(k["ow"]), _p(k["ne"]), _p(k["bc"]), _p(k["xyz"]))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def _om(mesh) -> OMesh:
+    return mesh if isinstance(mesh, OMesh) else OMesh(mesh)
+
+
+@dataclass
+class Geometry:
+    V: np.ndarray      # [N]
+    xc: np.ndarray     # [3, N]
+    Sf: np.ndarray     # [3, NF]
+    xf: np.ndarray     # [3, NF]
+
+
+def geometry(mesh) -> Geometry:
+    om = _om(mesh)
+    Sf = np.empty((3, om.n_faces))
+    xf = np.empty((3, om.n_faces))
+    V = np.empty(om.n_cells)
+    xc = np.empty((3, om.n_cells))
+    e = _lib().orc_face_geometry(om.ref, _p(Sf), _p(xf))
+    if e:
+        raise RuntimeError(f"orc_face_geometry failed ({e})")
+    e = _lib().orc_cell_geometry(om.ref, _p(V), _p(xc))
+    if e:
+        raise RuntimeError(f"orc_cell_geometry failed ({e})")
+    return Geometry(V, xc, Sf, xf)
+
+
+def vertex_field(mesh, xc, alpha, mode: int = 0) -> np.ndarray:
+    om = _om(mesh)
+    phi = np.empty(om.n_verts)
+    e = _lib().orc_vertex_field(om.ref, _p(np.ascontiguousarray(xc)), _p(np.ascontiguousarray(alpha, float)),
+                                mode, _p(phi))
+    if e:
+        raise RuntimeError("orc_vertex_field failed")
+    return phi
+
+
+def cut_cell(mesh, P: int, xc, phi, s: float) -> dict:
+    om = _om(mesh)
+    res = np.empty(9)
+    e = _lib().orc_cut_cell(om.ref, int(P), _p(np.ascontiguousarray(xc)), _p(np.ascontiguousarray(phi, float)),
+                            float(s), _p(res))
+    if e:
+        raise RuntimeError(f"orc_cut_cell failed ({e})")
+    return {"V": res[0], "S": res[1:4].copy(), "A": res[4], "c": res[5:8].copy(), "nloops": int(res[8])}
+
+
+def reconstruct(mesh, alpha, geom: Geometry | None = None, *, eps_mixed=1e-8, tol_rel=1e-13, max_iter=100,
+                vertex_mode=0, fixed_iso=False, iso=0.5, phi=None, hint_lo=None, hint_hi=None) -> dict:
+    om = _om(mesh)
+    geom = geom or geometry(om)
+    N = om.n_cells
+    alpha = np.ascontiguousarray(alpha, float)
+    out = dict(s=np.empty(N), n=np.empty((3, N)), A=np.empty(N), d=np.empty(N), alpha_got=np.empty(N),
+               status=np.empty(N, np.int32), iters=np.empty(N, np.int32))
+    op = _COpts(eps_mixed, tol_rel, max_iter, vertex_mode, int(bool(fixed_iso)), iso)
+    hl = None if hint_lo is None else np.ascontiguousarray(hint_lo, float)
+    hh = None if hint_hi is None else np.ascontiguousarray(hint_hi, float)
+    ph = None if phi is None else np.ascontiguousarray(phi, float)
+    e = _lib().orc_reconstruct(om.ref, _p(geom.V), _p(geom.xc), _p(alpha), ctypes.byref(op), _p(ph), _p(hl),
+                               _p(hh), _p(out["s"]), _p(out["n"]), _p(out["A"]), _p(out["d"]),
+                               _p(out["alpha_got"]), _p(out["status"]), _p(out["iters"]))
+    if e:
+        raise RuntimeError(f"orc_reconstruct failed ({e})")
+    return out
+
+
+def grad(mesh, geom: Geometry, T, Tb, T_sat, alpha, modified=True, printed=False):
+    om = _om(mesh)
+    N = om.n_cells
+    g = np.empty((3, N))
+    st = np.empty(N, np.int32)
+    e = _lib().orc_grad(om.ref, _p(geom.xc), _p(geom.xf), _p(np.ascontiguousarray(T, float)),
+                        _p(np.ascontiguousarray(Tb, float)), float(T_sat), _p(np.ascontiguousarray(alpha, float)),
+                        int(modified), int(printed), _p(g), _p(st))
+    if e:
+        raise RuntimeError("orc_grad failed")
+    return g, st
+
+
+def mass_transfer(geom: Geometry, alpha, n, A, gradT, k_l, k_v, h_lv, gl=None, gv=None):
+    N = len(A)
+    mdot = np.empty(N)
+    Qdot = np.empty(N)
+    e = _lib().orc_mass_transfer(N, _p(geom.V), _p(np.ascontiguousarray(alpha, float)),
+                                 _p(np.ascontiguousarray(n)), _p(np.ascontiguousarray(A)),
+                                 _p(np.ascontiguousarray(gradT)),
+                                 _p(None if gl is None else np.ascontiguousarray(gl)),
+                                 _p(None if gv is None else np.ascontiguousarray(gv)),
+                                 float(k_l), float(k_v), float(h_lv), _p(mdot), _p(Qdot))
+    if e:
+        raise RuntimeError("orc_mass_transfer failed")
+    return mdot, Qdot
+
+
+def band_mask(mesh, alpha, eps_mixed=1e-8) -> np.ndarray:
+    """Cells that are mixed or own a face crossed by the alpha = 1/2 level."""
+    a = np.asarray(alpha)
+    mixed = (a > eps_mixed) & (a < 1 - eps_mixed)
+    inner = mesh.face_neigh >= 0
+    o = mesh.face_owner[inner]
+    q = mesh.face_neigh[inner]
+    cross = (a[o] - 0.5) * (a[q] - 0.5) < 0
+    band = mixed.copy()
+    band[o[cross]] = True
+    band[q[cross]] = True
+    return band
+
+
+def run_path(wl, **kw) -> dict:
+    """Reconstruct + interface-modified gradient + mass transfer on a workload."""
+    om = OMesh(wl.mesh)
+    geom = geometry(om)
+    rec = reconstruct(om, wl.alpha, geom, **kw)
+    g, gst = grad(om, geom, wl.T, wl.T_bface, wl.T_sat, wl.alpha)
+    mdot, Qdot = mass_transfer(geom, wl.alpha, rec["n"], rec["A"], g, wl.k_l, wl.k_v, wl.h_lv)
+    return dict(geom=geom, rec=rec, grad=g, grad_status=gst, mdot=mdot, Qdot=Qdot, omesh=om)

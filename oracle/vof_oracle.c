@@ -1,0 +1,697 @@
+/* Plain single-threaded FP64 CPU oracle for the interface hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the tests, the smoke check and the bench's CPU
+ * baseline do.  It shares no code with the HIP library.
+ *
+ * What it computes, step by step, in the order the method states it:
+ *
+ *   geometry     face area vectors / centroids, cell volumes / centroids
+ *                (finite-volume cell-centred storage, Sec. 5 and App. B);
+ *   vertex field alpha at the polyhedron vertices (Sec. 2.1 says the iso-
+ *                surface is taken from a field defined at the vertices; the
+ *                cell-to-vertex rule is not given: inverse-distance average
+ *                of the cells sharing the vertex);
+ *   cut          for an isovalue s, edge intersections by linear interpolation
+ *                (Eq. edge_intersection), assembled into iso-polygons through
+ *                the faces (Sec. 2.1, isopolygon assembly); the liquid volume
+ *                by the divergence theorem over the liquid face parts and the
+ *                iso-polygons;
+ *   root-find    bisection on s until the liquid volume equals alpha V_P
+ *                (the volume-matched reading of the reconstruction);
+ *   gradient     least squares over face neighbours with the interface
+ *                modification (Sec. 2.4.4 "Interface-modified temperature
+ *                gradient", Eq. front_interpolation, App. B);
+ *   mass rate    q_l, q_v, mdot = (q_l+q_v)/(h_lv V_P) (Eq. mass_transfer),
+ *                Qdot = -mdot h_lv (Eq. latent_source), only where A_int > 0.
+ *
+ * Conventions where the paper is silent (each one is listed with its reason
+ * in the design notes of the repository):
+ *   - a vertex is liquid when phi >= s;
+ *   - a face with 4 or more crossings pairs each exit with the next entry in
+ *     loop order when the face-mean phi is >= s (liquid connected), else with
+ *     the previous entry;
+ *   - each iso-loop is fanned from its length-weighted polyline centroid;
+ *   - the interface normal points from vapour to liquid;
+ *   - the crossing point of a cell-centre connection is the linear
+ *     interpolation of alpha, t = (a_P - 1/2)/(a_P - a_Q) (the printed
+ *     Eq. front_interpolation gives the mirror point; a flag selects it).
+ *
+ * Compiled with -O2 -ffp-contract=off: no fused multiply-add contraction.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXF 96    /* faces per cell */
+#define ORC_MAXV 256   /* vertices per cell */
+#define ORC_MAXFV 64   /* vertices per face */
+#define ORC_MAXX 512   /* crossings per cell */
+
+enum {
+  ORC_OK = 0,
+  ORC_NOT_MIXED = 1,
+  ORC_LEARNED_FALLBACK = 2,
+  ORC_DEGENERATE = 3,
+  ORC_MAX_ITER = 4,
+  ORC_G_SINGULAR = 5,
+  ORC_BAD_INPUT = 6,
+  ORC_NO_ROOT = 7
+};
+
+typedef struct {
+  int64_t n_cells, n_faces, n_verts;
+  const int64_t *cell_face_off;
+  const int32_t *cell_face;
+  const int64_t *face_vert_off;
+  const int32_t *face_vert;
+  const int32_t *face_owner;
+  const int32_t *face_neigh;
+  const int8_t *face_bc;
+  const double *vert_xyz; /* [3][n_verts] */
+} orc_mesh;
+
+/* ------------------------------------------------------------------ vectors */
+static void v_sub(const double *a, const double *b, double *o) {
+  o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+static void v_cross(const double *a, const double *b, double *o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double v_dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static double v_det(const double *a, const double *b, const double *c) {
+  double t[3];
+  v_cross(b, c, t);
+  return v_dot(a, t);
+}
+static void vtx(const orc_mesh *m, int64_t v, double *o) {
+  o[0] = m->vert_xyz[v];
+  o[1] = m->vert_xyz[m->n_verts + v];
+  o[2] = m->vert_xyz[2 * m->n_verts + v];
+}
+
+/* ----------------------------------------------------------------- geometry */
+/* Face area vector S_f (right-hand rule on the stored loop, i.e. pointing out
+ * of the owner) and area centroid x_f, from the fan of triangles around the
+ * vertex mean.  Output SoA [3][NF]. */
+int orc_face_geometry(const orc_mesh *m, double *Sf, double *xf) {
+  for (int64_t f = 0; f < m->n_faces; ++f) {
+    int64_t o = m->face_vert_off[f], n = m->face_vert_off[f + 1] - o;
+    if (n < 3) return -1;
+    double c[3] = {0, 0, 0}, p[3];
+    for (int64_t k = 0; k < n; ++k) {
+      vtx(m, m->face_vert[o + k], p);
+      c[0] += p[0]; c[1] += p[1]; c[2] += p[2];
+    }
+    c[0] /= (double)n; c[1] /= (double)n; c[2] /= (double)n;
+    double S[3] = {0, 0, 0}, xs[3] = {0, 0, 0}, tri[3][3], a[3], b[3], s[3];
+    /* first pass: total area vector gives the face normal direction */
+    for (int64_t k = 0; k < n; ++k) {
+      vtx(m, m->face_vert[o + k], tri[0]);
+      vtx(m, m->face_vert[o + (k + 1) % n], tri[1]);
+      v_sub(tri[0], c, a);
+      v_sub(tri[1], c, b);
+      v_cross(a, b, s);
+      S[0] += 0.5 * s[0]; S[1] += 0.5 * s[1]; S[2] += 0.5 * s[2];
+    }
+    double Amag = sqrt(v_dot(S, S));
+    if (!(Amag > 0)) return -2;
+    double nh[3] = {S[0] / Amag, S[1] / Amag, S[2] / Amag}, wsum = 0;
+    for (int64_t k = 0; k < n; ++k) {
+      vtx(m, m->face_vert[o + k], tri[0]);
+      vtx(m, m->face_vert[o + (k + 1) % n], tri[1]);
+      v_sub(tri[0], c, a);
+      v_sub(tri[1], c, b);
+      v_cross(a, b, s);
+      double w = 0.5 * v_dot(s, nh);  /* signed triangle area */
+      for (int d = 0; d < 3; ++d) xs[d] += w * (c[d] + tri[0][d] + tri[1][d]) / 3.0;
+      wsum += w;
+    }
+    for (int d = 0; d < 3; ++d) {
+      Sf[d * m->n_faces + f] = S[d];
+      xf[d * m->n_faces + f] = xs[d] / wsum;
+    }
+  }
+  return 0;
+}
+
+/* Cell volume and centroid, from the tetrahedra (o, c_f, v_k, v_k+1) where o
+ * is the vertex mean of the cell and c_f the vertex mean of face f (the cell
+ * is star-shaped with respect to o).  xc is SoA [3][N]. */
+int orc_cell_geometry(const orc_mesh *m, double *V, double *xc) {
+  for (int64_t P = 0; P < m->n_cells; ++P) {
+    double o[3] = {0, 0, 0}, p[3];
+    int64_t cnt = 0;
+    for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+      int32_t f = m->cell_face[i];
+      for (int64_t k = m->face_vert_off[f]; k < m->face_vert_off[f + 1]; ++k) {
+        vtx(m, m->face_vert[k], p);
+        o[0] += p[0]; o[1] += p[1]; o[2] += p[2];
+        ++cnt;
+      }
+    }
+    if (cnt == 0) return -1;
+    /* mean over face-vertex incidences: still an interior point of a convex cell */
+    o[0] /= (double)cnt; o[1] /= (double)cnt; o[2] /= (double)cnt;
+    double vol = 0, mom[3] = {0, 0, 0};
+    for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+      int32_t f = m->cell_face[i];
+      int64_t fo = m->face_vert_off[f], n = m->face_vert_off[f + 1] - fo;
+      double sgn = (m->face_owner[f] == P) ? 1.0 : -1.0;
+      double c[3] = {0, 0, 0};
+      for (int64_t k = 0; k < n; ++k) {
+        vtx(m, m->face_vert[fo + k], p);
+        c[0] += p[0]; c[1] += p[1]; c[2] += p[2];
+      }
+      c[0] /= (double)n; c[1] /= (double)n; c[2] /= (double)n;
+      for (int64_t k = 0; k < n; ++k) {
+        double a[3], b[3], A[3], B[3], C[3];
+        vtx(m, m->face_vert[fo + k], a);
+        vtx(m, m->face_vert[fo + (k + 1) % n], b);
+        v_sub(c, o, A);
+        v_sub(a, o, B);
+        v_sub(b, o, C);
+        double tv = sgn * v_det(A, B, C) / 6.0;
+        vol += tv;
+        for (int d = 0; d < 3; ++d) mom[d] += tv * (o[d] + c[d] + a[d] + b[d]) / 4.0;
+      }
+    }
+    if (!(vol > 0)) return -2;
+    V[P] = vol;
+    for (int d = 0; d < 3; ++d) xc[d * m->n_cells + P] = mom[d] / vol;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------- vertex field */
+/* phi_v = sum_c w_c alpha_c / sum_c w_c over the cells c sharing vertex v,
+ * with w_c = 1/|x_v - x_c| (mode 0, inverse distance) or w_c = 1 (mode 1). */
+int orc_vertex_field(const orc_mesh *m, const double *xc, const double *alpha, int mode, double *phi) {
+  double *num = calloc((size_t)m->n_verts, sizeof(double));
+  double *den = calloc((size_t)m->n_verts, sizeof(double));
+  int64_t *last = malloc((size_t)m->n_verts * sizeof(int64_t));
+  if (!num || !den || !last) { free(num); free(den); free(last); return -1; }
+  for (int64_t v = 0; v < m->n_verts; ++v) last[v] = -1;
+  for (int64_t P = 0; P < m->n_cells; ++P) {
+    for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+      int32_t f = m->cell_face[i];
+      for (int64_t k = m->face_vert_off[f]; k < m->face_vert_off[f + 1]; ++k) {
+        int32_t v = m->face_vert[k];
+        if (last[v] == P) continue; /* each cell once per vertex */
+        last[v] = P;
+        double w = 1.0;
+        if (mode == 0) {
+          double p[3], c[3] = {xc[P], xc[m->n_cells + P], xc[2 * m->n_cells + P]}, d[3];
+          vtx(m, v, p);
+          v_sub(p, c, d);
+          w = 1.0 / sqrt(v_dot(d, d));
+        }
+        num[v] += w * alpha[P];
+        den[v] += w;
+      }
+    }
+  }
+  for (int64_t v = 0; v < m->n_verts; ++v) phi[v] = den[v] > 0 ? num[v] / den[v] : 0.0;
+  free(num); free(den); free(last);
+  return 0;
+}
+
+/* ------------------------------------------------------- cell-local polyhedron */
+typedef struct {
+  int nf, nv;
+  int fo[ORC_MAXF + 1];     /* face offsets into lv */
+  int lv[ORC_MAXF * 8 + ORC_MAXFV]; /* local vertex ids, loops outward from the cell */
+  double X[ORC_MAXV][3];    /* vertex positions relative to the cell centroid */
+  double phi[ORC_MAXV];
+  double cf[ORC_MAXF][3];   /* face vertex mean (relative) */
+  int32_t gv[ORC_MAXV];     /* global vertex ids */
+} poly_t;
+
+static int build_poly(const orc_mesh *m, int64_t P, const double *xP, const double *phi_glob, poly_t *py) {
+  py->nf = 0;
+  py->nv = 0;
+  py->fo[0] = 0;
+  int64_t nfc = m->cell_face_off[P + 1] - m->cell_face_off[P];
+  if (nfc > ORC_MAXF) return -1;
+  for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+    int32_t f = m->cell_face[i];
+    int64_t o = m->face_vert_off[f], n = m->face_vert_off[f + 1] - o;
+    if (n > ORC_MAXFV || py->fo[py->nf] + n > (int)(sizeof(py->lv) / sizeof(int))) return -2;
+    int rev = (m->face_owner[f] != P);
+    for (int64_t k = 0; k < n; ++k) {
+      int32_t g = m->face_vert[o + (rev ? (n - 1 - k) : k)];
+      int l = -1;
+      for (int j = 0; j < py->nv; ++j)
+        if (py->gv[j] == g) { l = j; break; }
+      if (l < 0) {
+        if (py->nv >= ORC_MAXV) return -3;
+        l = py->nv++;
+        py->gv[l] = g;
+        double p[3];
+        vtx(m, g, p);
+        v_sub(p, xP, py->X[l]);
+        py->phi[l] = phi_glob ? phi_glob[g] : 0.0;
+      }
+      py->lv[py->fo[py->nf] + k] = l;
+    }
+    py->fo[py->nf + 1] = py->fo[py->nf] + (int)n;
+    py->nf++;
+  }
+  for (int f = 0; f < py->nf; ++f) {
+    double c[3] = {0, 0, 0};
+    int n = py->fo[f + 1] - py->fo[f];
+    for (int k = 0; k < n; ++k)
+      for (int d = 0; d < 3; ++d) c[d] += py->X[py->lv[py->fo[f] + k]][d];
+    for (int d = 0; d < 3; ++d) py->cf[f][d] = c[d] / (double)n;
+  }
+  return 0;
+}
+
+/* ----------------------------------------------------------------- the cut */
+typedef struct {
+  double V;        /* liquid volume */
+  double S[3];     /* sum of iso-loop area vectors, pointing vapour -> liquid */
+  double A;        /* sum of |S_k| */
+  double c[3];     /* |S_k|-weighted mean of loop centres (relative) */
+  int nloops;
+  int ncross;
+} cut_t;
+
+/* crossing point on the edge between vertices a and b of the polyhedron, at
+ * isovalue s; computed from the liquid end so both faces sharing the edge
+ * obtain the same point (Eq. edge_intersection with alpha_iso = s). */
+static void crossing(const poly_t *py, int a, int b, double s, double *p) {
+  int i = py->phi[a] >= s ? a : b; /* liquid end */
+  int j = (i == a) ? b : a;
+  double lam = (s - py->phi[i]) / (py->phi[j] - py->phi[i]);
+  for (int d = 0; d < 3; ++d) p[d] = py->X[i][d] + lam * (py->X[j][d] - py->X[i][d]);
+}
+
+typedef struct {
+  int ea, eb;      /* exit edge (start) local vertex pair, as min/max */
+  int xa, xb;
+  int na, nb;      /* entry edge (end) */
+  double ps[3];    /* start point (exit crossing) */
+  double pe[3];    /* end point (entry crossing) */
+  int next;        /* next chord along the iso-loop */
+  int done;
+} chord_t;
+
+static int same_edge(int a0, int a1, int b0, int b1) {
+  return (a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0);
+}
+
+int orc_cut_poly(const poly_t *py, double s, cut_t *out) {
+  static chord_t ch[ORC_MAXX];
+  int nch = 0;
+  double Vf = 0;
+  out->ncross = 0;
+  for (int f = 0; f < py->nf; ++f) {
+    int o = py->fo[f], n = py->fo[f + 1] - o;
+    const double *cf = py->cf[f];
+    /* crossings of this face in loop order: position k means edge (k, k+1) */
+    int xk[ORC_MAXFV], xexit[ORC_MAXFV], nx = 0;
+    double fmean = 0;
+    for (int k = 0; k < n; ++k) fmean += py->phi[py->lv[o + k]];
+    fmean /= (double)n;
+    for (int k = 0; k < n; ++k) {
+      int a = py->lv[o + k], b = py->lv[o + (k + 1) % n];
+      int la = py->phi[a] >= s, lb = py->phi[b] >= s;
+      if (la && lb) {
+        Vf += v_det(cf, py->X[a], py->X[b]);
+      } else if (la && !lb) {            /* exit: liquid -> vapour */
+        double p[3];
+        crossing(py, a, b, s, p);
+        Vf += v_det(cf, py->X[a], p);
+        xk[nx] = k; xexit[nx] = 1; ++nx;
+      } else if (!la && lb) {            /* entry: vapour -> liquid */
+        double p[3];
+        crossing(py, a, b, s, p);
+        Vf += v_det(cf, p, py->X[b]);
+        xk[nx] = k; xexit[nx] = 0; ++nx;
+      }
+    }
+    out->ncross += nx;
+    if (nx == 0) continue;
+    /* pair exits with entries; an odd count cannot happen on a closed loop */
+    if (nx % 2) return -1;
+    int liquid_connected = fmean >= s;
+    for (int q = 0; q < nx; ++q) {
+      if (!xexit[q]) continue;
+      int r;
+      if (nx == 2 || liquid_connected) {
+        r = q;
+        do { r = (r + 1) % nx; } while (xexit[r]);
+      } else {
+        r = q;
+        do { r = (r - 1 + nx) % nx; } while (xexit[r]);
+      }
+      if (nch >= ORC_MAXX) return -2;
+      chord_t *c = &ch[nch++];
+      int ka = xk[q], kb = xk[r];
+      c->xa = py->lv[o + ka]; c->xb = py->lv[o + (ka + 1) % n];
+      c->na = py->lv[o + kb]; c->nb = py->lv[o + (kb + 1) % n];
+      crossing(py, c->xa, c->xb, s, c->ps);
+      crossing(py, c->na, c->nb, s, c->pe);
+      c->done = 0;
+      /* the chord closes this face's liquid polygon: exit -> entry */
+      Vf += v_det(cf, c->ps, c->pe);
+    }
+  }
+  /* link chords into iso-loops: after chord c (exit edge E), the loop goes on
+   * with the chord of the neighbouring face whose entry edge is E */
+  for (int i = 0; i < nch; ++i) {
+    ch[i].next = -1;
+    for (int j = 0; j < nch; ++j)
+      if (same_edge(ch[i].xa, ch[i].xb, ch[j].na, ch[j].nb)) { ch[i].next = j; break; }
+    if (ch[i].next < 0) return -3;
+  }
+  double Vi = 0, Ssum[3] = {0, 0, 0}, Asum = 0, cw[3] = {0, 0, 0};
+  int nloops = 0;
+  for (int i = 0; i < nch; ++i) {
+    if (ch[i].done) continue;
+    /* loop points: start points of the chords in link order */
+    int idx[ORC_MAXX], len = 0, j = i;
+    do {
+      if (len >= ORC_MAXX) return -4;
+      idx[len++] = j;
+      ch[j].done = 1;
+      j = ch[j].next;
+    } while (j != i && !ch[j].done);
+    if (j != i) return -5; /* not a permutation cycle */
+    /* fan apex: centroid of the loop taken as a polyline (segments weighted
+     * by length), which moves continuously when two loop points merge at a
+     * polyhedron vertex; the plain mean of the points would jump there */
+    double ck[3] = {0, 0, 0}, ltot = 0;
+    for (int k = 0; k < len; ++k) {
+      const double *a = ch[idx[k]].ps, *b = ch[idx[(k + 1) % len]].ps;
+      double e[3];
+      v_sub(b, a, e);
+      double l = sqrt(v_dot(e, e));
+      for (int d = 0; d < 3; ++d) ck[d] += l * (a[d] + b[d]) * 0.5;
+      ltot += l;
+    }
+    if (ltot > 0) {
+      for (int d = 0; d < 3; ++d) ck[d] /= ltot;
+    } else {
+      for (int d = 0; d < 3; ++d) ck[d] = ch[idx[0]].ps[d];
+    }
+    double Sk[3] = {0, 0, 0};
+    for (int k = 0; k < len; ++k) {
+      const double *a = ch[idx[k]].ps, *b = ch[idx[(k + 1) % len]].ps;
+      double u[3], w[3], t[3];
+      Vi += v_det(ck, a, b);
+      v_sub(a, ck, u);
+      v_sub(b, ck, w);
+      v_cross(u, w, t);
+      /* the fan is oriented out of the liquid; the interface normal is the
+       * opposite (vapour -> liquid) */
+      for (int d = 0; d < 3; ++d) Sk[d] -= 0.5 * t[d];
+    }
+    double Ak = sqrt(v_dot(Sk, Sk));
+    for (int d = 0; d < 3; ++d) {
+      Ssum[d] += Sk[d];
+      cw[d] += Ak * ck[d];
+    }
+    Asum += Ak;
+    ++nloops;
+  }
+  out->V = (Vf + Vi) / 6.0;
+  for (int d = 0; d < 3; ++d) {
+    out->S[d] = Ssum[d];
+    out->c[d] = Asum > 0 ? cw[d] / Asum : 0.0;
+  }
+  out->A = Asum;
+  out->nloops = nloops;
+  return 0;
+}
+
+/* One cut of cell P at isovalue s (test entry point). res = {V, S[3], A, c[3]
+ * relative to the centroid, nloops}. */
+int orc_cut_cell(const orc_mesh *m, int64_t P, const double *xc, const double *phi, double s, double *res) {
+  static poly_t py;
+  double xP[3] = {xc[P], xc[m->n_cells + P], xc[2 * m->n_cells + P]};
+  int e = build_poly(m, P, xP, phi, &py);
+  if (e) return e;
+  cut_t c;
+  e = orc_cut_poly(&py, s, &c);
+  if (e) return e - 10;
+  res[0] = c.V;
+  res[1] = c.S[0]; res[2] = c.S[1]; res[3] = c.S[2];
+  res[4] = c.A;
+  res[5] = c.c[0]; res[6] = c.c[1]; res[7] = c.c[2];
+  res[8] = c.nloops;
+  return 0;
+}
+
+/* ------------------------------------------------------ least-squares solve */
+/* Solve G g = b for symmetric 3x3 G by the explicit inverse (adjugate over
+ * determinant, App. B).  Returns 1 when G is singular: det <= 1e-12 (tr/3)^3. */
+static int solve_sym3(const double G[6] /* xx yy zz xy xz yz */, const double *b, double *g) {
+  double xx = G[0], yy = G[1], zz = G[2], xy = G[3], xz = G[4], yz = G[5];
+  double c00 = yy * zz - yz * yz;
+  double c01 = xz * yz - xy * zz;
+  double c02 = xy * yz - xz * yy;
+  double c11 = xx * zz - xz * xz;
+  double c12 = xy * xz - xx * yz;
+  double c22 = xx * yy - xy * xy;
+  double det = xx * c00 + xy * c01 + xz * c02;
+  double tr = (xx + yy + zz) / 3.0;
+  if (!(det > 1e-12 * tr * tr * tr)) {
+    g[0] = g[1] = g[2] = 0.0;
+    return 1;
+  }
+  g[0] = (c00 * b[0] + c01 * b[1] + c02 * b[2]) / det;
+  g[1] = (c01 * b[0] + c11 * b[1] + c12 * b[2]) / det;
+  g[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) / det;
+  return 0;
+}
+
+/* Least-squares gradient of a cell field (App. B; interface modification of
+ * Sec. 2.4.4).  modified: replace a crossing neighbour by (x_f, value_sat);
+ * printed: use the printed Eq. front_interpolation weight |a_Q-1/2|/|a_P-a_Q|
+ * instead of the linear-interpolation weight (a_P-1/2)/(a_P-a_Q).
+ * Boundary faces with bc==1 act as neighbours at the face centroid with the
+ * value Tb[f]; bc==2 (symmetry) faces are skipped.  grad is SoA [3][N]. */
+int orc_grad(const orc_mesh *m, const double *xc, const double *xf, const double *T, const double *Tb,
+             double T_sat, const double *alpha, int modified, int printed, double *grad, int32_t *status) {
+  int64_t N = m->n_cells;
+  for (int64_t P = 0; P < N; ++P) {
+    double G[6] = {0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};
+    double xP[3] = {xc[P], xc[N + P], xc[2 * N + P]};
+    for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+      int32_t f = m->cell_face[i];
+      double r[3], val;
+      int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+      if (Q >= 0) {
+        double xQ[3] = {xc[Q], xc[N + Q], xc[2 * N + Q]};
+        v_sub(xQ, xP, r);
+        val = T[Q];
+        if (modified && (alpha[P] - 0.5) * (alpha[Q] - 0.5) < 0.0) {
+          double t = printed ? fabs(alpha[Q] - 0.5) / fabs(alpha[P] - alpha[Q])
+                             : (alpha[P] - 0.5) / (alpha[P] - alpha[Q]);
+          r[0] *= t; r[1] *= t; r[2] *= t;
+          val = T_sat;
+        }
+      } else if (m->face_bc[f] == 1) {
+        double x[3] = {xf[f], xf[m->n_faces + f], xf[2 * m->n_faces + f]};
+        v_sub(x, xP, r);
+        val = Tb[f];
+      } else {
+        continue;
+      }
+      double dv = val - T[P];
+      G[0] += r[0] * r[0]; G[1] += r[1] * r[1]; G[2] += r[2] * r[2];
+      G[3] += r[0] * r[1]; G[4] += r[0] * r[2]; G[5] += r[1] * r[2];
+      b[0] += r[0] * dv; b[1] += r[1] * dv; b[2] += r[2] * dv;
+    }
+    double g[3];
+    int sing = solve_sym3(G, b, g);
+    if (status) status[P] = sing ? ORC_G_SINGULAR : ORC_OK;
+    for (int d = 0; d < 3; ++d) grad[d * N + P] = g[d];
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------- reconstruction */
+typedef struct {
+  double eps_mixed;   /* mixed when eps < alpha < 1-eps */
+  double tol_rel;     /* |V/V_P - alpha| <= tol_rel min(alpha, 1-alpha) */
+  int max_iter;
+  int vertex_mode;    /* 0 inverse distance, 1 plain mean */
+  int fixed_iso;      /* 1: no root-find, cut at iso */
+  double iso;
+} orc_opts;
+
+static double ulp_of(double x) {
+  x = fabs(x);
+  return nextafter(x, INFINITY) - x;
+}
+
+/* Reconstruct every mixed cell.  Outputs are dense over cells (SoA vectors
+ * [3][N]); non-mixed cells get s = NaN, n = 0, A = 0, d = 0, alpha_got =
+ * alpha.  phi_in may supply the vertex field (else it is built from alpha);
+ * hint_lo/hint_hi may supply a narrowed initial bracket per cell (NaN = none).
+ */
+int orc_reconstruct(const orc_mesh *m, const double *V, const double *xc, const double *alpha,
+                    const orc_opts *op, const double *phi_in, const double *hint_lo, const double *hint_hi,
+                    double *s_out, double *n_out, double *A_out, double *d_out, double *agot,
+                    int32_t *status, int32_t *iters) {
+  int64_t N = m->n_cells;
+  double *phi = NULL;
+  if (phi_in) {
+    phi = (double *)phi_in;
+  } else {
+    phi = malloc((size_t)m->n_verts * sizeof(double));
+    if (!phi) return -1;
+    orc_vertex_field(m, xc, alpha, op->vertex_mode, phi);
+  }
+  static poly_t py;
+  int err = 0;
+  for (int64_t P = 0; P < N && !err; ++P) {
+    double a = alpha[P];
+    s_out[P] = NAN;
+    A_out[P] = 0; d_out[P] = 0; agot[P] = a; iters[P] = 0;
+    for (int d = 0; d < 3; ++d) n_out[d * N + P] = 0;
+    if (!(a >= 0.0 && a <= 1.0)) { status[P] = ORC_BAD_INPUT; continue; }
+    if (!(a > op->eps_mixed && a < 1.0 - op->eps_mixed)) { status[P] = ORC_NOT_MIXED; continue; }
+    double xP[3] = {xc[P], xc[N + P], xc[2 * N + P]};
+    if (build_poly(m, P, xP, phi, &py)) { err = -2; break; }
+    int st = ORC_OK;
+    double pmin = INFINITY, pmax = -INFINITY;
+    for (int v = 0; v < py.nv; ++v) {
+      if (py.phi[v] < pmin) pmin = py.phi[v];
+      if (py.phi[v] > pmax) pmax = py.phi[v];
+    }
+    if (pmax - pmin <= 1e-12) {
+      /* degenerate vertex field: use the linear field from the plain
+       * least-squares gradient of alpha over the interior face neighbours */
+      st = ORC_DEGENERATE;
+      double G[6] = {0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0}, g[3];
+      for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+        int32_t f = m->cell_face[i];
+        int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+        if (Q < 0) continue;
+        double r[3] = {xc[Q] - xP[0], xc[N + Q] - xP[1], xc[2 * N + Q] - xP[2]};
+        double dv = alpha[Q] - a;
+        G[0] += r[0] * r[0]; G[1] += r[1] * r[1]; G[2] += r[2] * r[2];
+        G[3] += r[0] * r[1]; G[4] += r[0] * r[2]; G[5] += r[1] * r[2];
+        b[0] += r[0] * dv; b[1] += r[1] * dv; b[2] += r[2] * dv;
+      }
+      solve_sym3(G, b, g);
+      pmin = INFINITY; pmax = -INFINITY;
+      for (int v = 0; v < py.nv; ++v) {
+        py.phi[v] = a + v_dot(g, py.X[v]);
+        if (py.phi[v] < pmin) pmin = py.phi[v];
+        if (py.phi[v] > pmax) pmax = py.phi[v];
+      }
+      if (pmax - pmin <= 1e-12) { status[P] = st; continue; }
+    }
+    cut_t c;
+    double s;
+    int it = 0;
+    if (op->fixed_iso) {
+      s = op->iso;
+      if (orc_cut_poly(&py, s, &c)) { err = -3; break; }
+      it = 1;
+    } else {
+      /* bracket ends and their residuals r = V/V_P - alpha; at phi_min the
+       * whole cell is liquid (r = 1 - alpha), at phi_max none of it (r = -alpha) */
+      double lo = pmin, hi = pmax, rlo = 1.0 - a, rhi = -a;
+      double tol = op->tol_rel * (a < 1.0 - a ? a : 1.0 - a);
+      cut_t clo, chi;
+      int have_lo = 0, have_hi = 0, done = 0;
+      s = NAN;
+      if (hint_lo && hint_hi && !isnan(hint_lo[P]) && !isnan(hint_hi[P])) {
+        /* narrowed bracket: verify it with two cuts; when it fails keep the
+         * part of the full bracket that must hold the root */
+        double l2 = hint_lo[P] > pmin ? hint_lo[P] : pmin;
+        double h2 = hint_hi[P] < pmax ? hint_hi[P] : pmax;
+        if (l2 > h2) { l2 = pmin; h2 = pmax; }
+        cut_t cl, chh;
+        if (orc_cut_poly(&py, l2, &cl) || orc_cut_poly(&py, h2, &chh)) { err = -3; break; }
+        it += 2;
+        double rl = cl.V / V[P] - a, rh = chh.V / V[P] - a;
+        if (fabs(rl) <= tol) { s = l2; c = cl; done = 1; }
+        else if (fabs(rh) <= tol) { s = h2; c = chh; done = 1; }
+        else if (rl > 0 && rh < 0) { lo = l2; rlo = rl; clo = cl; have_lo = 1; hi = h2; rhi = rh; chi = chh; have_hi = 1; }
+        else if (rl <= 0) { hi = l2; rhi = rl; chi = cl; have_hi = 1; st = st ? st : ORC_LEARNED_FALLBACK; }
+        else { lo = h2; rlo = rh; clo = chh; have_lo = 1; st = st ? st : ORC_LEARNED_FALLBACK; }
+      }
+      int collapsed = 0;
+      while (!done) {
+        if (it >= op->max_iter) { st = ORC_MAX_ITER; break; }
+        s = lo + (hi - lo) / 2.0;
+        if (orc_cut_poly(&py, s, &c)) { err = -3; break; }
+        ++it;
+        double r = c.V / V[P] - a;
+        if (fabs(r) <= tol) break;
+        if (r > 0) { lo = s; rlo = r; clo = c; have_lo = 1; }
+        else { hi = s; rhi = r; chi = c; have_hi = 1; }
+        double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
+        if (hi - lo <= 2.0 * ulp_of(big)) { collapsed = 1; break; }
+      }
+      if (err) break;
+      if (collapsed) {
+        /* no isovalue meets the tolerance: keep the bracket end whose volume
+         * is nearer alpha V_P (the volume may jump, e.g. where a face with
+         * four crossings changes its pairing) */
+        int take_lo = fabs(rlo) <= fabs(rhi);
+        s = take_lo ? lo : hi;
+        if (take_lo ? have_lo : have_hi) {
+          c = take_lo ? clo : chi;
+        } else {
+          if (orc_cut_poly(&py, s, &c)) { err = -3; break; }
+          ++it;
+        }
+        if (fabs(take_lo ? rlo : rhi) > 1e-10 && st != ORC_MAX_ITER) st = ORC_NO_ROOT;
+      }
+      if (isnan(s)) { status[P] = st; continue; }
+    }
+    double Sm = sqrt(v_dot(c.S, c.S));
+    s_out[P] = s;
+    agot[P] = c.V / V[P];
+    iters[P] = it;
+    A_out[P] = c.A;
+    if (Sm > 0) {
+      double nn[3] = {c.S[0] / Sm, c.S[1] / Sm, c.S[2] / Sm};
+      for (int d = 0; d < 3; ++d) n_out[d * N + P] = nn[d];
+      /* d = n . (x_P - c_int), with x_P the origin of the local frame */
+      d_out[P] = -v_dot(nn, c.c);
+    }
+    status[P] = st;
+  }
+  if (!phi_in) free(phi);
+  return err;
+}
+
+/* ------------------------------------------------------------ mass transfer */
+/* mdot = (q_l + q_v)/(h_lv V_P), q_l = k_l (gl.n) A, q_v = -k_v (gv.n) A, only
+ * where A > 0 (Eq. mass_transfer, Eq. latent_source).  gl/gv NULL selects the
+ * one-sided fill from grad: the cell's own phase (liquid when alpha >= 1/2)
+ * takes grad, the other phase 0. */
+int orc_mass_transfer(int64_t N, const double *V, const double *alpha, const double *n, const double *A,
+                      const double *grad, const double *gl, const double *gv, double k_l, double k_v,
+                      double h_lv, double *mdot, double *Qdot) {
+  for (int64_t P = 0; P < N; ++P) {
+    if (!(A[P] > 0)) { mdot[P] = 0; Qdot[P] = 0; continue; }
+    double nn[3] = {n[P], n[N + P], n[2 * N + P]};
+    double L[3] = {0, 0, 0}, W[3] = {0, 0, 0};
+    if (gl && gv) {
+      for (int d = 0; d < 3; ++d) { L[d] = gl[d * N + P]; W[d] = gv[d * N + P]; }
+    } else if (alpha[P] >= 0.5) {
+      for (int d = 0; d < 3; ++d) L[d] = grad[d * N + P];
+    } else {
+      for (int d = 0; d < 3; ++d) W[d] = grad[d * N + P];
+    }
+    double ql = k_l * v_dot(L, nn) * A[P];
+    double qv = -k_v * v_dot(W, nn) * A[P];
+    mdot[P] = (ql + qv) / (h_lv * V[P]);
+    Qdot[P] = -mdot[P] * h_lv;
+  }
+  return 0;
+}

@@ -1,0 +1,93 @@
+"""The seeded workloads: mesh + alpha + T + boundary T + material constants.
+
+* ``hex_sphere``     16^3 hexahedra of the unit cube, vapour sphere r=0.3 at
+  the centre, alpha from 64^3 sub-points per cell, T rising linearly by 5 K
+  over 0.3 outside the sphere, k = 0.025 W/m/K and h_lv = 2.26e6 J/kg (the
+  paper's steam conductivity and latent heat, Table 1), T_sat = 373.15 K.
+* ``voronoi_bubble`` box-clipped jittered-BCC Voronoi mesh (2 n^3 seeds,
+  n = 46 gives 194,672 cells, ~14.5 faces per cell), one bubble r=0.25 at the
+  centre, T = T_sat + 1.25 K erf((rho - 0.25)/0.05) outside (the Scriven
+  superheat of Sec. 3.3), T_sat inside.
+* ``random_bubbles`` a mesh with many non-overlapping bubbles placed by random
+  sequential addition (radii U[2h, 12h], clearance 2h), T rising from each
+  bubble with its own slope U[1, 20] K per unit length.
+* ``pipe_film``      Voronoi cells of a pipe with a wavy liquid film on the wall.
+
+Temperatures are evaluated at the mean of a cell's vertices and boundary
+temperatures at the mean of a face's vertices (input placement only).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import fields
+from .meshes import Mesh, hex_mesh, voronoi_box_mesh, voronoi_pipe_mesh
+
+T_SAT = 373.15
+K_STEAM = 0.025
+H_LV = 2.26e6
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    alpha: np.ndarray
+    T: np.ndarray
+    T_bface: np.ndarray           # [NF], used on boundary faces only
+    T_sat: float = T_SAT
+    k_l: float = K_STEAM
+    k_v: float = K_STEAM
+    h_lv: float = H_LV
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_mixed(self) -> int:
+        a = self.alpha
+        return int(np.count_nonzero((a > 1e-8) & (a < 1.0 - 1e-8)))
+
+
+def hex_sphere(n: int = 16, r: float = 0.3, K: int = 64, dT: float = 5.0) -> Workload:
+    mesh = hex_mesh(n)
+    c = (0.5, 0.5, 0.5)
+    alpha = fields.sphere_alpha(mesh, np.array([[*c, r]]), K=K)
+    T = fields.radial_linear_T(mesh.cell_vertex_mean(), c, r, dT / r, T_SAT)
+    Tb = fields.radial_linear_T(mesh.face_vertex_mean(), c, r, dT / r, T_SAT)
+    return Workload(f"hex{n}^3 sphere r={r}", mesh, alpha, T, Tb, meta={"spheres": np.array([[*c, r]])})
+
+
+def voronoi_bubble(n: int = 46, seed: int = 2, r: float = 0.25, width: float = 0.05,
+                   dT: float = 1.25, K: int = 64) -> Workload:
+    mesh = voronoi_box_mesh(n, seed)
+    c = (0.5, 0.5, 0.5)
+    alpha = fields.sphere_alpha(mesh, np.array([[*c, r]]), K=K)
+    T = fields.radial_erf_T(mesh.cell_vertex_mean(), c, r, width, dT, T_SAT)
+    Tb = fields.radial_erf_T(mesh.face_vertex_mean(), c, r, width, dT, T_SAT)
+    return Workload(f"voronoi {mesh.n_cells} cells bubble r={r}", mesh, alpha, T, Tb,
+                    meta={"spheres": np.array([[*c, r]])})
+
+
+def random_bubbles(mesh: Mesh, seed: int, n_max: int = 1000, K: int = 16,
+                   r_lo_h: float = 2.0, r_hi_h: float = 12.0) -> Workload:
+    rng = np.random.default_rng(seed)
+    h = mesh.h
+    sph = fields.rsa_spheres(rng, n_max, r_lo_h * h, r_hi_h * h, 2.0 * h)
+    slopes = rng.uniform(1.0, 20.0, len(sph))
+    alpha = fields.sphere_alpha(mesh, sph, K=K)
+    T = fields.nearest_bubble_T(mesh.cell_vertex_mean(), sph, slopes, T_SAT)
+    Tb = fields.nearest_bubble_T(mesh.face_vertex_mean(), sph, slopes, T_SAT)
+    return Workload(f"{mesh.kind} {mesh.n_cells} cells, {len(sph)} bubbles", mesh, alpha, T, Tb,
+                    meta={"spheres": sph, "slopes": slopes, "n_bubbles": len(sph)})
+
+
+def pipe_film(n_radial: int = 40, seed: int = 4, R: float = 1.0, K: int = 16) -> Workload:
+    L = 52.0 / 9.5 * R
+    mesh = voronoi_pipe_mesh(n_radial, R, L, seed)
+    d0, amp, waves = 0.1 * R, 0.3, 5.0
+    alpha = fields.film_alpha(mesh, R, d0, amp, waves, L, K=K)
+    T = fields.film_T(mesh.cell_vertex_mean(), R, d0, amp, waves, L, 1.0, T_SAT)
+    Tb = fields.film_T(mesh.face_vertex_mean(), R, d0, amp, waves, L, 1.0, T_SAT)
+    return Workload(f"pipe {mesh.n_cells} cells film", mesh, alpha, T, Tb,
+                    meta={"R": R, "L": L, "d0": d0, "amp": amp, "waves": waves})

@@ -1,0 +1,408 @@
+"""Pins of the CPU oracle against closed forms, invariants and the paper.
+
+Each test fixes part of the oracle with something other than the oracle
+itself: analytic plane cuts of a cube and a tetrahedron, independent convex
+hull clipping, Monte Carlo counting, symmetry of the construction, exactness
+of least squares on linear data, and the one-dimensional relations of App. C.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import meshes, workloads
+from tests import polytools as pt
+
+
+def _linear_phi(mesh, g, c0=0.0):
+    return mesh.vert_xyz.T @ g + c0
+
+
+# ------------------------------------------------------------------ plane cuts
+def test_unit_cube_plane_cut_matches_closed_form():
+    """Vertex-linear field on the unit cube: the iso-cut is the plane, so the
+    liquid volume, the interface area, the normal and the centre distance have
+    closed forms (edge intersection, Eq. edge_intersection, is exact here)."""
+    mesh = meshes.hex_mesh(1)
+    om = oracle.OMesh(mesh)
+    geom = oracle.geometry(om)
+    assert geom.V[0] == pytest.approx(1.0, abs=1e-15)
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        m = rng.uniform(0.1, 1.0, 3) * rng.choice([-1, 1], 3)
+        phi = _linear_phi(mesh, m)
+        lo, hi = phi.min(), phi.max()
+        s = rng.uniform(lo, hi)
+        res = oracle.cut_cell(om, 0, geom.xc, phi, s)
+        # map to positive coefficients: x_i -> 1 - x_i for m_i < 0
+        mp = np.abs(m)
+        shift = np.sum(np.where(m < 0, -m, 0.0))    # m.x = mp.x' - shift
+        v_below = pt.below_unit_cube(mp, s + shift)
+        assert res["V"] == pytest.approx(1.0 - v_below, abs=1e-14)
+        assert res["A"] == pytest.approx(pt.below_unit_cube_area(mp, s + shift), rel=1e-12, abs=1e-14)
+        n = res["S"] / np.linalg.norm(res["S"])
+        np.testing.assert_allclose(n, m / np.linalg.norm(m), atol=1e-12)
+        # signed distance of the centroid to the plane, positive on the liquid side
+        d = -np.dot(n, res["c"])
+        assert d == pytest.approx((m @ geom.xc[:, 0] - s) / np.linalg.norm(m), abs=1e-13)
+
+
+def test_tetrahedron_cut_matches_simplex_formula():
+    """V_liq/V of a linear field on a tetrahedron equals 1 - sum_i (s-f_i)_+^3 /
+    prod_{j!=i}(f_j-f_i) in every case (one, two or three vertices liquid)."""
+    rng = np.random.default_rng(5)
+    for _ in range(60):
+        P = rng.normal(size=(4, 3))
+        mesh = pt.tet_mesh(P)
+        om = oracle.OMesh(mesh)
+        geom = oracle.geometry(om)
+        vt = abs(np.linalg.det(np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]]))) / 6.0
+        assert geom.V[0] == pytest.approx(vt, rel=1e-13)
+        g = rng.normal(size=3)
+        phi = _linear_phi(mesh, g)
+        s = rng.uniform(phi.min(), phi.max())
+        res = oracle.cut_cell(om, 0, geom.xc, phi, s)
+        assert res["V"] / vt == pytest.approx(1.0 - pt.tet_fraction_below(phi, s), abs=1e-12)
+        np.testing.assert_allclose(res["S"] / np.linalg.norm(res["S"]), g / np.linalg.norm(g), atol=1e-11)
+        assert res["nloops"] == 1
+
+
+def test_convex_hull_cut_matches_independent_clipping():
+    """Random convex polyhedra (triangulated hulls), linear field: volume and
+    cut area agree with convex-hull clipping done by scipy."""
+    rng = np.random.default_rng(3)
+    for _ in range(25):
+        pts = rng.normal(size=(rng.integers(8, 30), 3))
+        mesh = pt.hull_mesh(pts)
+        om = oracle.OMesh(mesh)
+        geom = oracle.geometry(om)
+        from scipy.spatial import ConvexHull
+        assert geom.V[0] == pytest.approx(ConvexHull(pts).volume, rel=1e-12)
+        g = rng.normal(size=3)
+        phi = _linear_phi(mesh, g)
+        s = rng.uniform(np.quantile(phi, 0.1), np.quantile(phi, 0.9))
+        res = oracle.cut_cell(om, 0, geom.xc, phi, s)
+        vol, area = pt.clip_hull_volume_area(mesh.vert_xyz.T, g, s)
+        assert res["V"] == pytest.approx(vol, rel=1e-11)
+        assert res["A"] == pytest.approx(area, rel=1e-11)
+
+
+def test_monte_carlo_volume_on_voronoi_cells():
+    """Counting 4e5 uniform points in a Voronoi cell (nearest-seed test) on the
+    liquid side of a plane agrees with the cut volume within 5 sigma."""
+    mesh = meshes.voronoi_box_mesh(5, seed=9)
+    om = oracle.OMesh(mesh)
+    geom = oracle.geometry(om)
+    rng = np.random.default_rng(1)
+    off, nb = mesh.face_neighbours()
+    for P in rng.choice(mesh.n_cells, 4, replace=False):
+        bb = mesh.cell_bbox()[P]
+        g = rng.normal(size=3)
+        phi = _linear_phi(mesh, g)
+        cell_phi = phi[mesh.face_vert[np.concatenate([np.arange(mesh.face_vert_off[f], mesh.face_vert_off[f + 1])
+                                                        for f in mesh.cell_face[mesh.cell_face_off[P]:mesh.cell_face_off[P + 1]]])]]
+        s = 0.5 * (cell_phi.min() + cell_phi.max())
+        nsamp = 400_000
+        X = rng.uniform(bb[:3], bb[3:], size=(nsamp, 3))
+        p = mesh.seeds[P]
+        inside = np.ones(nsamp, bool)
+        for q in nb[off[P]:off[P + 1]]:
+            qq = mesh.seeds[q]
+            inside &= (X @ (qq - p)) <= 0.5 * (qq @ qq - p @ p)
+        box_vol = np.prod(bb[3:] - bb[:3])
+        v_cell = inside.mean() * box_vol
+        liq = inside & (X @ g >= s)
+        frac = liq.mean()
+        v_mc = frac * box_vol
+        sigma = np.sqrt(frac * (1 - frac) / nsamp) * box_vol
+        res = oracle.cut_cell(om, P, geom.xc, phi, s)
+        assert abs(res["V"] - v_mc) < 5 * sigma + 1e-15
+        assert abs(geom.V[P] - v_cell) < 5 * np.sqrt(inside.mean() * (1 - inside.mean()) / nsamp) * box_vol
+
+
+# ---------------------------------------------------- general (non-linear) fields
+def _cell_vertex_ids(mesh, P):
+    fs = mesh.cell_face[mesh.cell_face_off[P]:mesh.cell_face_off[P + 1]]
+    return np.unique(np.concatenate([mesh.face_vert[mesh.face_vert_off[f]:mesh.face_vert_off[f + 1]] for f in fs]))
+
+
+def test_liquid_and_vapour_volumes_sum_to_cell_volume():
+    """For an arbitrary vertex field the iso-surface seen from the liquid side
+    (phi >= s) and from the vapour side (-phi >= -s) is the same surface, so
+    the two volumes add up to V_P."""
+    mesh = meshes.voronoi_box_mesh(5, seed=4)
+    om = oracle.OMesh(mesh)
+    geom = oracle.geometry(om)
+    rng = np.random.default_rng(2)
+    phi = rng.uniform(0, 1, mesh.n_verts)   # rough field: saddles, several loops
+    nloops_seen = set()
+    for P in range(mesh.n_cells):
+        ids = _cell_vertex_ids(mesh, P)
+        for s in rng.uniform(phi[ids].min(), phi[ids].max(), 3):
+            a = oracle.cut_cell(om, P, geom.xc, phi, s)
+            b = oracle.cut_cell(om, P, geom.xc, -phi, -s)
+            assert a["V"] + b["V"] == pytest.approx(geom.V[P], rel=1e-13)
+            assert a["A"] == pytest.approx(b["A"], rel=1e-12)
+            np.testing.assert_allclose(a["S"], -b["S"], atol=1e-14 * geom.V[P] ** (2 / 3))
+            nloops_seen.add(a["nloops"])
+    assert max(nloops_seen) >= 2   # the rough field exercises multi-loop cells
+
+
+def test_volume_is_monotone_in_isovalue():
+    """V_liq(s) does not increase with s (sampled at 400 isovalues per cell) for
+    a smooth inverse-distance vertex field."""
+    wl = workloads.voronoi_bubble(n=8, seed=3, r=0.3)
+    om = oracle.OMesh(wl.mesh)
+    geom = oracle.geometry(om)
+    phi = oracle.vertex_field(om, geom.xc, wl.alpha)
+    mixed = np.nonzero((wl.alpha > 1e-8) & (wl.alpha < 1 - 1e-8))[0]
+    for P in mixed[:20]:
+        ids = _cell_vertex_ids(wl.mesh, P)
+        ss = np.linspace(phi[ids].min(), phi[ids].max(), 400)
+        V = np.array([oracle.cut_cell(om, P, geom.xc, phi, s)["V"] for s in ss])
+        assert V[0] == pytest.approx(geom.V[P], rel=1e-13)
+        assert V[-1] == pytest.approx(0.0, abs=1e-15 * geom.V[P])
+        assert np.all(np.diff(V) <= 1e-14 * geom.V[P])
+
+
+# ---------------------------------------------------------------- reconstruction
+def test_alpha_recovered_on_every_mixed_cell(hex_sphere_wl, small_voronoi_wl):
+    for wl in (hex_sphere_wl, small_voronoi_wl):
+        om = oracle.OMesh(wl.mesh)
+        geom = oracle.geometry(om)
+        rec = oracle.reconstruct(om, wl.alpha, geom)
+        mixed = rec["status"] != oracle.NOT_MIXED
+        assert mixed.sum() == wl.n_mixed
+        ok = rec["status"] == oracle.OK
+        noroot = rec["status"] == oracle.NO_ROOT
+        assert np.all(ok | noroot | ~mixed)
+        assert noroot.sum() <= 0.02 * mixed.sum()
+        a = wl.alpha[ok]
+        err = np.abs(rec["alpha_got"][ok] - a)
+        # recovered to 1e-12 absolute; most cells stop on the relative tolerance
+        assert err.max() <= 1e-12
+        assert np.mean(err <= 1e-13 * np.minimum(a, 1 - a)) > 0.5
+        assert np.all(rec["A"][mixed] > 0)
+        assert np.all(np.abs(np.linalg.norm(rec["n"][:, mixed], axis=0) - 1) < 1e-14)
+        # no-root cells: the volume jumps across alpha at s*, and the side kept
+        # is the one nearer to alpha
+        phi = oracle.vertex_field(om, geom.xc, wl.alpha)
+        for P in np.nonzero(noroot)[0]:
+            s = rec["s"][P]
+            vm = oracle.cut_cell(om, P, geom.xc, phi, s - 1e-12)["V"] / geom.V[P]
+            vp = oracle.cut_cell(om, P, geom.xc, phi, s + 1e-12)["V"] / geom.V[P]
+            assert vm > wl.alpha[P] > vp
+            assert abs(rec["alpha_got"][P] - wl.alpha[P]) == pytest.approx(
+                min(abs(vm - wl.alpha[P]), abs(vp - wl.alpha[P])), abs=1e-9)
+        # normal points from vapour (inside the bubble) to liquid (outward)
+        c = wl.meta["spheres"][0, :3]
+        radial = geom.xc[:, mixed] - c[:, None]
+        assert np.mean(np.sum(radial * rec["n"][:, mixed], 0) > 0) > 0.97
+
+
+def test_total_interface_area_approximates_the_sphere(hex_sphere_wl):
+    rec = oracle.reconstruct(hex_sphere_wl.mesh, hex_sphere_wl.alpha)
+    assert rec["A"].sum() == pytest.approx(4 * np.pi * 0.3 ** 2, rel=0.01)
+
+
+def test_rigid_motion_invariance(small_voronoi_wl):
+    wl = small_voronoi_wl
+    rng = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    t = rng.normal(size=3)
+    m2 = meshes.Mesh(**{**wl.mesh.__dict__, "vert_xyz": Q @ wl.mesh.vert_xyz + t[:, None]})
+    a = oracle.reconstruct(wl.mesh, wl.alpha)
+    b = oracle.reconstruct(m2, wl.alpha)
+    mixed = (a["status"] == oracle.OK) & (b["status"] == oracle.OK)
+    np.testing.assert_allclose(b["A"][mixed], a["A"][mixed], rtol=1e-9)
+    np.testing.assert_allclose(b["d"][mixed], a["d"][mixed], atol=1e-9 * wl.mesh.h)
+    np.testing.assert_allclose(b["alpha_got"][mixed], a["alpha_got"][mixed], atol=1e-12)
+    np.testing.assert_allclose(b["n"][:, mixed], Q @ a["n"][:, mixed], atol=1e-9)
+
+
+def test_phase_swap_symmetry(small_voronoi_wl):
+    """alpha -> 1-alpha: s -> 1-s, n -> -n, same A, d -> -d."""
+    wl = small_voronoi_wl
+    a = oracle.reconstruct(wl.mesh, wl.alpha)
+    b = oracle.reconstruct(wl.mesh, 1.0 - wl.alpha)
+    m = (a["status"] == oracle.OK) & (b["status"] == oracle.OK)
+    np.testing.assert_allclose(b["A"][m], a["A"][m], rtol=1e-9)
+    np.testing.assert_allclose(b["n"][:, m], -a["n"][:, m], atol=1e-9)
+    np.testing.assert_allclose(b["d"][m], -a["d"][m], atol=1e-9 * wl.mesh.h)
+    np.testing.assert_allclose(b["s"][m], 1.0 - a["s"][m], atol=1e-9)
+
+
+def test_fixed_isovalue_mode_cuts_at_one_half(hex_sphere_wl):
+    wl = hex_sphere_wl
+    rec = oracle.reconstruct(wl.mesh, wl.alpha, fixed_iso=True, iso=0.5)
+    m = rec["status"] != oracle.NOT_MIXED
+    assert np.all(rec["s"][m] == 0.5)
+    assert np.all(rec["iters"][m] == 1)
+
+
+def test_degenerate_vertex_field_falls_back_to_linear_alpha():
+    """A uniform alpha gives a constant vertex field: the cell is flagged and,
+    with zero alpha gradient, no interface is placed."""
+    mesh = meshes.hex_mesh(4)
+    alpha = np.full(mesh.n_cells, 0.4)
+    rec = oracle.reconstruct(mesh, alpha)
+    assert np.all(rec["status"] == oracle.DEGENERATE)
+    assert np.all(rec["A"] == 0)
+    # a constant field on the vertices but a linear alpha across the cells
+    x = oracle.geometry(mesh).xc
+    alpha = 0.5 + 0.1 * (x[0] - 0.5)
+    phi = np.full(mesh.n_verts, 0.5)
+    rec = oracle.reconstruct(mesh, alpha, phi=phi)
+    assert np.all(rec["status"] == oracle.DEGENERATE)
+    ok = rec["A"] > 0
+    assert ok.all()
+    np.testing.assert_allclose(rec["n"][0], 1.0, atol=1e-12)
+    np.testing.assert_allclose(rec["A"], mesh.h ** 2, rtol=1e-12)
+
+
+def test_bad_and_pure_cells_are_not_reconstructed():
+    mesh = meshes.hex_mesh(3)
+    alpha = np.full(mesh.n_cells, 1.0)
+    alpha[0] = np.nan
+    alpha[1] = -0.2
+    alpha[2] = 0.0
+    alpha[3] = 1e-9
+    rec = oracle.reconstruct(mesh, alpha)
+    assert list(rec["status"][:4]) == [oracle.BAD_INPUT, oracle.BAD_INPUT, oracle.NOT_MIXED, oracle.NOT_MIXED]
+    assert np.all(rec["status"][4:] == oracle.NOT_MIXED)
+    assert np.all(np.isnan(rec["s"]))
+
+
+def test_narrowed_bracket_gives_the_same_result(small_voronoi_wl):
+    """A valid narrowed bracket and a wrong one both end inside the stopping
+    window; the wrong one is flagged as a fallback."""
+    wl = small_voronoi_wl
+    a = oracle.reconstruct(wl.mesh, wl.alpha)
+    m = a["status"] == oracle.OK
+    s = np.where(m, a["s"], np.nan)
+    good = oracle.reconstruct(wl.mesh, wl.alpha, hint_lo=s - 1e-3, hint_hi=s + 1e-3)
+    bad = oracle.reconstruct(wl.mesh, wl.alpha, hint_lo=s + 1e-2, hint_hi=s + 2e-2)
+    for r in (good, bad):
+        np.testing.assert_allclose(r["alpha_got"][m], a["alpha_got"][m], atol=1e-12)
+        np.testing.assert_allclose(r["A"][m], a["A"][m], rtol=1e-8, atol=1e-9 * wl.mesh.h ** 2)
+    assert np.all(good["status"][m] == oracle.OK)
+    assert np.mean(good["iters"][m]) < np.mean(a["iters"][m])
+    assert np.all(np.isin(bad["status"][m], [oracle.LEARNED_FALLBACK, oracle.OK]))
+    assert np.mean(bad["status"][m] == oracle.LEARNED_FALLBACK) > 0.9
+
+
+# ------------------------------------------------------------- least squares
+def test_least_squares_exact_for_linear_field(small_voronoi_wl):
+    wl = small_voronoi_wl
+    geom = oracle.geometry(wl.mesh)
+    g = np.array([0.3, -1.7, 2.2])
+    T = 5.0 + g @ geom.xc
+    Tb = 5.0 + g @ geom.xf
+    grad, st = oracle.grad(wl.mesh, geom, T, Tb, 0.0, np.ones(wl.mesh.n_cells), modified=True)
+    assert np.all(st == oracle.OK)
+    np.testing.assert_allclose(grad, np.broadcast_to(g[:, None], grad.shape), rtol=0, atol=1e-11)
+
+
+def test_modified_stencil_exact_for_planar_interface():
+    """alpha = 1/2 + kappa dist(x), T = T_sat + G dist(x) for a plane: the
+    alpha-interpolated crossing points lie on the plane where T = T_sat, so the
+    interface-modified gradient is exactly G n.  The printed mirror weight of
+    Eq. front_interpolation does not have this property."""
+    wl = workloads.voronoi_bubble(n=8, seed=5, r=0.3)
+    mesh = wl.mesh
+    geom = oracle.geometry(mesh)
+    nrm = np.array([1.0, 2.0, -0.5])
+    nrm /= np.linalg.norm(nrm)
+    dist = nrm @ (geom.xc - 0.5)
+    alpha = 0.5 + 0.6 * dist           # stays inside (0, 1) on the unit box
+    assert alpha.min() > 0 and alpha.max() < 1
+    T_sat, G = 373.15, 40.0
+    T = T_sat + G * dist
+    Tb = T_sat + G * (nrm @ (geom.xf - 0.5))
+    grad, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True)
+    np.testing.assert_allclose(grad, np.broadcast_to((G * nrm)[:, None], grad.shape), atol=1e-9)
+    band = oracle.band_mask(mesh, alpha)
+    printed, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True, printed=True)
+    err = np.linalg.norm(printed - (G * nrm)[:, None], axis=0)
+    assert err[band & (np.abs(alpha - 0.5) > 0.05)].max() > 1.0
+
+
+def _one_d_setup(theta_frac, d_over_h, n=8):
+    """Hex mesh, interface normal to x between two cell columns; returns
+    (gradient from the oracle, closed form Eq. g_fm, std ratio)."""
+    mesh = meshes.hex_mesh(n)
+    geom = oracle.geometry(mesh)
+    h = mesh.h
+    x = geom.xc[0]
+    i_iface = n // 2                       # cells with index >= i_iface are liquid
+    xP = (i_iface + 0.5) * h               # first liquid cell centre
+    x_int = xP - d_over_h * h              # interface between P and its vapour neighbour
+    # alpha linear in x across P and its vapour neighbour Q so that the
+    # alpha-interpolated crossing sits at x_int; 0 / 1 further away
+    kappa = 0.4 / h
+    alpha = np.clip(0.5 + kappa * (x - x_int), 0.0, 1.0)
+    T_sat, dT = 373.15, 2.0
+    T_far = T_sat + dT
+    T = np.where(x > x_int, T_sat + dT * np.clip((x - x_int) / (h * (1 + d_over_h)), 0, 1), T_sat)
+    theta = theta_frac * dT
+    T = np.where(np.isclose(x, xP), T_sat + theta, T)
+    T = np.where(np.isclose(x, xP + h), T_far, T)
+    Tb = np.full(mesh.n_faces, T_sat)
+    grad, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True)
+    P = np.nonzero(np.isclose(x, xP) & np.isclose(geom.xc[1], (n // 2 + 0.5) * h) &
+                   np.isclose(geom.xc[2], (n // 2 + 0.5) * h))[0][0]
+    d = d_over_h * h
+    g_fm = ((T[P] - T_sat) * d + (T_far - T[P]) * h) / (d * d + h * h)   # Eq. g_fm
+    g_std = (T_far - T_sat) / (2 * h)                                     # Eq. g_std
+    return grad[:, P], g_fm, g_std
+
+
+@pytest.mark.parametrize("d_over_h", [0.3, 0.5, 0.7])
+@pytest.mark.parametrize("theta_frac", [0.0, 0.2])
+def test_one_dimensional_modified_gradient_matches_app_c(d_over_h, theta_frac):
+    g, g_fm, _ = _one_d_setup(theta_frac, d_over_h)
+    assert g[0] == pytest.approx(g_fm, rel=1e-12)
+    assert abs(g[1]) < 1e-9 and abs(g[2]) < 1e-9
+
+
+def test_boost_ratio_reproduces_printed_values():
+    rows = np.loadtxt(__file__.replace("test_oracle_pins.py", "golden/appc_boost_ratio.txt"))
+    for d_over_h, printed in rows:
+        if d_over_h == 0.0:
+            continue
+        g, _, g_std = _one_d_setup(0.0, d_over_h)
+        assert round(g[0] / g_std, 2) == pytest.approx(printed, abs=0.011)
+    # d -> 0: the one-sided difference over h, twice the central one
+    g, _, g_std = _one_d_setup(0.0, 1e-6)
+    assert g[0] / g_std == pytest.approx(2.0, rel=1e-5)
+
+
+# ------------------------------------------------------------------ mass rate
+def test_mass_transfer_identity_and_sign(hex_sphere_wl):
+    wl = hex_sphere_wl
+    r = oracle.run_path(wl)
+    rec, geom = r["rec"], r["geom"]
+    A, n, g = rec["A"], rec["n"], r["grad"]
+    has = A > 0
+    assert np.all(r["mdot"][~has] == 0) and np.all(r["Qdot"][~has] == 0)
+    liq = wl.alpha >= 0.5
+    expect = np.where(liq, wl.k_l * np.sum(g * n, 0) * A, -wl.k_v * np.sum(g * n, 0) * A) / (wl.h_lv * geom.V)
+    np.testing.assert_allclose(r["mdot"][has], expect[has], rtol=1e-13)
+    np.testing.assert_allclose(r["Qdot"], -r["mdot"] * wl.h_lv, rtol=1e-15)
+    # superheated liquid around a vapour bubble: evaporation in liquid cells
+    assert np.all(r["mdot"][has & liq] > 0)
+
+
+def test_two_sided_gradients_are_used_when_given(hex_sphere_wl):
+    wl = hex_sphere_wl
+    r = oracle.run_path(wl)
+    rec, geom = r["rec"], r["geom"]
+    N = wl.mesh.n_cells
+    gl = np.tile([[1.0], [0.0], [0.0]], (1, N))
+    gv = np.tile([[0.0], [0.0], [-2.0]], (1, N))
+    mdot, _ = oracle.mass_transfer(geom, wl.alpha, rec["n"], rec["A"], r["grad"], 0.5, 0.25, 10.0, gl=gl, gv=gv)
+    has = rec["A"] > 0
+    ql = 0.5 * rec["n"][0] * rec["A"]
+    qv = -0.25 * (-2.0 * rec["n"][2]) * rec["A"]
+    np.testing.assert_allclose(mdot[has], ((ql + qv) / (10.0 * geom.V))[has], rtol=1e-13)
