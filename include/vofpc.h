@@ -1,0 +1,247 @@
+/* vofpc: interface hot path of a sharp-interface phase-change VOF method on
+ * unstructured polyhedral meshes, for AMD Instinct MI355X (gfx950).
+ *
+ * The path, per time step (the method of Kren, Nicheno and Sato, 2026):
+ *   1. compaction: the mixed cells (eps < alpha < 1-eps) and the gradient
+ *      band (mixed cells and cells owning a face crossed by alpha = 1/2);
+ *   2. reconstruction of every mixed cell: alpha is carried to the polyhedron
+ *      vertices; the cell is cut by the iso-polygons of that vertex field
+ *      (edge intersections by linear interpolation, Eq. edge_intersection,
+ *      assembled through the faces into closed polygons, Sec. 2.1); the
+ *      isovalue is bisected until the liquid volume equals alpha V_P; the
+ *      result is the interface normal n (vapour -> liquid), area A_int and
+ *      centre-to-interface distance d;
+ *   3. the interface-modified least-squares temperature gradient (Sec. 2.4.4,
+ *      Eq. front_interpolation, App. B): across a face crossed by the
+ *      interface the neighbour is replaced by the alpha-interpolated crossing
+ *      point held at T_sat;
+ *   4. the mass transfer rate mdot = (q_l + q_v)/(h_lv V_P) with
+ *      q_l = k_l (grad T_l . n) A_int, q_v = -k_v (grad T_v . n) A_int
+ *      (Eq. mass_transfer) and the latent source Qdot = -mdot h_lv
+ *      (Eq. latent_source), only where A_int > 0.
+ *
+ * Conventions of the whole interface:
+ *   - Every call returns a vofpc_status (0 = success, negative = error) and
+ *     never throws across the boundary; vofpc_last_error() returns a
+ *     thread-local message for the last failing call of the calling thread.
+ *   - Compute calls are asynchronous on the context's HIP stream; their
+ *     device outputs are valid once that stream has been synchronised.
+ *   - "device" pointers are HIP device allocations of the context's device
+ *     (for example torch tensor data pointers); "host" pointers are ordinary
+ *     host memory.  The caller owns every field, list and output buffer; the
+ *     library owns uploaded meshes, graphs and its own small scratch.
+ *   - Floating point is FP64 throughout.  Vector fields are structure of
+ *     arrays: a [3][n] array holds all x, then all y, then all z.
+ *   - Per-cell numerical outcomes are reported as VOFPC_CELL_* codes in the
+ *     status outputs, not as call errors.
+ */
+#ifndef VOFPC_H
+#define VOFPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status codes */
+typedef int vofpc_status;
+#define VOFPC_OK 0
+#define VOFPC_E_INVALID_ARG (-1) /* null or inconsistent argument */
+#define VOFPC_E_HIP (-2)         /* a HIP runtime call failed */
+#define VOFPC_E_OOM (-3)         /* device or host allocation failed */
+#define VOFPC_E_MESH (-4)        /* mesh topology or geometry is invalid */
+#define VOFPC_E_STATE (-5)       /* object used with the wrong context/device */
+
+/* per-cell outcome codes (status outputs of reconstruct and grad_T) */
+#define VOFPC_CELL_OK 0
+#define VOFPC_CELL_NOT_MIXED 1        /* alpha <= eps or >= 1-eps: no interface */
+#define VOFPC_CELL_LEARNED_FALLBACK 2 /* the narrowed bracket failed its check */
+#define VOFPC_CELL_DEGENERATE 3       /* constant vertex field: linear alpha used */
+#define VOFPC_CELL_MAX_ITER 4         /* bisection stopped at max_iter */
+#define VOFPC_CELL_G_SINGULAR 5       /* least-squares matrix singular: grad = 0 */
+#define VOFPC_CELL_BAD_INPUT 6        /* alpha NaN or outside [0,1] */
+#define VOFPC_CELL_NO_ROOT 7          /* liquid volume jumps across alpha V_P */
+
+typedef struct vofpc_ctx_s *vofpc_ctx;
+typedef struct vofpc_mesh_s *vofpc_mesh;
+typedef struct vofpc_graph_s *vofpc_graph;
+
+/* Thread-local message of the last failed call on this thread ("" if none).
+ * The pointer stays valid until the next vofpc call on the same thread. */
+const char *vofpc_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int vofpc_version(void);
+
+/* ------------------------------------------------------------------ context */
+/* Create a context on HIP device `device`, issuing work on `hip_stream` (a
+ * hipStream_t; NULL = the device's null stream).  The stream must stay valid
+ * while the context uses it.  *out receives the handle. */
+vofpc_status vofpc_ctx_create(int device, void *hip_stream, vofpc_ctx *out);
+/* Change the stream later work is issued on. */
+vofpc_status vofpc_ctx_set_stream(vofpc_ctx ctx, void *hip_stream);
+/* Destroy a context (after its meshes and graphs).  NULL is accepted. */
+vofpc_status vofpc_ctx_destroy(vofpc_ctx ctx);
+
+/* --------------------------------------------------------------------- mesh */
+/* A polyhedral mesh in CSR form (finite-volume, cell-centred storage).  All
+ * pointers are HOST pointers; the arrays are copied during the upload.
+ *   cell_face_off[n_cells+1], cell_face[cell_face_off[n_cells]]: faces of
+ *       each cell (each interior face appears in both of its cells);
+ *   face_vert_off[n_faces+1], face_vert[...]: vertex loop of each face,
+ *       counter-clockwise seen from outside its owner (right-hand normal
+ *       points from owner to neighbour);
+ *   face_owner[n_faces], face_neigh[n_faces] (-1 on the boundary);
+ *   face_bc[n_faces]: 0 interior, 1 boundary with a given value (acts as a
+ *       least-squares neighbour at the face centroid), 2 symmetry (skipped);
+ *   vert_xyz[3][n_verts]: vertex coordinates.
+ * Cells must be closed, convex polyhedra with planar faces; at most 255
+ * vertices and 255 faces per cell. */
+typedef struct {
+  int64_t n_cells, n_faces, n_verts;
+  const int64_t *cell_face_off;
+  const int32_t *cell_face;
+  const int64_t *face_vert_off;
+  const int32_t *face_vert;
+  const int32_t *face_owner;
+  const int32_t *face_neigh;
+  const int8_t *face_bc;
+  const double *vert_xyz;
+} vofpc_mesh_desc;
+
+/* Validate and upload a mesh, then compute its geometry on the device: cell
+ * volumes V and centroids x_P, face area vectors S_f and area centroids x_f,
+ * the stored inverse least-squares matrix of every cell (six components of
+ * the symmetric inverse, App. B) and the inverse-distance weights that carry
+ * cell values to vertices.  Synchronises the context stream.  Returns
+ * VOFPC_E_MESH for inconsistent topology, open or inverted cells. */
+vofpc_status vofpc_mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *desc, vofpc_mesh *out);
+/* Free a mesh and its device memory.  NULL is accepted. */
+vofpc_status vofpc_mesh_free(vofpc_mesh mesh);
+/* info[0..7] = n_cells, n_faces, n_verts, max faces per cell, max vertices
+ * per cell, max vertices per face, max edges per cell, device bytes held. */
+vofpc_status vofpc_mesh_info(vofpc_mesh mesh, int64_t info[8]);
+/* Copy the computed geometry into caller DEVICE buffers (any may be NULL):
+ * V[n_cells], xc[3][n_cells], Sf[3][n_faces], xf[3][n_faces]. */
+vofpc_status vofpc_mesh_geometry(vofpc_mesh mesh, double *V, double *xc, double *Sf, double *xf);
+
+/* ------------------------------------------------------------- compaction */
+/* Mixed-cell list M (cells with eps_mixed < alpha < 1-eps_mixed, ascending)
+ * and band list B (cells that are mixed or own a face with
+ * (alpha_P - 1/2)(alpha_Q - 1/2) < 0, ascending).  alpha: DEVICE [n_cells].
+ * mixed_idx and band_idx: DEVICE int32 [n_cells] (capacity n_cells);
+ * counts: DEVICE int32 [2] receives |M| and |B|.  No host readback. */
+vofpc_status vofpc_compact(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, double eps_mixed,
+                           int32_t *mixed_idx, int32_t *band_idx, int32_t *counts);
+
+/* --------------------------------------------------------- reconstruction */
+#define VOFPC_BRACKET_PLAIN 0   /* bisect on [phi_min, phi_max] of the cell */
+#define VOFPC_BRACKET_HINT 1    /* start from hint_lo/hint_hi, verified */
+#define VOFPC_VERTEX_IDW 0      /* vertex value: inverse-distance cell average */
+#define VOFPC_VERTEX_MEAN 1     /* vertex value: plain average of the cells */
+
+typedef struct {
+  double eps_mixed;   /* mixed when eps < alpha < 1-eps (default 1e-8) */
+  double tol_rel;     /* stop when |V/V_P - alpha| <= tol_rel min(alpha,1-alpha) (1e-13) */
+  int32_t max_iter;   /* bisection evaluations per cell (100) */
+  int32_t vertex_mode;/* VOFPC_VERTEX_* */
+  int32_t fixed_iso;  /* nonzero: no root-find, cut at `iso` (paper's isoap mode) */
+  int32_t bracket;    /* VOFPC_BRACKET_* */
+  double iso;         /* isovalue for fixed_iso (0.5) */
+  const double *phi_vertex; /* optional DEVICE [n_verts] vertex field override */
+} vofpc_recon_opts;
+
+/* Fill *opts with the defaults above. */
+vofpc_status vofpc_recon_opts_default(vofpc_recon_opts *opts);
+
+/* Interface record over the mixed list: entry k describes cell mixed_idx[k]
+ * (k < counts[0]).  All pointers are DEVICE arrays of `cap` entries (n is
+ * [3][cap]); cap must be >= the number of mixed cells (n_cells is always
+ * enough).  Entries k >= counts[0] are left untouched. */
+typedef struct {
+  double *s;          /* isovalue found (NaN when no interface) */
+  double *n;          /* [3][cap] unit normal, vapour -> liquid (0 when none) */
+  double *A;          /* interface area A_int (0 when none) */
+  double *d;          /* n . (x_P - c_int), positive when x_P is in the liquid */
+  double *alpha_got;  /* V_liq(s)/V_P */
+  int32_t *status;    /* VOFPC_CELL_* */
+  int32_t *iters;     /* volume evaluations spent */
+  int64_t cap;
+} vofpc_interface;
+
+/* Reconstruct the interface in every listed mixed cell.  alpha: DEVICE
+ * [n_cells]; mixed_idx/counts from vofpc_compact.  hint_lo/hint_hi: DEVICE
+ * [cap] narrowed brackets per mixed entry, read only when opts->bracket is
+ * VOFPC_BRACKET_HINT (NaN entries use the plain bracket).  A narrowed bracket
+ * is checked with two volume evaluations; if the root is outside it the
+ * bisection continues on the remaining part of the plain bracket and the cell
+ * is flagged VOFPC_CELL_LEARNED_FALLBACK, so the result stays in the same
+ * stopping window either way. */
+vofpc_status vofpc_reconstruct(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed_idx,
+                               const int32_t *counts, const vofpc_recon_opts *opts, const double *hint_lo,
+                               const double *hint_hi, const vofpc_interface *out);
+
+/* ----------------------------------------------------------------- gradient */
+#define VOFPC_SCOPE_BAND 0  /* write grad at band cells only (others untouched) */
+#define VOFPC_SCOPE_ALL 1   /* write grad at every cell */
+#define VOFPC_GRAD_MODIFIED 0 /* interface-modified stencil (Sec. 2.4.4) */
+#define VOFPC_GRAD_STANDARD 1 /* plain least squares, no modification */
+#define VOFPC_GRAD_PRINTED 2  /* modified, with the printed mirror weight |a_Q-1/2|/|a_P-a_Q| */
+
+/* Interface-modified least-squares gradient of T (App. B with Sec. 2.4.4).
+ * T: DEVICE [n_cells]; T_bface: DEVICE [n_faces] (values used on faces with
+ * face_bc == 1); alpha: DEVICE [n_cells]; band_idx/counts from
+ * vofpc_compact (ignored for VOFPC_SCOPE_ALL).  Band cells build their
+ * least-squares matrix on the fly; other cells use the stored inverse.
+ * grad: DEVICE [3][n_cells]; status: optional DEVICE int32 [n_cells]
+ * (VOFPC_CELL_OK or VOFPC_CELL_G_SINGULAR, written where grad is written). */
+vofpc_status vofpc_grad_T(vofpc_ctx ctx, vofpc_mesh mesh, const double *T, const double *T_bface, double T_sat,
+                          const double *alpha, const int32_t *band_idx, const int32_t *counts, int32_t scope,
+                          int32_t variant, double *grad, int32_t *status);
+
+/* ------------------------------------------------------------ mass transfer */
+/* mdot and Qdot for every mixed entry k (Eq. mass_transfer, Eq. latent_source):
+ * zero where A_int = 0.  gradT: DEVICE [3][n_cells].  gradT_l/gradT_v:
+ * optional DEVICE [3][n_cells] phase gradients; when both are NULL the cell's
+ * own phase (liquid when alpha >= 1/2) takes gradT and the other phase 0.
+ * mdot/Qdot: DEVICE [cap] over the mixed list.  mdot_cells/Qdot_cells:
+ * optional DEVICE [n_cells] dense fields, zero-filled then scattered. */
+vofpc_status vofpc_mass_transfer(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed_idx,
+                                 const int32_t *counts, const vofpc_interface *itf, const double *gradT,
+                                 const double *gradT_l, const double *gradT_v, double k_l, double k_v,
+                                 double h_lv, double *mdot, double *Qdot, double *mdot_cells,
+                                 double *Qdot_cells);
+
+/* ------------------------------------------------------------- whole step */
+/* Every buffer of one step: compaction, reconstruction, band gradient and
+ * mass transfer, with the meaning given above.  All pointers DEVICE. */
+typedef struct {
+  const double *alpha, *T, *T_bface;
+  double T_sat, k_l, k_v, h_lv;
+  vofpc_recon_opts opts;
+  const double *hint_lo, *hint_hi; /* with opts.bracket == VOFPC_BRACKET_HINT */
+  int32_t *mixed_idx, *band_idx, *counts;
+  vofpc_interface itf;
+  double *gradT;          /* [3][n_cells], written on the band */
+  int32_t *grad_status;   /* optional [n_cells] */
+  double *mdot, *Qdot;    /* [cap] over the mixed list */
+} vofpc_step_args;
+
+/* Issue one step on the context stream. */
+vofpc_status vofpc_step(vofpc_ctx ctx, vofpc_mesh mesh, const vofpc_step_args *args);
+
+/* Capture one step (with the buffers of *args) into a HIP graph on the
+ * context stream; replaying it re-runs the step on whatever the buffers hold
+ * at replay time.  The mixed and band counts stay on the device, so the
+ * graph needs no host readback. */
+vofpc_status vofpc_graph_create(vofpc_ctx ctx, vofpc_mesh mesh, const vofpc_step_args *args, vofpc_graph *out);
+/* Launch a captured step on the context stream. */
+vofpc_status vofpc_graph_launch(vofpc_graph g);
+/* Destroy a captured step.  NULL is accepted. */
+vofpc_status vofpc_graph_destroy(vofpc_graph g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VOFPC_H */

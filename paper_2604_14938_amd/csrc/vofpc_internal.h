@@ -1,0 +1,115 @@
+// Internal declarations shared by the vofpc translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/vofpc.h"
+
+namespace vofpc {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+void clear_error();
+
+#define VOFPC_HIP(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ::vofpc::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return VOFPC_E_HIP;                                                            \
+    }                                                                                \
+  } while (0)
+
+#define VOFPC_REQUIRE(cond, code, msg)                                               \
+  do {                                                                               \
+    if (!(cond)) {                                                                   \
+      ::vofpc::set_error(msg);                                                       \
+      return code;                                                                   \
+    }                                                                                \
+  } while (0)
+
+// ------------------------------------------------------------- device mesh
+// Everything a kernel needs about a mesh, as raw device pointers.
+struct DevMesh {
+  int64_t n_cells, n_faces, n_verts;
+  // topology (as uploaded)
+  const int64_t *cell_face_off;
+  const int32_t *cell_face;
+  const int64_t *face_vert_off;
+  const int32_t *face_vert;
+  const int32_t *face_owner;
+  const int32_t *face_neigh;
+  const int8_t *face_bc;
+  const double *xyz;  // [3][n_verts]
+  // per cell-face slot (same indexing as cell_face): neighbour across the
+  // face, or -1 (boundary with value) / -2 (symmetry); loop offset and size
+  // of the face inside the cell's packed loops
+  const int32_t *cf_nbr;
+  const uint16_t *cf_loff;
+  const uint8_t *cf_lsz;
+  // packed cell-local polyhedra: distinct vertices (global ids) and the
+  // outward face loops as local vertex ids, faces in cell_face order
+  const int64_t *cv_off;
+  const int32_t *cv_gid;
+  const int64_t *cl_off;
+  const uint8_t *cl_lv;
+  // vertex -> cell incidence with normalised inverse-distance weights
+  const int64_t *vc_off;
+  const int32_t *vc_cell;
+  const double *vc_w;
+  const double *vc_wmean;  // 1/count per incidence
+  // geometry
+  const double *V;     // [n_cells]
+  const double *xc;    // [3][n_cells]
+  const double *Sf;    // [3][n_faces]
+  const double *xf;    // [3][n_faces]
+  const double *ginv;  // [6][n_cells] xx yy zz xy xz yz of the inverse
+};
+
+}  // namespace vofpc
+
+struct vofpc_ctx_s {
+  int device;
+  hipStream_t stream;
+  int n_cu;
+};
+
+struct vofpc_mesh_s {
+  vofpc_ctx ctx;
+  vofpc::DevMesh d;
+  int64_t max_nf, max_nv, max_fv, max_ne, max_loop;
+  int64_t bytes;
+  // scratch for compaction (owned by the mesh; calls on one mesh must not
+  // overlap in time)
+  uint8_t *flags;
+  int32_t *blk_cnt;   // [2][n_blocks]
+  int32_t *blk_off;   // [2][n_blocks]
+  int64_t n_blk;
+  void *alloc[40];
+  int n_alloc;
+};
+
+struct vofpc_graph_s {
+  vofpc_ctx ctx;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace vofpc {
+// launchers (return VOFPC_OK or an error code with the message set)
+vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, double eps, int32_t *mixed,
+                            int32_t *band, int32_t *counts);
+vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, const int32_t *mixed,
+                                const int32_t *counts, const vofpc_recon_opts *o, const double *hlo,
+                                const double *hhi, const vofpc_interface *out);
+vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh m, const double *T, const double *Tb, double T_sat,
+                         const double *alpha, const int32_t *band, const int32_t *counts, int32_t scope,
+                         int32_t variant, double *grad, int32_t *status);
+vofpc_status launch_mass_transfer(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, const int32_t *mixed,
+                                  const int32_t *counts, const vofpc_interface *itf, const double *gradT,
+                                  const double *gl, const double *gv, double k_l, double k_v, double h_lv,
+                                  double *mdot, double *Qdot, double *mdot_c, double *Qdot_c);
+}  // namespace vofpc

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Every test runs the library on seeded synthetic workloads and compares with
+the oracle element by element (lists and status codes exactly; floating point
+to the tolerances in tests/parity.py).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import meshes, workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_14938_amd import vofpc
+    return vofpc
+
+
+@pytest.fixture(scope="module")
+def runner(V):
+    from paper_2604_14938_amd import runner as R
+    return R
+
+
+_WL = {}
+
+
+def _wl(name):
+    if name not in _WL:
+        if name == "hex16":
+            _WL[name] = workloads.hex_sphere()
+        elif name == "vor12":
+            _WL[name] = workloads.voronoi_bubble(n=12, seed=7, r=0.3)
+        elif name == "vor46":
+            _WL[name] = workloads.voronoi_bubble()
+        elif name == "hex_small_bubbles":
+            _WL[name] = workloads.random_bubbles(meshes.hex_mesh(24), seed=31, n_max=40, K=16)
+        elif name == "vor_small_bubbles":
+            _WL[name] = workloads.random_bubbles(meshes.voronoi_box_mesh(14, seed=32), seed=33, n_max=40, K=16)
+    return _WL[name]
+
+
+@pytest.mark.parametrize("name", ["hex16", "vor12", "hex_small_bubbles", "vor_small_bubbles", "vor46"])
+def test_step_matches_oracle(runner, name):
+    wl = _wl(name)
+    _say(f"step parity {name}: {wl.mesh.n_cells} cells, {wl.n_mixed} mixed")
+    run = runner.PathRun(wl)
+    run.step()
+    g = run.results()
+    ref = parity.oracle_path(wl)
+    parity.check_lists(wl, g)
+    # geometry
+    import torch
+    Vd, xc, Sf, xf = (t.cpu().numpy() for t in run.mesh.geometry())
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(Vd, ref["geom"].V, rtol=1e-12)
+    np.testing.assert_allclose(xc, ref["geom"].xc, atol=1e-12 * wl.mesh.h, rtol=0)
+    np.testing.assert_allclose(Sf, ref["geom"].Sf, atol=1e-13 * wl.mesh.h ** 2, rtol=1e-12)
+    rep = {}
+    parity.check_interface(wl, g, ref["rec"], report=rep)
+    band = g["band_idx"]
+    parity.check_grad(wl, g["gradT"], ref["grad"], band)
+    np.testing.assert_array_equal(g["grad_status"][band], ref["grad_status"][band])
+    parity.check_mdot(g["mdot"], ref["mdot"][g["mixed_idx"]])
+    np.testing.assert_allclose(g["Qdot"], -g["mdot"] * wl.h_lv, rtol=1e-15)
+    _say(f"{name} ok: {rep}; mean iters {g['iters'].mean():.1f}")
+    run.close()
+
+
+def test_graph_replay_matches_eager(runner):
+    wl = _wl("vor12")
+    _say("graph replay vor12")
+    import torch
+    run = runner.PathRun(wl)
+    run.step()
+    eager = run.results()
+    gr = run.capture()
+    for rep in range(3):
+        # clobber the outputs with eager work between replays
+        run.buf.itf.A.fill_(-1.0)
+        run.buf.mdot.fill_(7.0)
+        run.buf.counts.zero_()
+        torch.cuda.synchronize()
+        gr.launch()
+        got = run.results()
+        for k in ("mixed_idx", "band_idx", "alpha_got", "A", "n", "d", "status", "iters", "mdot"):
+            np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep}: {k}")
+        np.testing.assert_array_equal(got["gradT"][:, got["band_idx"]], eager["gradT"][:, eager["band_idx"]])
+    run.close()
+
+
+def test_replays_are_bitwise_deterministic(runner):
+    wl = _wl("vor12")
+    _say("determinism vor12")
+    run = runner.PathRun(wl)
+    outs = []
+    for _ in range(3):
+        run.step()
+        outs.append(run.results())
+    for k in ("alpha_got", "A", "n", "d", "s", "mdot"):
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
+        np.testing.assert_array_equal(outs[0][k], outs[2][k])
+    run.close()
+
+
+def test_separate_calls_match_the_step(V, runner):
+    """compact -> reconstruct -> grad_T -> mass_transfer issued one by one,
+    with the mean vertex rule and the two-sided gradients."""
+    import torch
+    wl = _wl("hex16")
+    _say("separate calls hex16")
+    run = runner.PathRun(wl, opts=V.recon_opts(vertex_mode=V.VERTEX_MEAN))
+    b = run.buf
+    V.compact(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.band_idx, b.counts)
+    V.reconstruct(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, b.itf, b.opts)
+    V.grad_T(run.ctx, run.mesh, run.T, run.Tb, wl.T_sat, run.alpha, b.band_idx, b.counts, b.gradT, b.grad_status)
+    N = wl.mesh.n_cells
+    gl = torch.tensor(np.tile([[1.0], [0.5], [0.0]], (1, N)), device=run.dev)
+    gv = torch.tensor(np.tile([[0.0], [0.0], [-2.0]], (1, N)), device=run.dev)
+    md_c = torch.full((N,), 3.0, dtype=torch.float64, device=run.dev)
+    qd_c = torch.full((N,), 3.0, dtype=torch.float64, device=run.dev)
+    V.mass_transfer(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, b.itf, b.gradT, 0.6, 0.03, wl.h_lv,
+                    b.mdot, b.Qdot, gradT_l=gl, gradT_v=gv, mdot_cells=md_c, Qdot_cells=qd_c)
+    g = run.results()
+    om = oracle.OMesh(wl.mesh)
+    geom = oracle.geometry(om)
+    rec = oracle.reconstruct(om, wl.alpha, geom, vertex_mode=1)
+    parity.check_interface(wl, g, rec)
+    md, _ = oracle.mass_transfer(geom, wl.alpha, rec["n"], rec["A"], np.zeros((3, N)), 0.6, 0.03, wl.h_lv,
+                                 gl=gl.cpu().numpy(), gv=gv.cpu().numpy())
+    parity.check_mdot(g["mdot"], md[g["mixed_idx"]])
+    dense = md_c.cpu().numpy()
+    expect = np.zeros(N)
+    expect[g["mixed_idx"]] = g["mdot"]
+    np.testing.assert_array_equal(dense, expect)
+    np.testing.assert_array_equal(qd_c.cpu().numpy(), -expect * wl.h_lv)
+    run.close()
+
+
+@pytest.mark.parametrize("variant", ["standard", "printed", "all"])
+def test_gradient_variants(V, runner, variant):
+    import torch
+    wl = _wl("vor12")
+    _say(f"gradient variant {variant}")
+    run = runner.PathRun(wl)
+    run.step()
+    b = run.buf
+    N = wl.mesh.n_cells
+    out = torch.zeros(3, N, dtype=torch.float64, device=run.dev)
+    st = torch.zeros(N, dtype=torch.int32, device=run.dev)
+    if variant == "all":
+        V.grad_T(run.ctx, run.mesh, run.T, run.Tb, wl.T_sat, run.alpha, None, None, out, st, scope=V.SCOPE_ALL)
+        cells = np.arange(N)
+        ref, rst = oracle.grad(wl.mesh, oracle.geometry(wl.mesh), wl.T, wl.T_bface, wl.T_sat, wl.alpha)
+    else:
+        var = V.GRAD_STANDARD if variant == "standard" else V.GRAD_PRINTED
+        V.grad_T(run.ctx, run.mesh, run.T, run.Tb, wl.T_sat, run.alpha, b.band_idx, b.counts, out, st, variant=var)
+        cells = run.results()["band_idx"]
+        ref, rst = oracle.grad(wl.mesh, oracle.geometry(wl.mesh), wl.T, wl.T_bface, wl.T_sat, wl.alpha,
+                               modified=(variant != "standard"), printed=(variant == "printed"))
+    torch.cuda.synchronize()
+    parity.check_grad(wl, out.cpu().numpy(), ref, cells)
+    np.testing.assert_array_equal(st.cpu().numpy()[cells], rst[cells])
+    run.close()
+
+
+def test_fixed_isovalue_and_vertex_override(V, runner):
+    import torch
+    wl = _wl("vor12")
+    _say("fixed iso + vertex override vor12")
+    rng = np.random.default_rng(4)
+    om = oracle.OMesh(wl.mesh)
+    geom = oracle.geometry(om)
+    phi = oracle.vertex_field(om, geom.xc, wl.alpha) + rng.uniform(-0.02, 0.02, wl.mesh.n_verts)
+    phi_t = torch.tensor(phi, device="cuda")
+    for fixed in (False, True):
+        run = runner.PathRun(wl, opts=V.recon_opts(fixed_iso=int(fixed), iso=0.5, phi_vertex=phi_t))
+        run.step()
+        g = run.results()
+        rec = oracle.reconstruct(om, wl.alpha, geom, fixed_iso=fixed, iso=0.5, phi=phi)
+        parity.check_interface(wl, g, rec)
+        if fixed:
+            assert np.all(g["s"][g["status"] == 0] == 0.5)
+        run.close()
+
+
+def test_hint_bracket_same_result_fewer_evaluations(V, runner):
+    import torch
+    wl = _wl("vor12")
+    _say("hint bracket vor12")
+    om = oracle.OMesh(wl.mesh)
+    geom = oracle.geometry(om)
+    plain = oracle.reconstruct(om, wl.alpha, geom)
+    mixed = np.nonzero(plain["status"] != oracle.NOT_MIXED)[0]
+    s = plain["s"]
+    rng = np.random.default_rng(9)
+    # good hints for most cells, wrong ones for every fifth cell
+    off = np.where(np.arange(wl.mesh.n_cells) % 5 == 0, 0.02, 0.0) + rng.uniform(-2e-4, 2e-4, wl.mesh.n_cells)
+    lo = s + off - 1e-3
+    hi = s + off + 1e-3
+    ref = oracle.reconstruct(om, wl.alpha, geom, hint_lo=lo, hint_hi=hi)
+    hl = torch.tensor(lo[mixed], device="cuda")
+    hh = torch.tensor(hi[mixed], device="cuda")
+    run = runner.PathRun(wl, opts=V.recon_opts(bracket=V.BRACKET_HINT), hint_lo=hl, hint_hi=hh)
+    run.step()
+    g = run.results()
+    parity.check_interface(wl, g, ref)
+    assert np.mean(g["iters"]) < np.mean(plain["iters"][mixed])
+    assert np.sum(g["status"] == V.CELL_LEARNED_FALLBACK) > 0
+    run.close()
+
+
+def test_edge_cases_empty_all_and_single(V, runner):
+    """No mixed cell; every cell mixed with a constant field; one mixed cell."""
+    import torch
+    mesh = meshes.hex_mesh(6)
+    N = mesh.n_cells
+    for label, alpha in (("empty", np.ones(N)), ("uniform", np.full(N, 0.37)),
+                         ("single", np.where(np.arange(N) == 100, 0.3, 1.0))):
+        _say(f"edge case {label}")
+        wl = workloads.Workload(label, mesh, alpha, np.full(N, 373.15), np.full(mesh.n_faces, 373.15))
+        run = runner.PathRun(wl)
+        run.step()
+        g = run.results()
+        parity.check_lists(wl, g)
+        rec = oracle.reconstruct(wl.mesh, wl.alpha)
+        parity.check_interface(wl, g, rec)
+        if label == "uniform":
+            assert np.all(g["status"] == V.CELL_DEGENERATE) and np.all(g["A"] == 0)
+        if label == "single":
+            assert g["n_mixed"] == 1 and g["A"][0] > 0
+        run.close()
+    torch.cuda.synchronize()
