@@ -223,6 +223,8 @@ def rsa_spheres(rng: np.random.Generator, n_max: int, r_lo: float, r_hi: float, 
         r = rng.uniform(r_lo, r_hi)
         placed = False
         # vectorised tries in blocks
+        if np.any(lo + r + clearance > hi - r - clearance):
+            break                     # no room for this sphere at all
         for _blk in range(0, max_attempts, 500):
             c = rng.uniform(lo + r + clearance, hi - r - clearance, size=(500, 3))
             if out:

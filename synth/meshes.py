@@ -286,8 +286,11 @@ def _voronoi_from_seeds(seeds: np.ndarray, lo, hi, keep=None):
     fid = np.repeat(np.arange(len(ridx)), flens)
     nxt = np.arange(len(fv)) + 1
     nxt[fo[1:] - 1] = fo[:-1]
-    A = X[fv]
-    B = X[fv[nxt]]
+    # relative to the owner seed: a small face far from the origin would
+    # otherwise lose its orientation to cancellation
+    ref = np.repeat(seeds[owner], flens, axis=0)
+    A = X[fv] - ref
+    B = X[fv[nxt]] - ref
     cr = np.cross(A, B)
     S = np.stack([np.bincount(fid, weights=cr[:, k], minlength=len(ridx)) for k in range(3)], 1)
     d = P[other] - seeds[owner]

@@ -38,6 +38,8 @@ def check_interface(wl, gpu, rec, h=None, report=None):
         report.update(max_dalpha=float(da.max(initial=0)), max_dA_rel=float((dA / np.maximum(Ao, 1e-300)).max(initial=0)),
                       max_dn=float(dn.max(initial=0)), max_dd=float(dd.max(initial=0)))
     assert da.max(initial=0) <= 1e-10, f"alpha* differs by {da.max()} at cell {idx[np.argmax(da)]}"
+    if len(idx) == 0:
+        return
     worst = np.argmax(dA - (1e-9 * Ao + 1e-9 * h * h))
     assert np.all(dA <= 1e-9 * Ao + 1e-9 * h * h), f"A differs: cell {idx[worst]} {gpu['A'][worst]} vs {Ao[worst]}"
     assert dn.max(initial=0) <= 1e-9, f"n differs by {dn.max()} at cell {idx[np.argmax(dn)]}"

@@ -48,9 +48,10 @@ def _wl(name):
         elif name == "vor46":
             _WL[name] = workloads.voronoi_bubble()
         elif name == "hex_small_bubbles":
-            _WL[name] = workloads.random_bubbles(meshes.hex_mesh(24), seed=31, n_max=40, K=16)
+            _WL[name] = workloads.random_bubbles(meshes.hex_mesh(24), seed=31, n_max=40, K=16, r_hi_h=5.0)
         elif name == "vor_small_bubbles":
-            _WL[name] = workloads.random_bubbles(meshes.voronoi_box_mesh(14, seed=32), seed=33, n_max=40, K=16)
+            _WL[name] = workloads.random_bubbles(meshes.voronoi_box_mesh(16, seed=32), seed=33, n_max=40, K=16,
+                                                 r_hi_h=3.0)
     return _WL[name]
 
 
@@ -230,7 +231,8 @@ def test_edge_cases_empty_all_and_single(V, runner):
     mesh = meshes.hex_mesh(6)
     N = mesh.n_cells
     for label, alpha in (("empty", np.ones(N)), ("uniform", np.full(N, 0.37)),
-                         ("single", np.where(np.arange(N) == 100, 0.3, 1.0))):
+                         ("single_interior", np.where(np.arange(N) == 100, 0.3, 1.0)),
+                         ("single_corner", np.where(np.arange(N) == 0, 0.3, 1.0))):
         _say(f"edge case {label}")
         wl = workloads.Workload(label, mesh, alpha, np.full(N, 373.15), np.full(mesh.n_faces, 373.15))
         run = runner.PathRun(wl)
@@ -241,7 +243,11 @@ def test_edge_cases_empty_all_and_single(V, runner):
         parity.check_interface(wl, g, rec)
         if label == "uniform":
             assert np.all(g["status"] == V.CELL_DEGENERATE) and np.all(g["A"] == 0)
-        if label == "single":
-            assert g["n_mixed"] == 1 and g["A"][0] > 0
+        if label == "single_interior":
+            # every vertex of an interior cell of a uniform grid gets the same
+            # inverse-distance value and the alpha gradient vanishes
+            assert g["n_mixed"] == 1 and g["status"][0] == V.CELL_DEGENERATE and g["A"][0] == 0
+        if label == "single_corner":
+            assert g["n_mixed"] == 1 and g["status"][0] == V.CELL_OK and g["A"][0] > 0
         run.close()
     torch.cuda.synchronize()

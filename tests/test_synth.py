@@ -1,0 +1,61 @@
+"""The seeded mesh and field generators produce valid inputs."""
+import numpy as np
+import pytest
+
+from synth import meshes, workloads
+
+
+def _closed_and_oriented(m):
+    """Every cell's outward loops use each directed edge once, with its reverse."""
+    cfo = m.cell_face_off
+    cells = np.repeat(np.arange(m.n_cells), np.diff(cfo))
+    faces = m.cell_face.astype(np.int64)
+    sz = np.diff(m.face_vert_off)[faces]
+    owner_side = m.face_owner[faces] == cells
+    a_list, b_list, c_list = [], [], []
+    for f_i, (f, n, own, P) in enumerate(zip(faces, sz, owner_side, cells)):
+        lp = m.face_vert[m.face_vert_off[f]:m.face_vert_off[f] + n]
+        if not own:
+            lp = lp[::-1]
+        a_list.append(lp)
+        b_list.append(np.roll(lp, -1))
+        c_list.append(np.full(n, P))
+    a = np.concatenate(a_list).astype(np.int64)
+    b = np.concatenate(b_list).astype(np.int64)
+    c = np.concatenate(c_list).astype(np.int64)
+    NV = m.n_verts
+    fwd = (c * NV + a) * NV + b
+    rev = (c * NV + b) * NV + a
+    assert len(np.unique(fwd)) == len(fwd), "a directed edge repeats within a cell"
+    assert np.all(np.isin(rev, fwd)), "a cell surface is not closed"
+
+
+def test_hex_mesh_is_closed():
+    m = meshes.hex_mesh(5)
+    _closed_and_oriented(m)
+    assert m.n_faces == 3 * 5 * 5 * 6
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (12, 7)])
+def test_voronoi_mesh_is_closed_and_fills_the_box(n, seed):
+    import oracle
+    m = meshes.voronoi_box_mesh(n, seed)
+    _closed_and_oriented(m)
+    g = oracle.geometry(m)
+    assert g.V.sum() == pytest.approx(1.0, rel=1e-12)
+    assert np.all(g.V > 0)
+    nf = np.diff(m.cell_face_off)
+    assert 12.0 < nf.mean() < 16.0
+
+
+def test_bench_sized_voronoi_mesh_is_closed():
+    m = meshes.voronoi_box_mesh(46, 2)
+    assert m.n_cells == 194672
+    _closed_and_oriented(m)
+
+
+def test_alpha_fractions_match_the_sphere_volume():
+    wl = workloads.hex_sphere()
+    vap = (1 - wl.alpha).sum() / wl.mesh.n_cells
+    assert vap == pytest.approx(4 / 3 * np.pi * 0.3 ** 3, rel=1e-4)
+    assert 400 < wl.n_mixed < 440
