@@ -207,6 +207,8 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   std::vector<int64_t> cv_off(N + 1, 0), cl_off(N + 1, 0);
   std::vector<int32_t> cv_gid;
   std::vector<uint8_t> cl_lv;
+  std::vector<uint16_t> cl_eid;            // local undirected edge id per loop position
+  std::vector<int32_t> edge_stamp(65536, -1), edge_id(65536, 0);
   std::vector<int32_t> cf_nbr(ncf);
   std::vector<uint16_t> cf_loff(ncf);
   std::vector<uint8_t> cf_lsz(ncf);
@@ -255,6 +257,22 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
       uint16_t r = (uint16_t)((dedge[j] & 0xff) << 8 | (dedge[j] >> 8));
       VOFPC_REQUIRE(std::binary_search(dedge.begin(), dedge.end(), r), VOFPC_E_MESH,
                     "mesh_upload: cell " + std::to_string(P) + " is not closed");
+    }
+    // local edge ids in order of first appearance along the loops
+    {
+      int32_t ne = 0;
+      for (int64_t i = cfo[P]; i < cfo[P + 1]; ++i) {
+        int64_t o = lbase + cf_loff[i], n = cf_lsz[i];
+        for (int64_t k = 0; k < n; ++k) {
+          int a = cl_lv[o + k], b = cl_lv[o + (k + 1 == n ? 0 : k + 1)];
+          int key = a < b ? (a << 8 | b) : (b << 8 | a);
+          if (edge_stamp[key] != (int32_t)P) {
+            edge_stamp[key] = (int32_t)P;
+            edge_id[key] = ne++;
+          }
+          cl_eid.push_back((uint16_t)edge_id[key]);
+        }
+      }
     }
     for (int32_t g : loc) cv_gid.push_back(g);
     cv_off[P + 1] = (int64_t)cv_gid.size();
@@ -306,6 +324,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   COPY(cv_gid, cv_gid.data(), cv_gid.size(), int32_t);
   COPY(cl_off, cl_off.data(), N + 1, int64_t);
   COPY(cl_lv, cl_lv.data(), cl_lv.size(), uint8_t);
+  COPY(cl_eid, cl_eid.data(), cl_eid.size(), uint16_t);
   COPY(vc_off, vc_off.data(), NV + 1, int64_t);
   COPY(vc_cell, vc_cell.data(), vc_cell.size(), int32_t);
   COPY(vc_w, (const double *)nullptr, vc_cell.size(), double);

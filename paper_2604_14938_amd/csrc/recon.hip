@@ -3,21 +3,34 @@
 // One cell per group of W lanes (W divides 64; a block is one wavefront, so a
 // block holds 64/W cells).  The cell's polyhedron is staged in LDS: vertex
 // positions relative to the centroid, the vertex field, the outward face
-// loops as local vertex ids.  A volume evaluation at isovalue s spreads the
-// faces over the lanes:
+// loops as local vertex ids with a local edge id and the reciprocal of the
+// vertex-value difference for every loop position.
+//
+// Full volume evaluation at isovalue s (faces spread over the lanes):
 //   - each face lane walks its loop: liquid edges and the liquid parts of the
 //     cut edges add to the divergence-theorem sum; exits (liquid -> vapour)
-//     and entries (vapour -> liquid) are kept as bit masks over loop
-//     positions; each exit is paired with an entry (the next one in loop
-//     order when the face-mean value is >= s or the face has two crossings,
-//     else the previous one), giving a chord exit -> entry that closes the
-//     face's liquid polygon;
+//     and entries (vapour -> liquid) are bit masks over loop positions; each
+//     exit is paired with an entry (the next one in loop order when the
+//     face-mean value is >= s or the face has two crossings, else the
+//     previous one), giving a chord exit -> entry that closes the face's
+//     liquid polygon;
 //   - chords are linked into iso-loops (the loop continues in the face whose
 //     entry edge is this chord's exit edge) and labelled by pointer jumping;
 //   - each loop is fanned from its length-weighted polyline centroid, which
 //     adds its volume share, its area vector and its centre.
 // Crossing points follow Eq. edge_intersection, computed from the liquid end
 // of the edge so both faces sharing an edge get the same point.
+//
+// Fixed-topology evaluation: the set of cut edges, their pairing and the
+// loops only change when s crosses a vertex value or a face-mean value.  A
+// full evaluation records, per chord (one chord per lane), the edge it leaves
+// through, its face centre, its neighbours on the loop and the constant sum
+// over the fully liquid edges, valid up to the neighbouring breakpoints; an
+// isovalue inside that interval then only moves the crossing points along
+// their edges and redoes the chord and loop sums.  Two such records are kept,
+// so a bracket closing in on a breakpoint from both sides stays on the short
+// path.  It evaluates the same volume function (same construction, fewer
+// operations) at the same bisection points.
 //
 // The isovalue is bisected until |V/V_P - alpha| <= tol_rel min(alpha,1-alpha);
 // when the bracket collapses first, the end nearer to alpha V_P is kept.
@@ -35,34 +48,74 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Group reductions.  Within a row of 16 lanes they use DPP butterflies
+// (xor 1 and xor 2 inside quads, then the half-row and row mirrors), which
+// stay inside groups of 8 and 16 lanes and avoid the LDS permute latency;
+// wider groups finish with cross-row shuffles.  Every lane of the group ends
+// with the same, bitwise identical, result (IEEE addition is commutative).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __builtin_bit_cast(int2, v).x, hi = __builtin_bit_cast(int2, v).y;
+  int2 r;
+  r.x = dpp_i<CTRL>(lo);
+  r.y = dpp_i<CTRL>(hi);
+  return __builtin_bit_cast(double, r);
+}
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kHalfMirror = 0x141, kRowMirror = 0x140;
+
 template <int W>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
-  return v;
-}
-template <int W>
-__device__ __forceinline__ int gmin_i(int v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, W));
+  static_assert(W == 8 || W == 16 || W == 32 || W == 64, "group width");
+  v += dpp_d<kQuadXor1>(v);
+  v += dpp_d<kQuadXor2>(v);
+  v += dpp_d<kHalfMirror>(v);
+  if (W >= 16) v += dpp_d<kRowMirror>(v);
+  if (W >= 32) v += __shfl_xor(v, 16, W);
+  if (W >= 64) v += __shfl_xor(v, 32, W);
   return v;
 }
 template <int W>
 __device__ __forceinline__ int gsum_i(int v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  v += dpp_i<kQuadXor1>(v);
+  v += dpp_i<kQuadXor2>(v);
+  v += dpp_i<kHalfMirror>(v);
+  if (W >= 16) v += dpp_i<kRowMirror>(v);
+  if (W >= 32) v += __shfl_xor(v, 16, W);
+  if (W >= 64) v += __shfl_xor(v, 32, W);
+  return v;
+}
+template <int W>
+__device__ __forceinline__ int gmin_i(int v) {
+  v = min(v, dpp_i<kQuadXor1>(v));
+  v = min(v, dpp_i<kQuadXor2>(v));
+  v = min(v, dpp_i<kHalfMirror>(v));
+  if (W >= 16) v = min(v, dpp_i<kRowMirror>(v));
+  if (W >= 32) v = min(v, __shfl_xor(v, 16, W));
+  if (W >= 64) v = min(v, __shfl_xor(v, 32, W));
   return v;
 }
 template <int W>
 __device__ __forceinline__ double gmin(double v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, W));
+  v = fmin(v, dpp_d<kQuadXor1>(v));
+  v = fmin(v, dpp_d<kQuadXor2>(v));
+  v = fmin(v, dpp_d<kHalfMirror>(v));
+  if (W >= 16) v = fmin(v, dpp_d<kRowMirror>(v));
+  if (W >= 32) v = fmin(v, __shfl_xor(v, 16, W));
+  if (W >= 64) v = fmin(v, __shfl_xor(v, 32, W));
   return v;
 }
 template <int W>
 __device__ __forceinline__ double gmax(double v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, W));
+  v = fmax(v, dpp_d<kQuadXor1>(v));
+  v = fmax(v, dpp_d<kQuadXor2>(v));
+  v = fmax(v, dpp_d<kHalfMirror>(v));
+  if (W >= 16) v = fmax(v, dpp_d<kRowMirror>(v));
+  if (W >= 32) v = fmax(v, __shfl_xor(v, 16, W));
+  if (W >= 64) v = fmax(v, __shfl_xor(v, 32, W));
   return v;
 }
 // exclusive prefix sum over the group
@@ -82,26 +135,58 @@ __device__ __forceinline__ double det3(double a0, double a1, double a2, double b
   return a0 * (b1 * c2 - b2 * c1) + a1 * (b2 * c0 - b0 * c2) + a2 * (b0 * c1 - b1 * c0);
 }
 
-template <int NV, int NF, int NL, int NCH>
+// Chord data of a fixed topology, one chord per lane (see the file comment),
+// valid for isovalues in (bp_lo, bp_hi].
+template <int W>
+struct FastSlot {
+  double xi[3][W];   // liquid end of the exit edge
+  double dx[3][W];   // vapour end minus liquid end
+  double phi_i[W];   // value at the liquid end
+  double inv[W];     // 1/(phi_vapour - phi_liquid)
+  double cf[3][W];   // centre of the chord's face
+  double xn[3][W];   // liquid end of the entry edge
+  double c_full;     // sum over the fully liquid face edges
+  double bp_lo, bp_hi;
+  uint8_t prev[W], next[W], lab[W];
+  int nch, nloops, valid;
+};
+
+constexpr int kSlotChords = 32;   // chords a cached topology can hold
+
+template <int W, int NV, int NF, int NL, int NCH>
 struct GroupMem {
   double X[3][NV];
   double phi[NV];
   double cf[3][NF];
   double fmean[NF];
-  double ps[3][NCH];
-  uint16_t floff[NF];
-  uint16_t xkey[NCH];
-  uint16_t nkey[NCH];
-  uint16_t nxt[NCH];
+  double inv[NL];         // 1/(phi[next] - phi[this]) of each loop position
+  double ps[3][NCH];      // chord exit points
+  FastSlot<W> fs[2];
+  uint16_t ch_xe[NCH];    // chord exit edge id
+  uint16_t ch_ne[NCH];    // chord entry edge id
+  uint16_t ch_face[NCH];  // chord face
+  uint16_t ch_xpos[NCH];  // loop position of the exit edge
+  uint16_t by_entry[NCH]; // chord entering through edge e
+  uint16_t by_exit[NCH];  // chord leaving through edge e
   uint16_t lab[2][NCH];
   uint16_t jmp[2][NCH];
+  uint16_t floff[NF];
+  uint16_t eid[NL];
+  double sp_s[8], sp_r[8], sp_res[8][8];  // speculative round: node isovalue, residual, cut
+  double end_res[2][8];                   // cut at the current bracket ends (lo, hi)
+  double ept[3][NCH];                     // crossing point of each cut edge (by edge id)
+  uint64_t fex[NF], fen[NF];              // exit / entry bit masks of each face
+  int sp_ok[8];
+  uint16_t pnext[NL];                     // next loop position of the same face
+  uint8_t pface[NL];                      // face of a loop position
+  uint8_t pk[NL];                         // index of the position within its face
   uint8_t fsz[NF];
   uint8_t lv[NL];
 };
 
 struct CutRes {
   double V, S0, S1, S2, A, c0, c1, c2;
-  int nloops;
+  int nch;
   bool err;
 };
 
@@ -117,17 +202,6 @@ struct ReconParams {
   vofpc_interface out;
 };
 
-// crossing point of the edge (a, b) at isovalue s, from its liquid end
-template <class GM>
-__device__ __forceinline__ void crossing(const GM &L, int a, int b, double s, double &p0, double &p1, double &p2) {
-  int i = (L.phi[a] >= s) ? a : b;
-  int j = (i == a) ? b : a;
-  double lam = (s - L.phi[i]) / (L.phi[j] - L.phi[i]);
-  p0 = L.X[0][i] + lam * (L.X[0][j] - L.X[0][i]);
-  p1 = L.X[1][i] + lam * (L.X[1][j] - L.X[1][i]);
-  p2 = L.X[2][i] + lam * (L.X[2][j] - L.X[2][i]);
-}
-
 __device__ __forceinline__ int next_bit_after(uint64_t mask, int q) {
   uint64_t hi = (q >= 63) ? 0ull : (mask & (~0ull << (q + 1)));
   return hi ? __ffsll((long long)hi) - 1 : __ffsll((long long)mask) - 1;
@@ -137,95 +211,119 @@ __device__ __forceinline__ int prev_bit_before(uint64_t mask, int q) {
   return lo ? 63 - __clzll((long long)lo) : 63 - __clzll((long long)mask);
 }
 
-// One volume evaluation of the staged cell at isovalue s.
-template <int W, int NV, int NF, int NL, int NCH>
-__device__ CutRes cut_eval(GroupMem<NV, NF, NL, NCH> &L, int lane, int nf, double s) {
-  CutRes R;
-  R.err = false;
-  double vf = 0.0;
-  int nch = 0;
-  bool err = false;
-  // ---- faces: liquid parts and chords
-  for (int base = 0; base < nf; base += W) {
-    const int f = base + lane;
-    uint64_t ex = 0, en = 0;
-    int m = 0, o = 0;
-    double c0 = 0, c1 = 0, c2 = 0;
-    if (f < nf) {
-      m = L.fsz[f];
-      o = L.floff[f];
-      c0 = L.cf[0][f]; c1 = L.cf[1][f]; c2 = L.cf[2][f];
-      if (m > 64) err = true;
-      int a = L.lv[o];
-      bool la = L.phi[a] >= s;
-      for (int k = 0; k < m && k < 64; ++k) {
-        int b = L.lv[o + (k + 1 == m ? 0 : k + 1)];
-        bool lb = L.phi[b] >= s;
-        if (la && lb) {
-          vf += det3(c0, c1, c2, L.X[0][a], L.X[1][a], L.X[2][a], L.X[0][b], L.X[1][b], L.X[2][b]);
-        } else if (la != lb) {
-          double p0, p1, p2;
-          crossing(L, a, b, s, p0, p1, p2);
-          if (la) {  // exit: liquid part from a to the crossing
-            vf += det3(c0, c1, c2, L.X[0][a], L.X[1][a], L.X[2][a], p0, p1, p2);
-            ex |= 1ull << k;
-          } else {   // entry: liquid part from the crossing to b
-            vf += det3(c0, c1, c2, p0, p1, p2, L.X[0][b], L.X[1][b], L.X[2][b]);
-            en |= 1ull << k;
-          }
-        }
-        a = b;
-        la = lb;
-      }
-    }
-    int my = __popcll(ex);
-    if (my && (en == 0 || __popcll(en) != my)) {  // a closed loop alternates exits and entries
-      err = true;
-      my = 0;
-    }
-    const int slot = nch + gscan_excl<W>(my, lane);
-    if (my) {
-      const int nx = my + __popcll(en);
-      const bool liquid_connected = (nx == 2) || (L.fmean[f] >= s);
-      uint64_t rem = ex;
-      int j = 0;
-      while (rem) {
-        const int q = __ffsll((long long)rem) - 1;
-        rem &= rem - 1;
-        const int r = liquid_connected ? next_bit_after(en, q) : prev_bit_before(en, q);
-        const int xa = L.lv[o + q], xb = L.lv[o + (q + 1 == m ? 0 : q + 1)];
-        const int na = L.lv[o + r], nb = L.lv[o + (r + 1 == m ? 0 : r + 1)];
-        double s0, s1, s2, e0, e1, e2;
-        crossing(L, xa, xb, s, s0, s1, s2);
-        crossing(L, na, nb, s, e0, e1, e2);
-        vf += det3(c0, c1, c2, s0, s1, s2, e0, e1, e2);
-        const int c = slot + j++;
-        if (c < NCH) {
-          L.ps[0][c] = s0; L.ps[1][c] = s1; L.ps[2][c] = s2;
-          L.xkey[c] = (uint16_t)(xa < xb ? (xa << 8 | xb) : (xb << 8 | xa));
-          L.nkey[c] = (uint16_t)(na < nb ? (na << 8 | nb) : (nb << 8 | na));
-        } else {
-          err = true;
-        }
-      }
-    }
-    nch += gsum_i<W>(my);
+// crossing point on loop position `pos` (edge a -> b), from the liquid end
+template <class GM>
+__device__ __forceinline__ void crossing_at(const GM &L, int pos, int a, int b, double s, double &p0, double &p1,
+                                            double &p2) {
+  const double iv = L.inv[pos];  // 1/(phi_b - phi_a); from b the reciprocal is -iv
+  int i, j;
+  double lam;
+  if (L.phi[a] >= s) {
+    i = a; j = b; lam = (s - L.phi[a]) * iv;
+  } else {
+    i = b; j = a; lam = (s - L.phi[b]) * (-iv);
   }
-  wave_sync();
-  if (nch > NCH) nch = NCH;
-  // ---- link chords: next = the chord whose entry edge is this chord's exit edge
+  p0 = L.X[0][i] + lam * (L.X[0][j] - L.X[0][i]);
+  p1 = L.X[1][i] + lam * (L.X[1][j] - L.X[1][i]);
+  p2 = L.X[2][i] + lam * (L.X[2][j] - L.X[2][i]);
+}
+
+// Sums of one loop over the lanes selected by `mine`: polyline centroid,
+// fan volume, area vector.
+template <int W>
+__device__ __forceinline__ void one_loop(bool mine, double len, double p0, double p1, double p2, double q0, double q1,
+                                         double q2, double first0, double first1, double first2, double &Vi,
+                                         double &S0, double &S1, double &S2, double &Asum, double &cw0, double &cw1,
+                                         double &cw2) {
+  double l = mine ? len : 0.0;
+  double m0 = mine ? len * (p0 + q0) : 0.0;
+  double m1 = mine ? len * (p1 + q1) : 0.0;
+  double m2 = mine ? len * (p2 + q2) : 0.0;
+  l = gsum<W>(l); m0 = gsum<W>(m0); m1 = gsum<W>(m1); m2 = gsum<W>(m2);
+  double k0, k1, k2;
+  if (l > 0) {
+    const double h = 0.5 / l;
+    k0 = m0 * h; k1 = m1 * h; k2 = m2 * h;
+  } else {
+    k0 = first0; k1 = first1; k2 = first2;
+  }
+  double vi = 0, t0 = 0, t1 = 0, t2 = 0;
+  if (mine) {
+    vi = det3(k0, k1, k2, p0, p1, p2, q0, q1, q2);
+    const double u0 = p0 - k0, u1 = p1 - k1, u2 = p2 - k2;
+    const double w0 = q0 - k0, w1 = q1 - k1, w2 = q2 - k2;
+    // the fan is oriented out of the liquid; the normal is the opposite
+    t0 = -0.5 * (u1 * w2 - u2 * w1);
+    t1 = -0.5 * (u2 * w0 - u0 * w2);
+    t2 = -0.5 * (u0 * w1 - u1 * w0);
+  }
+  vi = gsum<W>(vi); t0 = gsum<W>(t0); t1 = gsum<W>(t1); t2 = gsum<W>(t2);
+  const double Ak = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+  Vi += vi;
+  S0 += t0; S1 += t1; S2 += t2;
+  Asum += Ak;
+  cw0 += Ak * k0; cw1 += Ak * k1; cw2 += Ak * k2;
+}
+
+// Loop sums with one chord per lane (nch <= W): lane c holds the loop point
+// p (exit point of chord c), the lane of the next point on its loop and its
+// loop label (smallest chord index on the loop; idle lanes are not valid).
+// nloops is the number of loops when known, else -1.
+template <int W>
+__device__ __forceinline__ void loops_reg(int lane, bool valid, double p0, double p1, double p2, int next, int lab,
+                                          int nloops, CutRes &R) {
+  const double q0 = __shfl(p0, next, W), q1 = __shfl(p1, next, W), q2 = __shfl(p2, next, W);
+  const double d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2;
+  const double len = valid ? sqrt(d0 * d0 + d1 * d1 + d2 * d2) : 0.0;
+  double Vi = 0, S0 = 0, S1 = 0, S2 = 0, Asum = 0, cw0 = 0, cw1 = 0, cw2 = 0;
+  if (nloops < 0) nloops = gsum_i<W>((valid && lab == lane) ? 1 : 0);
+  if (nloops == 1) {
+    const double f0 = __shfl(p0, 0, W), f1 = __shfl(p1, 0, W), f2 = __shfl(p2, 0, W);
+    one_loop<W>(valid, len, p0, p1, p2, q0, q1, q2, f0, f1, f2, Vi, S0, S1, S2, Asum, cw0, cw1, cw2);
+  } else if (nloops > 1) {
+    int prev = -1;
+    while (true) {
+      const int cand = gmin_i<W>((valid && lab == lane && lane > prev) ? lane : 0x7fffffff);
+      if (cand == 0x7fffffff) break;
+      const double f0 = __shfl(p0, cand, W), f1 = __shfl(p1, cand, W), f2 = __shfl(p2, cand, W);
+      one_loop<W>(valid && lab == cand, len, p0, p1, p2, q0, q1, q2, f0, f1, f2, Vi, S0, S1, S2, Asum, cw0, cw1,
+                  cw2);
+      prev = cand;
+    }
+  }
+  R.V += Vi * (1.0 / 6.0);
+  R.S0 = S0; R.S1 = S1; R.S2 = S2;
+  R.A = Asum;
+  if (Asum > 0) {
+    const double ia = 1.0 / Asum;
+    R.c0 = cw0 * ia; R.c1 = cw1 * ia; R.c2 = cw2 * ia;
+  } else {
+    R.c0 = R.c1 = R.c2 = 0;
+  }
+}
+
+// Loop labels of the chords in registers by pointer jumping.
+template <int W>
+__device__ __forceinline__ int labels_reg(int lane, bool valid, int next, int nch) {
+  int lab = valid ? lane : 0x7fff;
+  int j = valid ? next : lane;
+  for (int span = 1; span < nch; span <<= 1) {
+    const int lj = __shfl(lab, j, W);
+    const int jj = __shfl(j, j, W);
+    lab = lab < lj ? lab : lj;
+    j = jj;
+  }
+  return lab;
+}
+
+// Loop sums for more chords than lanes: labels and sums through LDS.
+template <int W, class GM>
+__device__ void loops_lds(GM &L, int lane, int nch, CutRes &R) {
   for (int c = lane; c < nch; c += W) {
-    const uint16_t key = L.xkey[c];
-    int nx = -1;
-    for (int j = 0; j < nch; ++j)
-      if (L.nkey[j] == key) { nx = j; break; }
-    if (nx < 0) { err = true; nx = c; }
-    L.nxt[c] = (uint16_t)nx;
     L.lab[0][c] = (uint16_t)c;
-    L.jmp[0][c] = (uint16_t)nx;
+    L.jmp[0][c] = L.by_entry[L.ch_xe[c]];
   }
   wave_sync();
-  // ---- loop labels: minimum chord index on each cycle, by pointer jumping
   int cur = 0;
   for (int span = 1; span < nch; span <<= 1) {
     for (int c = lane; c < nch; c += W) {
@@ -237,9 +335,8 @@ __device__ CutRes cut_eval(GroupMem<NV, NF, NL, NCH> &L, int lane, int nf, doubl
     wave_sync();
     cur ^= 1;
   }
-  // ---- loops: centroid, fan volume, area vector
   double Vi = 0, S0 = 0, S1 = 0, S2 = 0, Asum = 0, cw0 = 0, cw1 = 0, cw2 = 0;
-  int nloops = 0, prev = -1;
+  int prev = -1;
   while (true) {
     int cand = 0x7fffffff;
     for (int c = lane; c < nch; c += W)
@@ -249,7 +346,7 @@ __device__ CutRes cut_eval(GroupMem<NV, NF, NL, NCH> &L, int lane, int nf, doubl
     double l = 0, m0 = 0, m1 = 0, m2 = 0;
     for (int c = lane; c < nch; c += W) {
       if (L.lab[cur][c] != cand) continue;
-      const int n = L.nxt[c];
+      const int n = L.by_entry[L.ch_xe[c]];
       const double a0 = L.ps[0][c], a1 = L.ps[1][c], a2 = L.ps[2][c];
       const double b0 = L.ps[0][n], b1 = L.ps[1][n], b2 = L.ps[2][n];
       const double d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
@@ -269,13 +366,12 @@ __device__ CutRes cut_eval(GroupMem<NV, NF, NL, NCH> &L, int lane, int nf, doubl
     double vi = 0, t0 = 0, t1 = 0, t2 = 0;
     for (int c = lane; c < nch; c += W) {
       if (L.lab[cur][c] != cand) continue;
-      const int n = L.nxt[c];
+      const int n = L.by_entry[L.ch_xe[c]];
       const double a0 = L.ps[0][c], a1 = L.ps[1][c], a2 = L.ps[2][c];
       const double b0 = L.ps[0][n], b1 = L.ps[1][n], b2 = L.ps[2][n];
       vi += det3(k0, k1, k2, a0, a1, a2, b0, b1, b2);
       const double u0 = a0 - k0, u1 = a1 - k1, u2 = a2 - k2;
       const double w0 = b0 - k0, w1 = b1 - k1, w2 = b2 - k2;
-      // the fan is oriented out of the liquid; the normal is the opposite
       t0 -= 0.5 * (u1 * w2 - u2 * w1);
       t1 -= 0.5 * (u2 * w0 - u0 * w2);
       t2 -= 0.5 * (u0 * w1 - u1 * w0);
@@ -286,11 +382,9 @@ __device__ CutRes cut_eval(GroupMem<NV, NF, NL, NCH> &L, int lane, int nf, doubl
     S0 += t0; S1 += t1; S2 += t2;
     Asum += Ak;
     cw0 += Ak * k0; cw1 += Ak * k1; cw2 += Ak * k2;
-    ++nloops;
     prev = cand;
   }
-  vf = gsum<W>(vf);
-  R.V = (vf + Vi) * (1.0 / 6.0);
+  R.V += Vi * (1.0 / 6.0);
   R.S0 = S0; R.S1 = S1; R.S2 = S2;
   R.A = Asum;
   if (Asum > 0) {
@@ -298,9 +392,181 @@ __device__ CutRes cut_eval(GroupMem<NV, NF, NL, NCH> &L, int lane, int nf, doubl
   } else {
     R.c0 = R.c1 = R.c2 = 0;
   }
-  R.nloops = nloops;
+}
+
+// Full volume evaluation, faces over the lanes of the wave.  With
+// build_slot >= 0 it also records the fixed-topology chord data of this
+// isovalue into that cache slot (when the chords fit it).
+template <int NV, int NF, int NL, int NCH>
+__device__ CutRes cut_full(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, int nf, int nl, double s,
+                           int build_slot) {
+  constexpr int W = 64;
+  CutRes R;
+  R.err = false;
+  double vfull = 0.0, vcut = 0.0;
+  int nch = 0;
+  bool err = false;
+  // (1) loop positions over the lanes: liquid edges and liquid parts of cut
+  // edges, exit / entry bits of every face, crossing points by edge
+  for (int f = lane; f < nf; f += W) {
+    L.fex[f] = 0;
+    L.fen[f] = 0;
+  }
+  wave_sync();
+  for (int pos = lane; pos < nl; pos += W) {
+    const int f = L.pface[pos];
+    const int a = L.lv[pos], b = L.lv[L.pnext[pos]];
+    const bool la = L.phi[a] >= s, lb = L.phi[b] >= s;
+    const double c0 = L.cf[0][f], c1 = L.cf[1][f], c2 = L.cf[2][f];
+    if (la && lb) {
+      vfull += det3(c0, c1, c2, L.X[0][a], L.X[1][a], L.X[2][a], L.X[0][b], L.X[1][b], L.X[2][b]);
+    } else if (la != lb) {
+      double p0, p1, p2;
+      crossing_at(L, pos, a, b, s, p0, p1, p2);
+      const uint64_t bit = 1ull << L.pk[pos];
+      if (la) {  // exit: liquid part from a to the crossing
+        vcut += det3(c0, c1, c2, L.X[0][a], L.X[1][a], L.X[2][a], p0, p1, p2);
+        atomicOr((unsigned long long *)&L.fex[f], (unsigned long long)bit);
+        const int e = L.eid[pos];
+        L.ept[0][e] = p0; L.ept[1][e] = p1; L.ept[2][e] = p2;
+      } else {   // entry: liquid part from the crossing to b
+        vcut += det3(c0, c1, c2, p0, p1, p2, L.X[0][b], L.X[1][b], L.X[2][b]);
+        atomicOr((unsigned long long *)&L.fen[f], (unsigned long long)bit);
+      }
+    }
+  }
+  wave_sync();
+  // (2) chords: each exit is paired with an entry of its face (the next one
+  // in loop order when the face-mean value is >= s or the face has two
+  // crossings, else the previous one); chords are numbered in position order
+  for (int base = 0; base < nl; base += W) {
+    const int pos = base + lane;
+    bool is_exit = false;
+    int f = 0, q = 0;
+    uint64_t ex = 0, en = 0;
+    if (pos < nl) {
+      f = L.pface[pos];
+      q = L.pk[pos];
+      ex = L.fex[f];
+      en = L.fen[f];
+      is_exit = (ex >> q) & 1ull;
+    }
+    if (is_exit && __popcll(en) != __popcll(ex)) {  // a closed loop alternates exits and entries
+      err = true;
+      is_exit = false;
+    }
+    const uint64_t bal = __ballot(is_exit);
+    const int c = nch + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (is_exit) {
+      const bool liquid_connected = (__popcll(ex) == 1) || (L.fmean[f] >= s);
+      const int r = liquid_connected ? next_bit_after(en, q) : prev_bit_before(en, q);
+      const int o = L.floff[f];
+      const int xe = L.eid[pos], ne = L.eid[o + r];
+      const double s0 = L.ept[0][xe], s1 = L.ept[1][xe], s2 = L.ept[2][xe];
+      const double e0 = L.ept[0][ne], e1 = L.ept[1][ne], e2 = L.ept[2][ne];
+      vcut += det3(L.cf[0][f], L.cf[1][f], L.cf[2][f], s0, s1, s2, e0, e1, e2);
+      if (c < NCH) {
+        L.ps[0][c] = s0; L.ps[1][c] = s1; L.ps[2][c] = s2;
+        L.ch_xe[c] = (uint16_t)xe;
+        L.ch_ne[c] = (uint16_t)ne;
+        L.ch_face[c] = (uint16_t)f;
+        L.ch_xpos[c] = (uint16_t)pos;
+        L.by_entry[ne] = (uint16_t)c;
+        L.by_exit[xe] = (uint16_t)c;
+      } else {
+        err = true;
+      }
+    }
+    nch += __popcll(bal);
+  }
+  wave_sync();
+  if (nch > NCH) nch = NCH;
+  vfull = gsum<W>(vfull);
+  vcut = gsum<W>(vcut);
+  R.V = (vfull + vcut) * (1.0 / 6.0);
+  R.nch = nch;
+  if (nch <= W) {
+    const bool valid = lane < nch;
+    double p0 = 0, p1 = 0, p2 = 0;
+    int next = lane;
+    if (valid) {
+      p0 = L.ps[0][lane]; p1 = L.ps[1][lane]; p2 = L.ps[2][lane];
+      next = L.by_entry[L.ch_xe[lane]];
+    }
+    const int lab = labels_reg<W>(lane, valid, next, nch);
+    const int nloops = gsum_i<W>((valid && lab == lane) ? 1 : 0);
+    loops_reg<W>(lane, valid, p0, p1, p2, next, lab, nloops, R);
+    if (build_slot >= 0 && nch <= kSlotChords) {
+      FastSlot<kSlotChords> &F = L.fs[build_slot];
+      if (lane == 0) {
+        F.nch = nch;
+        F.nloops = nloops;
+        F.c_full = vfull;
+      }
+      int prev = lane;
+      if (valid) {
+        const int pos = L.ch_xpos[lane];
+        const int f = L.ch_face[lane];
+        const int o = L.floff[f], m = L.fsz[f];
+        const int a = L.lv[pos];                                       // liquid end
+        const int b = L.lv[(pos + 1 - o == m) ? o : pos + 1];          // vapour end
+        F.xi[0][lane] = L.X[0][a]; F.xi[1][lane] = L.X[1][a]; F.xi[2][lane] = L.X[2][a];
+        F.dx[0][lane] = L.X[0][b] - L.X[0][a];
+        F.dx[1][lane] = L.X[1][b] - L.X[1][a];
+        F.dx[2][lane] = L.X[2][b] - L.X[2][a];
+        F.phi_i[lane] = L.phi[a];
+        F.inv[lane] = L.inv[pos];
+        F.cf[0][lane] = L.cf[0][f]; F.cf[1][lane] = L.cf[1][f]; F.cf[2][lane] = L.cf[2][f];
+        prev = L.by_exit[L.ch_ne[lane]];
+        F.next[lane] = (uint8_t)next;
+        F.lab[lane] = (uint8_t)lab;
+        F.prev[lane] = (uint8_t)prev;
+      }
+      wave_sync();
+      // liquid end of the entry edge = liquid end of the previous chord's exit edge
+      if (valid) {
+        F.xn[0][lane] = F.xi[0][prev]; F.xn[1][lane] = F.xi[1][prev]; F.xn[2][lane] = F.xi[2][prev];
+      }
+    }
+  } else {
+    loops_lds<W>(L, lane, nch, R);
+  }
   R.err = gsum_i<W>(err ? 1 : 0) != 0;
   wave_sync();
+  return R;
+}
+
+// Evaluation on a fixed topology by a segment of C lanes, chord c on lane c
+// of the segment (see the file comment).
+template <int C>
+__device__ CutRes cut_fast(const FastSlot<kSlotChords> &F, int c, double s) {
+  CutRes R;
+  R.err = false;
+  const int nch = F.nch;
+  R.nch = nch;
+  const bool valid = c < nch;
+  double p0 = 0, p1 = 0, p2 = 0, v = 0.0;
+  int prev = c, next = c, lab = C;
+  if (valid) {
+    const double lam = (s - F.phi_i[c]) * F.inv[c];
+    p0 = F.xi[0][c] + lam * F.dx[0][c];
+    p1 = F.xi[1][c] + lam * F.dx[1][c];
+    p2 = F.xi[2][c] + lam * F.dx[2][c];
+    prev = F.prev[c];
+    next = F.next[c];
+    lab = F.lab[c];
+  }
+  // entry point of this chord = exit point of the previous chord on the loop
+  const double n0 = __shfl(p0, prev, C), n1 = __shfl(p1, prev, C), n2 = __shfl(p2, prev, C);
+  if (valid) {
+    const double c0 = F.cf[0][c], c1 = F.cf[1][c], c2 = F.cf[2][c];
+    v = det3(c0, c1, c2, F.xi[0][c], F.xi[1][c], F.xi[2][c], p0, p1, p2) +
+        det3(c0, c1, c2, p0, p1, p2, n0, n1, n2) +
+        det3(c0, c1, c2, n0, n1, n2, F.xn[0][c], F.xn[1][c], F.xn[2][c]);
+  }
+  v = gsum<C>(v);
+  R.V = (F.c_full + v) * (1.0 / 6.0);
+  loops_reg<C>(c, valid, p0, p1, p2, next, lab, F.nloops, R);
   return R;
 }
 
@@ -309,19 +575,102 @@ __device__ __forceinline__ double ulp_of(double x) {
   return nextafter(x, __builtin_inf()) - x;
 }
 
-template <int W, int NV, int NF, int NL, int NCH>
-__global__ __launch_bounds__(64) void recon_kernel(ReconParams p) {
-  constexpr int G = 64 / W;
-  __shared__ GroupMem<NV, NF, NL, NCH> mem[G];
-  const int g = threadIdx.x / W, lane = threadIdx.x % W;
-  GroupMem<NV, NF, NL, NCH> &L = mem[g];
+// The topology of a cut (which vertices are liquid, how faces with four or
+// more crossings pair them) is constant for isovalues between consecutive
+// breakpoints, the vertex values and the face-mean values: on (b_i, b_i+1].
+// This returns that interval around s.
+template <class GM>
+__device__ __forceinline__ void breakpoint_interval(const GM &L, int lane, int nv, int nf, double s, double &lo,
+                                                    double &hi) {
+  double a = -__builtin_inf(), b = __builtin_inf();
+  for (int i = lane; i < nv; i += 64) {
+    const double v = L.phi[i];
+    if (v < s) a = fmax(a, v); else b = fmin(b, v);
+  }
+  for (int f = lane; f < nf; f += 64) {
+    const double v = L.fmean[f];
+    if (v < s) a = fmax(a, v); else b = fmin(b, v);
+  }
+  lo = gmax<64>(a);
+  hi = gmin<64>(b);
+}
+
+// Full evaluation at s that refreshes the older cache slot.
+template <int NV, int NF, int NL, int NCH>
+__device__ __forceinline__ CutRes full_step(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, int nv, int nf,
+                                            int nl, double s, int &lru) {
+  const int slot = lru;
+  CutRes c = cut_full(L, lane, nf, nl, s, slot);
+  const bool ok = c.nch <= kSlotChords && !c.err;
+  double blo = 0, bhi = 0;
+  if (ok) breakpoint_interval(L, lane, nv, nf, s, blo, bhi);
+  if (lane == 0) {
+    L.fs[slot].valid = ok ? 1 : 0;
+    L.fs[slot].bp_lo = blo;
+    L.fs[slot].bp_hi = bhi;
+  }
+  wave_sync();
+  lru ^= 1;
+  return c;
+}
+
+// One speculative round: segment j-1 evaluates node j of the next `levels`
+// bisection levels below the bracket (lo, hi) on a cached topology (nodes in
+// heap order; node j's isovalue is the midpoint the sequential bisection
+// reaches after the left/right choices spelled by the bits of j).  Results
+// go to L.sp_*; a node whose isovalue no cached slot covers is marked not ok.
+template <int C, int NV, int NF, int NL, int NCH>
+__device__ __forceinline__ void spec_round(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, double lo, double hi,
+                                           int nodes, double VP, double a) {
+  const int seg = lane / C, c = lane % C;
+  const int j = seg + 1;
+  if (j <= nodes) {
+    double l = lo, h = hi;
+    const int d = 31 - __clz(j);
+    for (int b = d - 1; b >= 0; --b) {
+      const double mid = l + (h - l) / 2.0;
+      if ((j >> b) & 1) l = mid; else h = mid;
+    }
+    const double s = l + (h - l) / 2.0;
+    int use = -1;
+    if (L.fs[0].valid && s > L.fs[0].bp_lo && s <= L.fs[0].bp_hi && L.fs[0].nch <= C) use = 0;
+    else if (L.fs[1].valid && s > L.fs[1].bp_lo && s <= L.fs[1].bp_hi && L.fs[1].nch <= C) use = 1;
+    if (use >= 0) {
+      const CutRes R = cut_fast<C>(L.fs[use], c, s);
+      if (c == 0) {
+        L.sp_s[j] = s;
+        L.sp_r[j] = R.V / VP - a;
+        L.sp_res[j][0] = R.V; L.sp_res[j][1] = R.S0; L.sp_res[j][2] = R.S1; L.sp_res[j][3] = R.S2;
+        L.sp_res[j][4] = R.A; L.sp_res[j][5] = R.c0; L.sp_res[j][6] = R.c1; L.sp_res[j][7] = R.c2;
+        L.sp_ok[j] = 1;
+      }
+    } else if (c == 0) {
+      L.sp_ok[j] = 0;
+    }
+  }
+  wave_sync();
+}
+
+template <class GM>
+__device__ __forceinline__ void store_end(GM &L, int lane, int side, const CutRes &c) {
+  if (lane == 0) {
+    double *e = L.end_res[side];
+    e[0] = c.V; e[1] = c.S0; e[2] = c.S1; e[3] = c.S2; e[4] = c.A; e[5] = c.c0; e[6] = c.c1; e[7] = c.c2;
+  }
+}
+
+// One cell per wavefront (block of 64 lanes).
+template <int NV, int NF, int NL, int NCH>
+__global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
+  constexpr int W = 64;
+  __shared__ GroupMem<kSlotChords, NV, NF, NL, NCH> L;
+  const int lane = threadIdx.x;
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells;
   const int64_t cap = p.out.cap;
   int64_t count = p.counts[0];
   if (count > cap) count = cap;
-  const int64_t stride = (int64_t)gridDim.x * G;
-  for (int64_t k = (int64_t)blockIdx.x * G + g; k < count; k += stride) {
+  for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
     const int P = p.mixed[k];
     const double a = p.alpha[P];
     double s_out = __builtin_nan(""), A_out = 0, d_out = 0, n0 = 0, n1 = 0, n2 = 0, ag = a;
@@ -341,7 +690,7 @@ __global__ __launch_bounds__(64) void recon_kernel(ReconParams p) {
     } else {
       const double xP0 = m.xc[P], xP1 = m.xc[N + P], xP2 = m.xc[2 * N + P];
       const double VP = m.V[P];
-      // ---- stage the polyhedron
+      // ---- stage the polyhedron (vertex field by inverse-distance weights)
       for (int i = lane; i < nv; i += W) {
         const int gv = m.cv_gid[v0 + i];
         L.X[0][i] = m.xyz[gv] - xP0;
@@ -357,7 +706,10 @@ __global__ __launch_bounds__(64) void recon_kernel(ReconParams p) {
         }
         L.phi[i] = ph;
       }
-      for (int i = lane; i < nl; i += W) L.lv[i] = m.cl_lv[l0 + i];
+      for (int i = lane; i < nl; i += W) {
+        L.lv[i] = m.cl_lv[l0 + i];
+        L.eid[i] = m.cl_eid[l0 + i];
+      }
       for (int f = lane; f < nf; f += W) {
         L.floff[f] = m.cf_loff[f0 + f];
         L.fsz[f] = m.cf_lsz[f0 + f];
@@ -410,18 +762,31 @@ __global__ __launch_bounds__(64) void recon_kernel(ReconParams p) {
         if (pmax - pmin <= 1e-12) have_field = false;
       }
       if (have_field) {
-        // face vertex means (fan centres of the planar faces) and face-mean
+        wave_sync();
+        // face vertex means (fan centres of the planar faces), face-mean
         // vertex values (pairing rule of faces with four or more crossings)
+        // and the reciprocal value difference of every loop position
         for (int f = lane; f < nf; f += W) {
           const int o = L.floff[f], n = L.fsz[f];
           double c0 = 0, c1 = 0, c2 = 0, fm = 0;
           for (int k2 = 0; k2 < n; ++k2) {
             const int v = L.lv[o + k2];
+            const int vn = L.lv[o + (k2 + 1 == n ? 0 : k2 + 1)];
             c0 += L.X[0][v]; c1 += L.X[1][v]; c2 += L.X[2][v];
             fm += L.phi[v];
+            L.inv[o + k2] = 1.0 / (L.phi[vn] - L.phi[v]);
           }
           L.cf[0][f] = c0 / n; L.cf[1][f] = c1 / n; L.cf[2][f] = c2 / n;
           L.fmean[f] = fm / n;
+          for (int k2 = 0; k2 < n; ++k2) {
+            L.pface[o + k2] = (uint8_t)f;
+            L.pk[o + k2] = (uint8_t)k2;
+            L.pnext[o + k2] = (uint16_t)(o + (k2 + 1 == n ? 0 : k2 + 1));
+          }
+        }
+        if (lane == 0) {
+          L.fs[0].valid = 0;
+          L.fs[1].valid = 0;
         }
         wave_sync();
         CutRes c;
@@ -430,60 +795,107 @@ __global__ __launch_bounds__(64) void recon_kernel(ReconParams p) {
         bool cut_ok = false;
         if (p.fixed_iso) {
           s = p.iso;
-          c = cut_eval<W>(L, lane, nf, s);
+          c = cut_full(L, lane, nf, nl, s, -1);
           it = 1;
           cut_ok = true;
         } else {
           double lo = pmin, hi = pmax, rlo = 1.0 - a, rhi = -a;
           const double tol = p.tol_rel * (a < 1.0 - a ? a : 1.0 - a);
-          CutRes clo, chi;
           bool have_lo = false, have_hi = false, done = false, collapsed = false;
+          int lru = 0;
           if (p.use_hint) {
             const double hl = p.hint_lo[k], hh = p.hint_hi[k];
             if (!isnan(hl) && !isnan(hh)) {
               double l2 = hl > pmin ? hl : pmin;
               double h2 = hh < pmax ? hh : pmax;
               if (l2 > h2) { l2 = pmin; h2 = pmax; }
-              const CutRes cl = cut_eval<W>(L, lane, nf, l2);
-              const CutRes chh = cut_eval<W>(L, lane, nf, h2);
+              const CutRes cl = full_step(L, lane, nv, nf, nl, l2, lru);
+              const CutRes chh = full_step(L, lane, nv, nf, nl, h2, lru);
               it += 2;
               const double rl = cl.V / VP - a, rh = chh.V / VP - a;
               if (fabs(rl) <= tol) { s = l2; c = cl; done = true; }
               else if (fabs(rh) <= tol) { s = h2; c = chh; done = true; }
               else if (rl > 0 && rh < 0) {
-                lo = l2; rlo = rl; clo = cl; have_lo = true;
-                hi = h2; rhi = rh; chi = chh; have_hi = true;
+                lo = l2; rlo = rl; have_lo = true;
+                hi = h2; rhi = rh; have_hi = true;
+                store_end(L, lane, 0, cl);
+                store_end(L, lane, 1, chh);
               } else if (rl <= 0) {
-                hi = l2; rhi = rl; chi = cl; have_hi = true;
+                hi = l2; rhi = rl; have_hi = true;
+                store_end(L, lane, 1, cl);
                 if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
               } else {
-                lo = h2; rlo = rh; clo = chh; have_lo = true;
+                lo = h2; rlo = rh; have_lo = true;
+                store_end(L, lane, 0, chh);
                 if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
               }
               if (done) cut_ok = true;
             }
           }
-          while (!done) {
+          while (!done && !collapsed) {
             if (it >= p.max_iter) { st = VOFPC_CELL_MAX_ITER; break; }
+            // speculative round on the cached topologies, when they fit
+            const int nmax = max(L.fs[0].valid ? L.fs[0].nch : 0, L.fs[1].valid ? L.fs[1].nch : 0);
+            int used = 0;
+            if (nmax > 0) {
+              int nodes;
+              if (nmax <= 8) { spec_round<8>(L, lane, lo, hi, 7, VP, a); nodes = 7; }
+              else if (nmax <= 16) { spec_round<16>(L, lane, lo, hi, 3, VP, a); nodes = 3; }
+              else { spec_round<32>(L, lane, lo, hi, 1, VP, a); nodes = 1; }
+              // replay the sequential bisection through the evaluated nodes
+              int j = 1;
+              while (j <= nodes && L.sp_ok[j]) {
+                if (it >= p.max_iter) { st = VOFPC_CELL_MAX_ITER; done = true; break; }
+                s = L.sp_s[j];
+                const double r = L.sp_r[j];
+                ++it;
+                ++used;
+                c.V = L.sp_res[j][0]; c.S0 = L.sp_res[j][1]; c.S1 = L.sp_res[j][2]; c.S2 = L.sp_res[j][3];
+                c.A = L.sp_res[j][4]; c.c0 = L.sp_res[j][5]; c.c1 = L.sp_res[j][6]; c.c2 = L.sp_res[j][7];
+                c.err = false;
+                cut_ok = true;
+                if (fabs(r) <= tol) { done = true; break; }
+                const int side = r > 0 ? 0 : 1;
+                if (r > 0) { lo = s; rlo = r; have_lo = true; }
+                else { hi = s; rhi = r; have_hi = true; }
+                if (lane < 8) L.end_res[side][lane] = L.sp_res[j][lane];
+                const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
+                if (hi - lo <= 2.0 * ulp_of(big)) { collapsed = true; break; }
+                j = 2 * j + (r > 0 ? 1 : 0);
+              }
+              wave_sync();
+            }
+            if (done || collapsed || used > 0) continue;
+            // no cached topology covers the next midpoint: full evaluation
             s = lo + (hi - lo) / 2.0;
-            c = cut_eval<W>(L, lane, nf, s);
+            c = full_step(L, lane, nv, nf, nl, s, lru);
             ++it;
             cut_ok = true;
             const double r = c.V / VP - a;
             if (fabs(r) <= tol) break;
-            if (r > 0) { lo = s; rlo = r; clo = c; have_lo = true; }
-            else { hi = s; rhi = r; chi = c; have_hi = true; }
+            if (r > 0) { lo = s; rlo = r; have_lo = true; }
+            else { hi = s; rhi = r; have_hi = true; }
+            if (lane == 0) {
+              double *e = L.end_res[r > 0 ? 0 : 1];
+              e[0] = c.V; e[1] = c.S0; e[2] = c.S1; e[3] = c.S2; e[4] = c.A; e[5] = c.c0; e[6] = c.c1; e[7] = c.c2;
+            }
             const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
             if (hi - lo <= 2.0 * ulp_of(big)) { collapsed = true; break; }
           }
           if (collapsed) {
+            wave_sync();
             const bool take_lo = fabs(rlo) <= fabs(rhi);
-            s = take_lo ? lo : hi;
-            if (take_lo ? have_lo : have_hi) {
-              c = take_lo ? clo : chi;
-            } else {
-              c = cut_eval<W>(L, lane, nf, s);
-              ++it;
+            const double se = take_lo ? lo : hi;
+            if (se != s) {
+              if (take_lo ? have_lo : have_hi) {
+                const double *e = L.end_res[take_lo ? 0 : 1];
+                c.V = e[0]; c.S0 = e[1]; c.S1 = e[2]; c.S2 = e[3]; c.A = e[4]; c.c0 = e[5]; c.c1 = e[6]; c.c2 = e[7];
+                c.err = false;
+              } else {
+                c = cut_full(L, lane, nf, nl, se, -1);
+                ++it;
+              }
+              s = se;
             }
             if (fabs(take_lo ? rlo : rhi) > 1e-10 && st != VOFPC_CELL_MAX_ITER) st = VOFPC_CELL_NO_ROOT;
           }
@@ -516,17 +928,15 @@ __global__ __launch_bounds__(64) void recon_kernel(ReconParams p) {
 }
 
 namespace {
-template <int W, int NV, int NF, int NL, int NCH>
+template <int NV, int NF, int NL, int NCH>
 vofpc_status launch_t(vofpc_ctx ctx, const ReconParams &p, int64_t n_cells) {
-  constexpr int G = 64 / W;
-  int64_t need = (n_cells + G - 1) / G;
   int blocks_per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, recon_kernel<W, NV, NF, NL, NCH>, 64, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, recon_kernel<NV, NF, NL, NCH>, 64, 0);
   if (e != hipSuccess || blocks_per_cu <= 0) blocks_per_cu = 4;
-  int64_t grid = (int64_t)ctx->n_cu * blocks_per_cu * 4;
-  if (grid > need) grid = need;
+  int64_t grid = (int64_t)ctx->n_cu * blocks_per_cu;
+  if (grid > n_cells) grid = n_cells;
   if (grid < 1) grid = 1;
-  recon_kernel<W, NV, NF, NL, NCH><<<(unsigned)grid, 64, 0, ctx->stream>>>(p);
+  recon_kernel<NV, NF, NL, NCH><<<(unsigned)grid, 64, 0, ctx->stream>>>(p);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;
 }
@@ -567,10 +977,10 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   const int64_t nf = M->max_nf, nv = M->max_nv, nl = M->max_loop, ne = M->max_ne, fv = M->max_fv;
   VOFPC_REQUIRE(fv <= 64, VOFPC_E_MESH, "reconstruct: faces with more than 64 vertices are not supported");
   const int64_t N = M->d.n_cells;
-  if (nv <= 16 && nf <= 8 && nl <= 48 && ne <= 24) return launch_t<8, 16, 8, 48, 24>(ctx, p, N);
-  if (nv <= 64 && nf <= 32 && nl <= 256 && ne <= 96) return launch_t<16, 64, 32, 256, 96>(ctx, p, N);
-  if (nv <= 128 && nf <= 64 && nl <= 512 && ne <= 192) return launch_t<32, 128, 64, 512, 192>(ctx, p, N);
-  return launch_t<64, 255, 255, 1536, 768>(ctx, p, N);
+  if (nv <= 16 && nf <= 8 && nl <= 48 && ne <= 24) return launch_t<16, 8, 48, 24>(ctx, p, N);
+  if (nv <= 48 && nf <= 32 && nl <= 128 && ne <= 64) return launch_t<48, 32, 128, 64>(ctx, p, N);
+  if (nv <= 64 && nf <= 64 && nl <= 256 && ne <= 128) return launch_t<64, 64, 256, 128>(ctx, p, N);
+  return launch_t<255, 255, 1536, 768>(ctx, p, N);
 }
 
 }  // namespace vofpc

@@ -56,6 +56,7 @@ struct DevMesh {
   const int32_t *cv_gid;
   const int64_t *cl_off;
   const uint8_t *cl_lv;
+  const uint16_t *cl_eid;  // local undirected edge id of each loop position
   // vertex -> cell incidence with normalised inverse-distance weights
   const int64_t *vc_off;
   const int32_t *vc_cell;
