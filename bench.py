@@ -89,6 +89,22 @@ def step_bytes(mesh, mixed, band, recon_b) -> int:
     return int(b)
 
 
+def measured_traffic():
+    """HBM bytes per reconstruction launch from the committed rocprofv3
+    counter summary, if the kernel source has not changed since; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "recon_kernel_voronoi195k_traffic.json")
+    src = os.path.join(ROOT, "paper_2604_14938_amd", "csrc", "recon.hip")
+    try:
+        info = json.load(open(path))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if info.get("recon_source_sha256") != cur:
+        return None
+    return float(info["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(wl, budget_s: float = 10.0) -> dict:
     import oracle
     om = oracle.OMesh(wl.mesh)
@@ -220,7 +236,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel_us": recon_ms * 1e3,
             "algorithmic_bytes": rb,
         },
