@@ -66,6 +66,7 @@ typedef int vofpc_status;
 typedef struct vofpc_ctx_s *vofpc_ctx;
 typedef struct vofpc_mesh_s *vofpc_mesh;
 typedef struct vofpc_graph_s *vofpc_graph;
+typedef struct vofpc_mlp_s *vofpc_mlp;
 
 /* Thread-local message of the last failed call on this thread ("" if none).
  * The pointer stays valid until the next vofpc call on the same thread. */
@@ -213,6 +214,59 @@ vofpc_status vofpc_mass_transfer(vofpc_ctx ctx, vofpc_mesh mesh, const double *a
                                  double h_lv, double *mdot, double *Qdot, double *mdot_cells,
                                  double *Qdot_cells);
 
+/* ---------------------------------------------------------- bracket network */
+/* A small network narrows the initial bisection bracket of every mixed cell;
+ * the reconstruction verifies the narrowed bracket with two volume
+ * evaluations and falls back to the rest of the plain bracket when it does
+ * not hold the root, so the network changes only how many evaluations a cell
+ * needs.  Architecture: 32 features -> 64 -> 64 -> 4 (tanh hidden layers),
+ * BF16 weights and activations on MFMA with FP32 accumulation, FP32 master
+ * weights updated by Adam.  Outputs per cell: u, the isovalue normalised to
+ * the cell's vertex-value range, (s - phi_min)/(phi_max - phi_min), and a
+ * 3-vector for the interface normal.  Loss: mean (u-u*)^2 + 0.1 mean|n-n*|^2.
+ * Parameters are one FP32 vector in the order W1[64][32], b1[64],
+ * W2[64][64], b2[64], W3[4][64], b3[4]. */
+
+/* Number of network parameters (6532). */
+int vofpc_mlp_param_count(void);
+/* Create a network on the context's device; `max_batch` bounds the rows of
+ * one training call (it sizes the gradient workspace).  Weights start at 0. */
+vofpc_status vofpc_mlp_create(vofpc_ctx ctx, int64_t max_batch, vofpc_mlp *out);
+/* Destroy a network.  NULL is accepted. */
+vofpc_status vofpc_mlp_destroy(vofpc_mlp mlp);
+/* Copy all parameters from HOST float[n] (n = vofpc_mlp_param_count()) and
+ * reset the Adam state.  Synchronises the context stream. */
+vofpc_status vofpc_mlp_set_params(vofpc_mlp mlp, const float *host, int64_t n);
+/* Copy the FP32 master parameters to HOST float[n].  Synchronises. */
+vofpc_status vofpc_mlp_get_params(vofpc_mlp mlp, float *host, int64_t n);
+/* Forward pass: X DEVICE float[n][32] -> Y DEVICE float[n][4]. */
+vofpc_status vofpc_mlp_forward(vofpc_ctx ctx, vofpc_mlp mlp, const float *X, int64_t n, float *Y);
+/* Loss and gradient of the mean loss over n rows of X with targets T DEVICE
+ * float[n][4] (u*, n*): grad DEVICE float[param_count], loss DEVICE float[1]
+ * (either may be NULL).  Deterministic (fixed-order reduction). */
+vofpc_status vofpc_mlp_gradient(vofpc_ctx ctx, vofpc_mlp mlp, const float *X, const float *T, int64_t n,
+                                float *grad, float *loss);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the gradient of
+ * n rows; loss DEVICE float[1] receives the pre-step loss (may be NULL). */
+vofpc_status vofpc_mlp_train_step(vofpc_ctx ctx, vofpc_mlp mlp, const float *X, const float *T, int64_t n,
+                                  float lr, float *loss);
+/* Network inputs of every listed mixed cell (entry k = cell mixed_idx[k]):
+ * features DEVICE float[cap][32], phi_range DEVICE double[cap][2] =
+ * (phi_min, phi_max - phi_min) of the cell's vertex field (the vertex rule of
+ * opts, which may be NULL for the defaults).  Definitions: 0 alpha_P; 1-7
+ * vertex-value quantiles q = 1/8..7/8 normalised to the range; 8 normalised
+ * mean; 9 range; 10-12 sum A_f (alpha_Q-alpha_P) n_f / sum A_f; 13-18 the
+ * same with n_f n_f^T (xx yy zz xy xz yz); 19-24 sum A_f n_f n_f^T / sum A_f;
+ * 25 faces/32; 26-28 mean, min, max of the neighbours' alpha; 29-31 zero. */
+vofpc_status vofpc_features(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed_idx,
+                            const int32_t *counts, const vofpc_recon_opts *opts, float *features,
+                            double *phi_range, int64_t cap);
+/* Narrowed brackets from the network: hint = phi_min + clamp(u,0,1) W +- delta
+ * with delta = delta_scale W (DEVICE double[cap] each; NaN where W = 0). */
+vofpc_status vofpc_mlp_bracket(vofpc_ctx ctx, vofpc_mlp mlp, const float *features, const double *phi_range,
+                               const int32_t *counts, int64_t cap, double delta_scale, double *hint_lo,
+                               double *hint_hi);
+
 /* ------------------------------------------------------------- whole step */
 /* Every buffer of one step: compaction, reconstruction, band gradient and
  * mass transfer, with the meaning given above.  All pointers DEVICE. */
@@ -220,12 +274,19 @@ typedef struct {
   const double *alpha, *T, *T_bface;
   double T_sat, k_l, k_v, h_lv;
   vofpc_recon_opts opts;
-  const double *hint_lo, *hint_hi; /* with opts.bracket == VOFPC_BRACKET_HINT */
+  double *hint_lo, *hint_hi; /* read with opts.bracket == VOFPC_BRACKET_HINT; written by the learned form */
   int32_t *mixed_idx, *band_idx, *counts;
   vofpc_interface itf;
   double *gradT;          /* [3][n_cells], written on the band */
   int32_t *grad_status;   /* optional [n_cells] */
   double *mdot, *Qdot;    /* [cap] over the mixed list */
+  /* learned form: with mlp set, the step computes features into `features`
+   * (float[cap][32]) and `phi_range` (double[cap][2]), writes the network's
+   * brackets into hint_lo/hint_hi and reconstructs from them */
+  vofpc_mlp mlp;
+  double delta_scale;
+  float *features;
+  double *phi_range;
 } vofpc_step_args;
 
 /* Issue one step on the context stream. */

@@ -120,7 +120,21 @@ static vofpc_status issue_step(vofpc_ctx ctx, vofpc_mesh mesh, const vofpc_step_
   VOFPC_REQUIRE(a, VOFPC_E_INVALID_ARG, "step: null arguments");
   vofpc_status s = launch_compact(ctx, mesh, a->alpha, a->opts.eps_mixed, a->mixed_idx, a->band_idx, a->counts);
   if (s) return s;
-  s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, a->hint_lo, a->hint_hi, &a->itf);
+  if (a->mlp) {
+    VOFPC_REQUIRE(a->features && a->phi_range && a->hint_lo && a->hint_hi, VOFPC_E_INVALID_ARG,
+                  "step: the learned form needs features, phi_range, hint_lo and hint_hi buffers");
+    s = launch_features(ctx, mesh, a->alpha, a->mixed_idx, a->counts, a->itf.cap, &a->opts, a->features,
+                        a->phi_range);
+    if (s) return s;
+    s = launch_bracket(ctx, a->mlp, a->features, a->phi_range, a->counts, a->itf.cap, a->delta_scale, a->hint_lo,
+                       a->hint_hi);
+    if (s) return s;
+    vofpc_recon_opts o = a->opts;
+    o.bracket = VOFPC_BRACKET_HINT;
+    s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &o, a->hint_lo, a->hint_hi, &a->itf);
+  } else {
+    s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, a->hint_lo, a->hint_hi, &a->itf);
+  }
   if (s) return s;
   s = launch_grad(ctx, mesh, a->T, a->T_bface, a->T_sat, a->alpha, a->band_idx, a->counts, VOFPC_SCOPE_BAND,
                   VOFPC_GRAD_MODIFIED, a->gradT, a->grad_status);

@@ -109,6 +109,11 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh m, const double *alpha
 vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh m, const double *T, const double *Tb, double T_sat,
                          const double *alpha, const int32_t *band, const int32_t *counts, int32_t scope,
                          int32_t variant, double *grad, int32_t *status);
+vofpc_status launch_features(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed,
+                             const int32_t *counts, int64_t cap, const vofpc_recon_opts *o, float *feat,
+                             double *prange);
+vofpc_status launch_bracket(vofpc_ctx ctx, vofpc_mlp M, const float *feat, const double *prange,
+                            const int32_t *counts, int64_t cap, double ksig, double *hlo, double *hhi);
 vofpc_status launch_mass_transfer(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, const int32_t *mixed,
                                   const int32_t *counts, const vofpc_interface *itf, const double *gradT,
                                   const double *gl, const double *gv, double k_l, double k_v, double h_lv,

@@ -16,7 +16,7 @@ class PathRun:
     """Device-resident inputs and buffers of one workload, ready to step."""
 
     def __init__(self, wl, device: int = 0, opts: V.ReconOpts | None = None, ctx: V.Context | None = None,
-                 hint_lo=None, hint_hi=None):
+                 hint_lo=None, hint_hi=None, mlp: "V.Mlp | None" = None, delta_scale: float = 0.0):
         self.dev = torch.device("cuda", device)
         # a stream of its own (default priority): graph capture needs a
         # non-null stream
@@ -27,7 +27,8 @@ class PathRun:
         self.T = torch.as_tensor(np.ascontiguousarray(wl.T), **f64)
         self.Tb = torch.as_tensor(np.ascontiguousarray(wl.T_bface), **f64)
         self.buf = V.StepBuffers(self.ctx, self.mesh, self.alpha, self.T, self.Tb, wl.T_sat, wl.k_l, wl.k_v,
-                                 wl.h_lv, opts=opts, hint_lo=hint_lo, hint_hi=hint_hi)
+                                 wl.h_lv, opts=opts, hint_lo=hint_lo, hint_hi=hint_hi, mlp=mlp,
+                                 delta_scale=delta_scale)
         torch.cuda.synchronize(self.dev)   # inputs were written on torch's stream
         self.graph = None
 

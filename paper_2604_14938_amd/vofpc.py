@@ -55,7 +55,8 @@ class CInterface(ctypes.Structure):
 class StepArgs(ctypes.Structure):
     _fields_ = [("alpha", P), ("T", P), ("T_bface", P), ("T_sat", D), ("k_l", D), ("k_v", D), ("h_lv", D),
                 ("opts", ReconOpts), ("hint_lo", P), ("hint_hi", P), ("mixed_idx", P), ("band_idx", P),
-                ("counts", P), ("itf", CInterface), ("gradT", P), ("grad_status", P), ("mdot", P), ("Qdot", P)]
+                ("counts", P), ("itf", CInterface), ("gradT", P), ("grad_status", P), ("mdot", P), ("Qdot", P),
+                ("mlp", P), ("delta_scale", D), ("features", P), ("phi_range", P)]
 
 
 def _load():
@@ -81,6 +82,16 @@ def _load():
         "vofpc_graph_create": ([P, P, P, P], ctypes.c_int),
         "vofpc_graph_launch": ([P], ctypes.c_int),
         "vofpc_graph_destroy": ([P], ctypes.c_int),
+        "vofpc_mlp_param_count": ([], ctypes.c_int),
+        "vofpc_mlp_create": ([P, I64, P], ctypes.c_int),
+        "vofpc_mlp_destroy": ([P], ctypes.c_int),
+        "vofpc_mlp_set_params": ([P, P, I64], ctypes.c_int),
+        "vofpc_mlp_get_params": ([P, P, I64], ctypes.c_int),
+        "vofpc_mlp_forward": ([P, P, P, I64, P], ctypes.c_int),
+        "vofpc_mlp_gradient": ([P, P, P, P, I64, P, P], ctypes.c_int),
+        "vofpc_mlp_train_step": ([P, P, P, P, I64, ctypes.c_float, P], ctypes.c_int),
+        "vofpc_features": ([P, P, P, P, P, P, P, P, I64], ctypes.c_int),
+        "vofpc_mlp_bracket": ([P, P, P, P, P, I64, D, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -258,11 +269,67 @@ def mass_transfer(ctx: Context, mesh: Mesh, alpha, mixed_idx, counts, itf: Inter
                                    _ptr(mdot), _ptr(Qdot), _ptr(mdot_cells), _ptr(Qdot_cells)), "vofpc_mass_transfer")
 
 
+class Mlp:
+    """The bracket network on a context's device."""
+
+    def __init__(self, ctx: Context, max_batch: int = 1 << 16):
+        self.ctx = ctx
+        self.n_params = int(lib.vofpc_mlp_param_count())
+        h = P()
+        _check(lib.vofpc_mlp_create(ctx.h, int(max_batch), ctypes.byref(h)), "vofpc_mlp_create")
+        self.h = h
+        self.max_batch = int(max_batch)
+
+    def set_params(self, v: np.ndarray) -> None:
+        v = np.ascontiguousarray(v, np.float32)
+        _check(lib.vofpc_mlp_set_params(self.h, v.ctypes.data, v.size), "vofpc_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        v = np.empty(self.n_params, np.float32)
+        _check(lib.vofpc_mlp_get_params(self.h, v.ctypes.data, v.size), "vofpc_mlp_get_params")
+        return v
+
+    def forward(self, X, Y) -> None:
+        _check(lib.vofpc_mlp_forward(self.ctx.h, self.h, _ptr(X), X.shape[0], _ptr(Y)), "vofpc_mlp_forward")
+
+    def gradient(self, X, T, grad=None, loss=None) -> None:
+        _check(lib.vofpc_mlp_gradient(self.ctx.h, self.h, _ptr(X), _ptr(T), X.shape[0], _ptr(grad), _ptr(loss)),
+               "vofpc_mlp_gradient")
+
+    def train_step(self, X, T, lr: float, loss=None) -> None:
+        _check(lib.vofpc_mlp_train_step(self.ctx.h, self.h, _ptr(X), _ptr(T), X.shape[0], float(lr), _ptr(loss)),
+               "vofpc_mlp_train_step")
+
+    def bracket(self, features, phi_range, counts, cap, delta_scale, hint_lo, hint_hi) -> None:
+        _check(lib.vofpc_mlp_bracket(self.ctx.h, self.h, _ptr(features), _ptr(phi_range), _ptr(counts), int(cap),
+                                     float(delta_scale), _ptr(hint_lo), _ptr(hint_hi)), "vofpc_mlp_bracket")
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            lib.vofpc_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def features(ctx: Context, mesh: Mesh, alpha, mixed_idx, counts, feat, phi_range, opts: ReconOpts | None = None):
+    _check(lib.vofpc_features(ctx.h, mesh.h, _ptr(alpha), _ptr(mixed_idx), _ptr(counts),
+                              ctypes.byref(opts) if opts is not None else None, _ptr(feat), _ptr(phi_range),
+                              feat.shape[0]), "vofpc_features")
+
+
 class StepBuffers:
-    """Every device buffer of one step, sized for a mesh (capacity n_cells)."""
+    """Every device buffer of one step, sized for a mesh (capacity n_cells).
+    With `mlp` set the step runs the learned form (features, network bracket,
+    reconstruction from the bracket)."""
 
     def __init__(self, ctx: Context, mesh: Mesh, alpha, T, T_bface, T_sat, k_l, k_v, h_lv,
-                 opts: ReconOpts | None = None, hint_lo=None, hint_hi=None):
+                 opts: ReconOpts | None = None, hint_lo=None, hint_hi=None, mlp: "Mlp | None" = None,
+                 delta_scale: float = 0.0):
         dev = ctx.device
         N = mesh.n_cells
         self.alpha, self.T, self.T_bface = alpha, T, T_bface
@@ -278,6 +345,15 @@ class StepBuffers:
         self.grad_status = torch.zeros(N, **i32)
         self.mdot = torch.zeros(N, dtype=torch.float64, device=dev)
         self.Qdot = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.mlp = mlp
+        self.delta_scale = float(delta_scale)
+        self.features = self.phi_range = None
+        if mlp is not None:
+            self.features = torch.zeros(N, 32, dtype=torch.float32, device=dev)
+            self.phi_range = torch.zeros(N, 2, dtype=torch.float64, device=dev)
+            if self.hint_lo is None:
+                self.hint_lo = torch.zeros(N, dtype=torch.float64, device=dev)
+                self.hint_hi = torch.zeros(N, dtype=torch.float64, device=dev)
 
     def args(self) -> StepArgs:
         a = StepArgs()
@@ -289,6 +365,9 @@ class StepBuffers:
         a.itf = self.itf.c()
         a.gradT, a.grad_status = _ptr(self.gradT), _ptr(self.grad_status)
         a.mdot, a.Qdot = _ptr(self.mdot), _ptr(self.Qdot)
+        a.mlp = self.mlp.h if self.mlp is not None else None
+        a.delta_scale = self.delta_scale
+        a.features, a.phi_range = _ptr(self.features), _ptr(self.phi_range)
         return a
 
 

@@ -10,7 +10,8 @@
  * Region kinds:
  *   0  vapour inside any of the listed spheres (x,y,z,r), liquid elsewhere;
  *   1  annular film: liquid where sqrt(x^2+z^2) > R - delta(y), with
- *      delta(y) = d0 (1 + amp sin(2 pi waves y / L)); params (R,d0,amp,waves,L).
+ *      delta(y) = d0 (1 + amp sin(2 pi waves y / L)); params (R,d0,amp,waves,L);
+ *   2  half-space: liquid where n.x >= c; params (nx, ny, nz, c).
  */
 #include <math.h>
 #include <stdint.h>
@@ -24,6 +25,7 @@ static int liquid_at(int kind, const double *x, int nsph, const double *sph,
     }
     return 1;
   }
+  if (kind == 2) return prm[0] * x[0] + prm[1] * x[1] + prm[2] * x[2] >= prm[3];
   double r = sqrt(x[0] * x[0] + x[2] * x[2]);
   double delta = prm[1] * (1.0 + prm[2] * sin(2.0 * M_PI * prm[3] * x[1] / prm[4]));
   return r > prm[0] - delta;

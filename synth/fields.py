@@ -172,6 +172,27 @@ def film_alpha(mesh: Mesh, R: float, d0: float, amp: float, waves: float, L: flo
     return alpha
 
 
+def plane_alpha(mesh: Mesh, normal, c: float, K: int = 16) -> np.ndarray:
+    """Liquid where n.x >= c (a planar interface), by sub-point counting in the
+    cells the plane crosses."""
+    n = np.asarray(normal, float)
+    n = n / np.linalg.norm(n)
+    N = mesh.n_cells
+    cells_v, verts_v = _cell_vertices(mesh)
+    d = n @ mesh.vert_xyz[:, verts_v] - c
+    lo = np.full(N, np.inf)
+    hi = np.full(N, -np.inf)
+    np.minimum.at(lo, cells_v, d)
+    np.maximum.at(hi, cells_v, d)
+    alpha = (lo >= 0).astype(float)
+    cut = np.nonzero((lo < 0) & (hi > 0))[0]
+    if len(cut):
+        bbox = mesh.cell_bbox()
+        alpha[cut] = subsample(mesh, cut, bbox, 2, np.zeros(len(cut) + 1, np.int64), np.zeros((1, 4)),
+                               [n[0], n[1], n[2], c, 0.0], K)
+    return alpha
+
+
 # ---------------------------------------------------------------- temperatures
 def radial_linear_T(points: np.ndarray, c, r0: float, slope: float, T_sat: float) -> np.ndarray:
     """T_sat inside |x-c| <= r0, T_sat + slope (|x-c| - r0) outside."""
