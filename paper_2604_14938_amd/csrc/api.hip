@@ -36,6 +36,19 @@ extern "C" vofpc_status vofpc_ctx_create(int device, void *stream, vofpc_ctx *ou
   c->device = device;
   c->stream = (hipStream_t)stream;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (hipMalloc(&c->queue, 2 * sizeof(int)) != hipSuccess) {
+    delete c;
+    set_error("ctx_create: hipMalloc of the work-queue counters failed");
+    return VOFPC_E_OOM;
+  }
+  hipError_t e = hipMemset(c->queue, 0, 2 * sizeof(int));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(c->queue);
+    delete c;
+    set_error(std::string("ctx_create: ") + hipGetErrorString(e));
+    return VOFPC_E_HIP;
+  }
   *out = c;
   return VOFPC_OK;
 }
@@ -49,6 +62,10 @@ extern "C" vofpc_status vofpc_ctx_set_stream(vofpc_ctx ctx, void *stream) {
 
 extern "C" vofpc_status vofpc_ctx_destroy(vofpc_ctx ctx) {
   clear_error();
+  if (ctx && ctx->queue) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->queue);
+  }
   delete ctx;
   return VOFPC_OK;
 }

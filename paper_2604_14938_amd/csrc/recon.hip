@@ -118,6 +118,14 @@ __device__ __forceinline__ double gmax(double v) {
   if (W >= 64) v = fmax(v, __shfl_xor(v, 32, W));
   return v;
 }
+// value of lane l (uniform l) on every lane
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  int2 t = __builtin_bit_cast(int2, v);
+  t.x = __builtin_amdgcn_readlane(t.x, l);
+  t.y = __builtin_amdgcn_readlane(t.y, l);
+  return __builtin_bit_cast(double, t);
+}
+
 // exclusive prefix sum over the group
 template <int W>
 __device__ __forceinline__ int gscan_excl(int v, int lane) {
@@ -172,11 +180,10 @@ struct GroupMem {
   uint16_t jmp[2][NCH];
   uint16_t floff[NF];
   uint16_t eid[NL];
-  double sp_s[8], sp_r[8], sp_res[8][8];  // speculative round: node isovalue, residual, cut
+  double sp_s[8];                         // isovalues of a parallel round
   double end_res[2][8];                   // cut at the current bracket ends (lo, hi)
   double ept[3][NCH];                     // crossing point of each cut edge (by edge id)
   uint64_t fex[NF], fen[NF];              // exit / entry bit masks of each face
-  int sp_ok[8];
   uint16_t pnext[NL];                     // next loop position of the same face
   uint8_t pface[NL];                      // face of a loop position
   uint8_t pk[NL];                         // index of the position within its face
@@ -199,6 +206,7 @@ struct ReconParams {
   const double *hint_lo, *hint_hi;
   double eps, tol_rel, iso;
   int max_iter, vertex_mode, fixed_iso, use_hint;
+  int *queue;   // claim counter of the cells beyond the first grid-size ones
   vofpc_interface out;
 };
 
@@ -493,9 +501,22 @@ __device__ CutRes cut_full(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, 
       p0 = L.ps[0][lane]; p1 = L.ps[1][lane]; p2 = L.ps[2][lane];
       next = L.by_entry[L.ch_xe[lane]];
     }
-    const int lab = labels_reg<W>(lane, valid, next, nch);
-    const int nloops = gsum_i<W>((valid && lab == lane) ? 1 : 0);
-    loops_reg<W>(lane, valid, p0, p1, p2, next, lab, nloops, R);
+    int lab, nloops;
+    if (nch <= 16) {
+      // chords in the first row: row-local shuffles and DPP sums, then the
+      // sums of lane 0 go to the whole wave
+      lab = labels_reg<16>(lane, valid, next, nch);
+      nloops = gsum_i<16>((valid && lab == lane) ? 1 : 0);
+      loops_reg<16>(lane, valid, p0, p1, p2, next, lab, nloops, R);
+      nloops = __builtin_amdgcn_readfirstlane(nloops);
+      R.V = readlane_d(R.V, 0); R.S0 = readlane_d(R.S0, 0); R.S1 = readlane_d(R.S1, 0);
+      R.S2 = readlane_d(R.S2, 0); R.A = readlane_d(R.A, 0); R.c0 = readlane_d(R.c0, 0);
+      R.c1 = readlane_d(R.c1, 0); R.c2 = readlane_d(R.c2, 0);
+    } else {
+      lab = labels_reg<W>(lane, valid, next, nch);
+      nloops = gsum_i<W>((valid && lab == lane) ? 1 : 0);
+      loops_reg<W>(lane, valid, p0, p1, p2, next, lab, nloops, R);
+    }
     if (build_slot >= 0 && nch <= kSlotChords) {
       FastSlot<kSlotChords> &F = L.fs[build_slot];
       if (lane == 0) {
@@ -614,41 +635,27 @@ __device__ __forceinline__ CutRes full_step(GroupMem<kSlotChords, NV, NF, NL, NC
   return c;
 }
 
-// One speculative round: segment j-1 evaluates node j of the next `levels`
-// bisection levels below the bracket (lo, hi) on a cached topology (nodes in
-// heap order; node j's isovalue is the midpoint the sequential bisection
-// reaches after the left/right choices spelled by the bits of j).  Results
-// go to L.sp_*; a node whose isovalue no cached slot covers is marked not ok.
+// Evaluate the isovalues L.sp_s[0..npts) on cached slot u, C lanes per
+// isovalue (segment j takes point j).  The first lane of each evaluating
+// segment returns true with the point and its cut sums.
 template <int C, int NV, int NF, int NL, int NCH>
-__device__ __forceinline__ void spec_round(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, double lo, double hi,
-                                           int nodes, double VP, double a) {
+__device__ __forceinline__ bool fast_round(const GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, int u, int npts,
+                                           double &x, CutRes &R) {
   const int seg = lane / C, c = lane % C;
-  const int j = seg + 1;
-  if (j <= nodes) {
-    double l = lo, h = hi;
-    const int d = 31 - __clz(j);
-    for (int b = d - 1; b >= 0; --b) {
-      const double mid = l + (h - l) / 2.0;
-      if ((j >> b) & 1) l = mid; else h = mid;
-    }
-    const double s = l + (h - l) / 2.0;
-    int use = -1;
-    if (L.fs[0].valid && s > L.fs[0].bp_lo && s <= L.fs[0].bp_hi && L.fs[0].nch <= C) use = 0;
-    else if (L.fs[1].valid && s > L.fs[1].bp_lo && s <= L.fs[1].bp_hi && L.fs[1].nch <= C) use = 1;
-    if (use >= 0) {
-      const CutRes R = cut_fast<C>(L.fs[use], c, s);
-      if (c == 0) {
-        L.sp_s[j] = s;
-        L.sp_r[j] = R.V / VP - a;
-        L.sp_res[j][0] = R.V; L.sp_res[j][1] = R.S0; L.sp_res[j][2] = R.S1; L.sp_res[j][3] = R.S2;
-        L.sp_res[j][4] = R.A; L.sp_res[j][5] = R.c0; L.sp_res[j][6] = R.c1; L.sp_res[j][7] = R.c2;
-        L.sp_ok[j] = 1;
-      }
-    } else if (c == 0) {
-      L.sp_ok[j] = 0;
-    }
+  x = 0.0;
+  R.V = R.S0 = R.S1 = R.S2 = R.A = R.c0 = R.c1 = R.c2 = 0.0;
+  if (seg < npts) {
+    x = L.sp_s[seg];
+    R = cut_fast<C>(L.fs[u], c, x);
   }
-  wave_sync();
+  return seg < npts && c == 0;
+}
+
+// Root of the inverse quadratic through three (isovalue, residual) points;
+// NaN or infinite when two residuals coincide.
+__device__ __forceinline__ double iqi(double x0, double f0, double x1, double f1, double x2, double f2) {
+  return x0 * f1 * f2 / ((f0 - f1) * (f0 - f2)) + x1 * f0 * f2 / ((f1 - f0) * (f1 - f2)) +
+         x2 * f0 * f1 / ((f2 - f0) * (f2 - f1));
 }
 
 template <class GM>
@@ -670,7 +677,10 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
   const int64_t cap = p.out.cap;
   int64_t count = p.counts[0];
   if (count > cap) count = cap;
-  for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
+  // cells go to blocks through a counter: block b starts with cell b and
+  // then claims the next unclaimed one, so blocks that meet cheap cells do
+  // more of them
+  for (int64_t k = blockIdx.x; k < count;) {
     const int P = p.mixed[k];
     const double a = p.alpha[P];
     double s_out = __builtin_nan(""), A_out = 0, d_out = 0, n0 = 0, n1 = 0, n2 = 0, ag = a;
@@ -801,104 +811,207 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
         } else {
           double lo = pmin, hi = pmax, rlo = 1.0 - a, rhi = -a;
           const double tol = p.tol_rel * (a < 1.0 - a ? a : 1.0 - a);
-          bool have_lo = false, have_hi = false, done = false, collapsed = false;
-          int lru = 0;
+          bool have_lo = false, have_hi = false, collapsed = false;
+          double s3 = 0, r3 = 0;   // third point for inverse quadratic interpolation
+          bool have3 = false;
+          int kept = 0;            // > 0: lo kept that many updates in a row, < 0: hi
+          bool slow = false;       // the last update did not halve the bracket
+          int lru = 0, probe = -1;
+          // learned bracket: its centre is the first isovalue tried; the
+          // status records whether the root fell outside it
+          bool hint = false, first = true;
+          double hl = 0, hh = 0;
           if (p.use_hint) {
-            const double hl = p.hint_lo[k], hh = p.hint_hi[k];
+            hl = p.hint_lo[k];
+            hh = p.hint_hi[k];
             if (!isnan(hl) && !isnan(hh)) {
-              double l2 = hl > pmin ? hl : pmin;
-              double h2 = hh < pmax ? hh : pmax;
-              if (l2 > h2) { l2 = pmin; h2 = pmax; }
-              const CutRes cl = full_step(L, lane, nv, nf, nl, l2, lru);
-              const CutRes chh = full_step(L, lane, nv, nf, nl, h2, lru);
-              it += 2;
-              const double rl = cl.V / VP - a, rh = chh.V / VP - a;
-              if (fabs(rl) <= tol) { s = l2; c = cl; done = true; }
-              else if (fabs(rh) <= tol) { s = h2; c = chh; done = true; }
-              else if (rl > 0 && rh < 0) {
-                lo = l2; rlo = rl; have_lo = true;
-                hi = h2; rhi = rh; have_hi = true;
-                store_end(L, lane, 0, cl);
-                store_end(L, lane, 1, chh);
-              } else if (rl <= 0) {
-                hi = l2; rhi = rl; have_hi = true;
-                store_end(L, lane, 1, cl);
-                if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
-              } else {
-                lo = h2; rlo = rh; have_lo = true;
-                store_end(L, lane, 0, chh);
-                if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
-              }
-              if (done) cut_ok = true;
+              hl = hl > pmin ? hl : pmin;
+              hh = hh < pmax ? hh : pmax;
+              hint = hl <= hh;
             }
           }
-          while (!done && !collapsed) {
-            if (it >= p.max_iter) { st = VOFPC_CELL_MAX_ITER; break; }
-            // speculative round on the cached topologies, when they fit
-            const int nmax = max(L.fs[0].valid ? L.fs[0].nch : 0, L.fs[1].valid ? L.fs[1].nch : 0);
-            int used = 0;
-            if (nmax > 0) {
-              int nodes;
-              if (nmax <= 8) { spec_round<8>(L, lane, lo, hi, 7, VP, a); nodes = 7; }
-              else if (nmax <= 16) { spec_round<16>(L, lane, lo, hi, 3, VP, a); nodes = 3; }
-              else { spec_round<32>(L, lane, lo, hi, 1, VP, a); nodes = 1; }
-              // replay the sequential bisection through the evaluated nodes
-              int j = 1;
-              while (j <= nodes && L.sp_ok[j]) {
-                if (it >= p.max_iter) { st = VOFPC_CELL_MAX_ITER; done = true; break; }
-                s = L.sp_s[j];
-                const double r = L.sp_r[j];
-                ++it;
-                ++used;
-                c.V = L.sp_res[j][0]; c.S0 = L.sp_res[j][1]; c.S1 = L.sp_res[j][2]; c.S2 = L.sp_res[j][3];
-                c.A = L.sp_res[j][4]; c.c0 = L.sp_res[j][5]; c.c1 = L.sp_res[j][6]; c.c2 = L.sp_res[j][7];
-                c.err = false;
-                cut_ok = true;
-                if (fabs(r) <= tol) { done = true; break; }
-                const int side = r > 0 ? 0 : 1;
-                if (r > 0) { lo = s; rlo = r; have_lo = true; }
-                else { hi = s; rhi = r; have_hi = true; }
-                if (lane < 8) L.end_res[side][lane] = L.sp_res[j][lane];
-                const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
-                if (hi - lo <= 2.0 * ulp_of(big)) { collapsed = true; break; }
-                j = 2 * j + (r > 0 ? 1 : 0);
-              }
-              wave_sync();
-            }
-            if (done || collapsed || used > 0) continue;
-            // no cached topology covers the next midpoint: full evaluation
-            s = lo + (hi - lo) / 2.0;
-            c = full_step(L, lane, nv, nf, nl, s, lru);
-            ++it;
-            cut_ok = true;
-            const double r = c.V / VP - a;
-            if (fabs(r) <= tol) break;
-            if (r > 0) { lo = s; rlo = r; have_lo = true; }
-            else { hi = s; rhi = r; have_hi = true; }
-            if (lane == 0) {
-              double *e = L.end_res[r > 0 ? 0 : 1];
-              e[0] = c.V; e[1] = c.S0; e[2] = c.S1; e[3] = c.S2; e[4] = c.A; e[5] = c.c0; e[6] = c.c1; e[7] = c.c2;
-            }
+          while (true) {
             const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
             if (hi - lo <= 2.0 * ulp_of(big)) { collapsed = true; break; }
+            if (it >= p.max_iter) { st = VOFPC_CELL_MAX_ITER; break; }
+            const double w0 = hi - lo;
+            // next estimate: regula falsi with the Illinois weight on an end
+            // kept twice, inverse quadratic interpolation when it stays
+            // inside the bracket, a bisection step after a slow update
+            const double fl = kept >= 2 ? 0.5 * rlo : rlo, fh = kept <= -2 ? 0.5 * rhi : rhi;
+            double se = lo + w0 * (fl / (fl - fh));
+            double d = 0.125 * w0;
+            if (have3 && kept > -2 && kept < 2) {
+              const double q = iqi(lo, rlo, hi, rhi, s3, r3);
+              if (q > lo && q < hi) {
+                d = 4.0 * fabs(q - se);
+                se = q;
+              }
+            }
+            if (first && hint) se = 0.5 * (hl + hh);
+            if (slow || !(se > lo && se < hi)) {
+              se = lo + w0 / 2.0;
+              d = 0.125 * w0;
+            }
+            first = false;
+            if (!(se > lo && se < hi)) { collapsed = true; break; }
+            const double du = 8.0 * ulp_of(se);
+            d = d > du ? d : du;
+            d = d < 0.5 * w0 ? d : 0.5 * w0;
+            // a slot just built is probed at once; otherwise the slot that
+            // covers the estimate, if any
+            int u = probe;
+            probe = -1;
+            if (u < 0) {
+              if (L.fs[0].valid && se > L.fs[0].bp_lo && se <= L.fs[0].bp_hi) u = 0;
+              else if (L.fs[1].valid && se > L.fs[1].bp_lo && se <= L.fs[1].bp_hi) u = 1;
+            }
+            if (u < 0) {
+              // no cached topology covers the estimate: full evaluation
+              const int slot = lru;
+              const CutRes cf = full_step(L, lane, nv, nf, nl, se, lru);
+              ++it;
+              const double r = cf.V / VP - a;
+              if (fabs(r) <= tol) {
+                s = se; c = cf; cut_ok = true;
+                break;
+              }
+              if (r > 0) {
+                s3 = lo; r3 = rlo;
+                lo = se; rlo = r; have_lo = true;
+                store_end(L, lane, 0, cf);
+                kept = kept <= 0 ? kept - 1 : -1;
+              } else {
+                s3 = hi; r3 = rhi;
+                hi = se; rhi = r; have_hi = true;
+                store_end(L, lane, 1, cf);
+                kept = kept >= 0 ? kept + 1 : 1;
+              }
+              have3 = true;
+              slow = (hi - lo) > 0.5 * w0;
+              if (L.fs[slot].valid) probe = slot;
+              wave_sync();
+              continue;
+            }
+            // parallel round on the cached topology: the estimate, the ends
+            // of the topology interval when the bracket reaches past them,
+            // a ladder around the estimate and the bracket midpoint
+            const double blo = L.fs[u].bp_lo, bhi = L.fs[u].bp_hi;
+            const int nch = L.fs[u].nch;
+            const int C = nch <= 8 ? 8 : (nch <= 16 ? 16 : 32);
+            const int K = 64 / C;
+            // candidates in lanes 0..7 (estimate, left and right interval
+            // ends, ladder -d/16, +d/16, -d, +d, midpoint); the first K that
+            // lie inside both the bracket and the interval are evaluated
+            double xc;
+            bool okc;
+            {
+              const double tl = lane == 3 ? -0.0625 : lane == 4 ? 0.0625 : lane == 5 ? -1.0 : lane == 6 ? 1.0 : 0.0;
+              xc = se + tl * d;
+              if (lane == 1) xc = nextafter(blo, __builtin_inf());
+              if (lane == 2) xc = bhi;
+              if (lane == 7) xc = lo + w0 / 2.0;
+              okc = lane < 8 && xc > lo && xc < hi && xc > blo && xc <= bhi && (lane != 1 || lo <= blo) &&
+                    (lane != 2 || hi > bhi);
+            }
+            const uint64_t cm = __ballot(okc);
+            const int cpos = __popcll(cm & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            int np = __popcll(cm);
+            np = np < K ? np : K;
+            if (okc && cpos < K) L.sp_s[cpos] = xc;
+            if (np == 0) continue;   // a probe round with nothing inside the bracket
+            wave_sync();
+            double xj;
+            CutRes Rj;
+            bool vj;
+            if (C == 8) vj = fast_round<8>(L, lane, u, np, xj, Rj);
+            else if (C == 16) vj = fast_round<16>(L, lane, u, np, xj, Rj);
+            else vj = fast_round<32>(L, lane, u, np, xj, Rj);
+            it += np;
+            // the point nearest to alpha V_P ends the search; otherwise the
+            // tightest sign change becomes the bracket.  Segment j's point and
+            // residual move to lane j, reductions run over lanes 0..7.
+            const double rj = Rj.V / VP - a;
+            const double inf = __builtin_inf();
+            (void)vj;
+            const int srcl = (lane < 8 ? lane : 0) * C;
+            const double x8 = __shfl(xj, srcl), r8 = __shfl(rj, srcl);
+            const bool v8 = lane < np;
+            const bool fnd = v8 && fabs(r8) <= tol;
+            const uint64_t fm = __ballot(fnd);
+            if (fm) {
+              const double mabs = readlane_d(gmin<8>(fnd ? fabs(r8) : inf), 0);
+              const int bj = __ffsll((long long)__ballot(fnd && fabs(r8) == mabs)) - 1;
+              const int bl = bj * C;
+              s = readlane_d(xj, bl);
+              c.V = readlane_d(Rj.V, bl); c.S0 = readlane_d(Rj.S0, bl); c.S1 = readlane_d(Rj.S1, bl);
+              c.S2 = readlane_d(Rj.S2, bl); c.A = readlane_d(Rj.A, bl); c.c0 = readlane_d(Rj.c0, bl);
+              c.c1 = readlane_d(Rj.c1, bl); c.c2 = readlane_d(Rj.c2, bl);
+              c.err = false;
+              cut_ok = true;
+              break;
+            }
+            const double olo = lo, orlo = rlo, ohi = hi, orhi = rhi;
+            const bool pos = v8 && r8 > 0 && x8 > lo && x8 < hi;
+            const double slo = readlane_d(gmax<8>(pos ? x8 : -inf), 0);
+            int jl = -1, jh = -1;
+            if (slo > lo) {
+              jl = __ffsll((long long)__ballot(pos && x8 == slo)) - 1;
+              lo = slo;
+              rlo = readlane_d(r8, jl);
+            }
+            const bool neg = v8 && !(r8 > 0) && x8 > lo && x8 < hi;
+            const double shi = readlane_d(gmin<8>(neg ? x8 : inf), 0);
+            if (shi < hi) {
+              jh = __ffsll((long long)__ballot(neg && x8 == shi)) - 1;
+              hi = shi;
+              rhi = readlane_d(r8, jh);
+            }
+            if (jl >= 0 && lane == jl * C) {
+              double *e = L.end_res[0];
+              e[0] = Rj.V; e[1] = Rj.S0; e[2] = Rj.S1; e[3] = Rj.S2; e[4] = Rj.A; e[5] = Rj.c0; e[6] = Rj.c1; e[7] = Rj.c2;
+            }
+            if (jh >= 0 && lane == jh * C) {
+              double *e = L.end_res[1];
+              e[0] = Rj.V; e[1] = Rj.S0; e[2] = Rj.S1; e[3] = Rj.S2; e[4] = Rj.A; e[5] = Rj.c0; e[6] = Rj.c1; e[7] = Rj.c2;
+            }
+            have_lo = have_lo || jl >= 0;
+            have_hi = have_hi || jh >= 0;
+            // third point: the evaluated point off the bracket nearest the root
+            const bool off = v8 && lane != jl && lane != jh;
+            const double m3 = readlane_d(gmin<8>(off ? fabs(r8) : inf), 0);
+            double b3 = inf;
+            if (m3 < inf) {
+              const int l3 = __ffsll((long long)__ballot(off && fabs(r8) == m3)) - 1;
+              b3 = m3; s3 = readlane_d(x8, l3); r3 = readlane_d(r8, l3);
+            }
+            if (jl >= 0 && fabs(orlo) < b3) { b3 = fabs(orlo); s3 = olo; r3 = orlo; }
+            if (jh >= 0 && fabs(orhi) < b3) { b3 = fabs(orhi); s3 = ohi; r3 = orhi; }
+            have3 = have3 || b3 < inf;
+            if (jl >= 0 && jh >= 0) kept = 0;
+            else if (jl >= 0) kept = kept <= 0 ? kept - 1 : -1;
+            else if (jh >= 0) kept = kept >= 0 ? kept + 1 : 1;
+            slow = (hi - lo) > 0.5 * w0;
+            wave_sync();
           }
-          if (collapsed) {
+          if (collapsed || st == VOFPC_CELL_MAX_ITER) {
+            // the bracket end nearer to alpha V_P
             wave_sync();
             const bool take_lo = fabs(rlo) <= fabs(rhi);
             const double se = take_lo ? lo : hi;
-            if (se != s) {
-              if (take_lo ? have_lo : have_hi) {
-                const double *e = L.end_res[take_lo ? 0 : 1];
-                c.V = e[0]; c.S0 = e[1]; c.S1 = e[2]; c.S2 = e[3]; c.A = e[4]; c.c0 = e[5]; c.c1 = e[6]; c.c2 = e[7];
-                c.err = false;
-              } else {
-                c = cut_full(L, lane, nf, nl, se, -1);
-                ++it;
-              }
-              s = se;
+            if (take_lo ? have_lo : have_hi) {
+              const double *e = L.end_res[take_lo ? 0 : 1];
+              c.V = e[0]; c.S0 = e[1]; c.S1 = e[2]; c.S2 = e[3]; c.A = e[4]; c.c0 = e[5]; c.c1 = e[6]; c.c2 = e[7];
+              c.err = false;
+            } else {
+              c = cut_full(L, lane, nf, nl, se, -1);
+              ++it;
             }
-            if (fabs(take_lo ? rlo : rhi) > 1e-10 && st != VOFPC_CELL_MAX_ITER) st = VOFPC_CELL_NO_ROOT;
+            s = se;
+            cut_ok = true;
+            if (collapsed && fabs(take_lo ? rlo : rhi) > 1e-10) st = VOFPC_CELL_NO_ROOT;
           }
+          if (hint && cut_ok && st == VOFPC_CELL_OK && !(s >= hl && s <= hh)) st = VOFPC_CELL_LEARNED_FALLBACK;
         }
         if (cut_ok && c.err) {
           st = VOFPC_CELL_BAD_INPUT;
@@ -914,6 +1027,7 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
         }
       }
     }
+    int nk = 0;
     if (lane == 0) {
       p.out.s[k] = s_out;
       p.out.n[k] = n0; p.out.n[cap + k] = n1; p.out.n[2 * cap + k] = n2;
@@ -922,7 +1036,12 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
       p.out.alpha_got[k] = ag;
       p.out.status[k] = st;
       p.out.iters[k] = it;
+      // wrapping increment: a launch makes exactly `count` claims (one
+      // after each cell; the first one at or past `count` ends a block), so
+      // the counter is back at zero when the launch ends
+      nk = (int)atomicInc((unsigned int *)p.queue, (unsigned int)(count - 1));
     }
+    k = (int64_t)gridDim.x + __builtin_amdgcn_readfirstlane(nk);
     wave_sync();
   }
 }
@@ -973,6 +1092,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   p.vertex_mode = o->vertex_mode;
   p.fixed_iso = o->fixed_iso ? 1 : 0;
   p.use_hint = (o->bracket == VOFPC_BRACKET_HINT) ? 1 : 0;
+  p.queue = ctx->queue;
   p.out = *out;
   const int64_t nf = M->max_nf, nv = M->max_nv, nl = M->max_loop, ne = M->max_ne, fv = M->max_fv;
   VOFPC_REQUIRE(fv <= 64, VOFPC_E_MESH, "reconstruct: faces with more than 64 vertices are not supported");

@@ -76,6 +76,10 @@ struct vofpc_ctx_s {
   int device;
   hipStream_t stream;
   int n_cu;
+  // claim counter of the reconstruction kernel's cell queue; zero between
+  // launches (each launch wraps it back), so calls on one context must not
+  // overlap
+  int *queue = nullptr;
 };
 
 struct vofpc_mesh_s {

@@ -66,7 +66,7 @@ def labelled_cells(ctx, vmesh, mesh, alpha, buf):
     """Features and labels of every OK mixed cell of one field (device tensors)."""
     dev = ctx.device
     a = torch.as_tensor(alpha, dtype=torch.float64, device=dev)
-    N = mesh.n_cells
+    torch.cuda.synchronize()   # written on torch's stream; the library runs on the context's
     V.compact(ctx, vmesh, a, buf["mixed"], buf["band"], buf["counts"])
     V.features(ctx, vmesh, a, buf["mixed"], buf["counts"], buf["feat"], buf["prange"])
     V.reconstruct(ctx, vmesh, a, buf["mixed"], buf["counts"], buf["itf"])
@@ -82,11 +82,10 @@ def labelled_cells(ctx, vmesh, mesh, alpha, buf):
     u = (itf.s[:M] - pr[:, 0]) / torch.where(W > 0, W, torch.ones_like(W))
     T = torch.stack([u, itf.n[0, :M], itf.n[1, :M], itf.n[2, :M]], 1).float()
     X = buf["feat"][:M]
-    del N
     return X[ok].clone(), T[ok].clone()
 
 
-def make_dataset(ctx, n_target: int, seed: int, max_fields: int = 400):
+def make_dataset(ctx, n_target: int, seed: int, max_fields: int = 600):
     from synth import fields, meshes, workloads
     X_parts, T_parts = [], []
     n = 0
@@ -115,7 +114,8 @@ def make_dataset(ctx, n_target: int, seed: int, max_fields: int = 400):
         frng = np.random.default_rng(s)
         if fk == "bubbles":
             wl = workloads.random_bubbles(m, seed=s, n_max=int(frng.integers(20, 200)), K=12,
-                                          r_lo_h=2.0, r_hi_h=float(frng.uniform(4.0, 12.0)))
+                                          r_lo_h=2.0,
+                                          r_hi_h=min(float(frng.uniform(4.0, 12.0)), 0.3 / m.h))
             alpha = wl.alpha
         else:
             nrm = frng.normal(size=3)
@@ -144,12 +144,14 @@ def train(samples: int, steps: int, seed: int, out: str, batch: int = 4096, lr: 
     g = torch.Generator(device="cpu").manual_seed(seed)
     perm = torch.randperm(X.shape[0], generator=g).to(X.device)
     X, T = X[perm].contiguous(), T[perm].contiguous()
+    torch.cuda.synchronize()
     nval = max(1, X.shape[0] // 10)
     Xv, Tv = X[:nval].contiguous(), T[:nval].contiguous()
     Xt, Tt = X[nval:].contiguous(), T[nval:].contiguous()
     mlp = V.Mlp(ctx, max_batch=max(batch, nval))
     mlp.set_params(xavier(seed, mlp.n_params))
     loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+    torch.cuda.synchronize()
     hist = []
     ntr = Xt.shape[0]
     t1 = time.time()
@@ -163,6 +165,7 @@ def train(samples: int, steps: int, seed: int, out: str, batch: int = 4096, lr: 
             log(f"step {it}: loss {hist[-1][1]:.3e}")
     torch.cuda.synchronize()
     Yv = torch.zeros(nval, 4, dtype=torch.float32, device=X.device)
+    torch.cuda.synchronize()
     mlp.forward(Xv, Yv)
     torch.cuda.synchronize()
     err = (Yv[:, 0].clamp(0, 1) - Tv[:, 0]).double()

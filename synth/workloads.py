@@ -74,6 +74,8 @@ def random_bubbles(mesh: Mesh, seed: int, n_max: int = 1000, K: int = 16,
     rng = np.random.default_rng(seed)
     h = mesh.h
     sph = fields.rsa_spheres(rng, n_max, r_lo_h * h, r_hi_h * h, 2.0 * h)
+    if len(sph) == 0:
+        raise ValueError(f"random_bubbles: no bubble of radius up to {r_hi_h} h fits the box")
     slopes = rng.uniform(1.0, 20.0, len(sph))
     alpha = fields.sphere_alpha(mesh, sph, K=K)
     T = fields.nearest_bubble_T(mesh.cell_vertex_mean(), sph, slopes, T_SAT)

@@ -52,6 +52,7 @@ def test_forward_matches_reference(V):
     X = rng.normal(size=(1003, 32)).astype(np.float32)   # ragged: not a multiple of 16
     Xd = torch.tensor(X, device="cuda")
     Yd = torch.zeros(1003, 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()   # inputs were written on torch's stream
     mlp.forward(Xd, Yd)
     torch.cuda.synchronize()
     y = Yd.cpu().numpy()
@@ -76,7 +77,9 @@ def test_gradient_matches_reference(V):
     T = rng.normal(size=(2000, 4)).astype(np.float32)
     g = torch.zeros(mlp.n_params, dtype=torch.float32, device="cuda")
     L = torch.zeros(1, dtype=torch.float32, device="cuda")
-    mlp.gradient(torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda"), g, L)
+    Xd, Td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
+    torch.cuda.synchronize()
+    mlp.gradient(Xd, Td, g, L)
     torch.cuda.synchronize()
     Lr, gr = R.backward(p, X, T)
     gg = R.unflatten(g.cpu().numpy())
@@ -100,6 +103,8 @@ def test_adam_first_step_and_loss_decrease(V):
     W = rng.normal(size=(32, 4)).astype(np.float32) * 0.2
     T = np.tanh(X @ W).astype(np.float32)
     Xd, Td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
+    L = torch.zeros(1, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
     lr = 1e-3
     mlp.train_step(Xd, Td, lr)
     after = R.unflatten(mlp.get_params())
@@ -110,7 +115,6 @@ def test_adam_first_step_and_loss_decrease(V):
     for k in R.ORDER:
         big = np.abs(gr[k]) > 1e-3 * np.abs(gr[k]).max()
         np.testing.assert_allclose(after[k][big], ref[k][big], atol=1e-6, err_msg=k)
-    L = torch.zeros(1, dtype=torch.float32, device="cuda")
     losses = []
     for it in range(300):
         mlp.train_step(Xd, Td, 3e-3, L)
@@ -132,6 +136,7 @@ def test_features_match_reference(V):
     V.compact(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.band_idx, b.counts)
     feat = torch.zeros(N, 32, dtype=torch.float32, device="cuda")
     pr = torch.zeros(N, 2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     V.features(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, feat, pr)
     torch.cuda.synchronize()
     M = int(b.counts[0].item())

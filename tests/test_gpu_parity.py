@@ -251,3 +251,30 @@ def test_edge_cases_empty_all_and_single(V, runner):
             assert g["n_mixed"] == 1 and g["status"][0] == V.CELL_OK and g["A"][0] > 0
         run.close()
     torch.cuda.synchronize()
+
+
+def test_repeated_launches_share_the_cell_queue(V, runner):
+    """Launches of different sizes in a row on one context (the reconstruction
+    hands cells to blocks through a per-context counter) give the results of
+    a full launch for every cell they cover."""
+    import torch
+    wl = _wl("vor12")
+    _say("repeated launches vor12")
+    run = runner.PathRun(wl)
+    run.step()
+    full = run.results()
+    b = run.buf
+    M = full["n_mixed"]
+    cnt = torch.zeros(2, dtype=torch.int32, device=run.dev)
+    for m in (M, 3, 0, 1, M - 1, M):
+        cnt[0] = m
+        cnt[1] = full["n_band"]
+        b.itf.status.fill_(-1)
+        torch.cuda.synchronize()
+        V.reconstruct(run.ctx, run.mesh, run.alpha, b.mixed_idx, cnt, b.itf)
+        torch.cuda.synchronize()
+        st = b.itf.status.cpu().numpy()
+        np.testing.assert_array_equal(st[:m], full["status"][:m])
+        assert np.all(st[m:] == -1)
+        np.testing.assert_array_equal(b.itf.alpha_got[:m].cpu().numpy(), full["alpha_got"][:m])
+    run.close()
