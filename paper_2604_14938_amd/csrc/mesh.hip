@@ -208,6 +208,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   std::vector<int32_t> cv_gid;
   std::vector<uint8_t> cl_lv;
   std::vector<uint16_t> cl_eid;            // local undirected edge id per loop position
+  std::vector<uint32_t> cl_info;           // face (bits 0-7), index in face (8-15), next position (16-31)
   std::vector<int32_t> edge_stamp(65536, -1), edge_id(65536, 0);
   std::vector<int32_t> cf_nbr(ncf);
   std::vector<uint16_t> cf_loff(ncf);
@@ -229,6 +230,9 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
       VOFPC_REQUIRE(loff < 65535, VOFPC_E_MESH, "mesh_upload: cell loops too long");
       cf_loff[i] = (uint16_t)loff;
       cf_lsz[i] = (uint8_t)n;
+      const uint32_t fl = (uint32_t)(i - cfo[P]);
+      for (int64_t k = 0; k < n; ++k)
+        cl_info.push_back(fl | (uint32_t)k << 8 | (uint32_t)(loff + (k + 1 == n ? 0 : k + 1)) << 16);
       int32_t first = -1, prev = -1;
       for (int64_t k = 0; k < n; ++k) {
         int32_t g = d->face_vert[o + (rev ? n - 1 - k : k)];
@@ -325,6 +329,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   COPY(cl_off, cl_off.data(), N + 1, int64_t);
   COPY(cl_lv, cl_lv.data(), cl_lv.size(), uint8_t);
   COPY(cl_eid, cl_eid.data(), cl_eid.size(), uint16_t);
+  COPY(cl_info, cl_info.data(), cl_info.size(), uint32_t);
   COPY(vc_off, vc_off.data(), NV + 1, int64_t);
   COPY(vc_cell, vc_cell.data(), vc_cell.size(), int32_t);
   COPY(vc_w, (const double *)nullptr, vc_cell.size(), double);

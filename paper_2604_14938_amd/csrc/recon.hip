@@ -159,7 +159,7 @@ struct FastSlot {
   int nch, nloops, valid;
 };
 
-constexpr int kSlotChords = 32;   // chords a cached topology can hold
+constexpr int kSlotChords = 16;   // chords a cached topology can hold
 
 template <int W, int NV, int NF, int NL, int NCH>
 struct GroupMem {
@@ -168,7 +168,6 @@ struct GroupMem {
   double cf[3][NF];
   double fmean[NF];
   double inv[NL];         // 1/(phi[next] - phi[this]) of each loop position
-  double ps[3][NCH];      // chord exit points
   FastSlot<W> fs[2];
   uint16_t ch_xe[NCH];    // chord exit edge id
   uint16_t ch_ne[NCH];    // chord entry edge id
@@ -176,8 +175,8 @@ struct GroupMem {
   uint16_t ch_xpos[NCH];  // loop position of the exit edge
   uint16_t by_entry[NCH]; // chord entering through edge e
   uint16_t by_exit[NCH];  // chord leaving through edge e
-  uint16_t lab[2][NCH];
-  uint16_t jmp[2][NCH];
+  uint16_t lab[2][NCH > 64 ? NCH : 1];   // loop labelling through LDS (more chords than lanes)
+  uint16_t jmp[2][NCH > 64 ? NCH : 1];
   uint16_t floff[NF];
   uint16_t eid[NL];
   double sp_s[8];                         // isovalues of a parallel round
@@ -355,8 +354,9 @@ __device__ void loops_lds(GM &L, int lane, int nch, CutRes &R) {
     for (int c = lane; c < nch; c += W) {
       if (L.lab[cur][c] != cand) continue;
       const int n = L.by_entry[L.ch_xe[c]];
-      const double a0 = L.ps[0][c], a1 = L.ps[1][c], a2 = L.ps[2][c];
-      const double b0 = L.ps[0][n], b1 = L.ps[1][n], b2 = L.ps[2][n];
+      const int ea = L.ch_xe[c], eb = L.ch_xe[n];
+      const double a0 = L.ept[0][ea], a1 = L.ept[1][ea], a2 = L.ept[2][ea];
+      const double b0 = L.ept[0][eb], b1 = L.ept[1][eb], b2 = L.ept[2][eb];
       const double d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
       const double len = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
       l += len;
@@ -369,14 +369,16 @@ __device__ void loops_lds(GM &L, int lane, int nch, CutRes &R) {
     if (l > 0) {
       k0 = m0 / l; k1 = m1 / l; k2 = m2 / l;
     } else {
-      k0 = L.ps[0][cand]; k1 = L.ps[1][cand]; k2 = L.ps[2][cand];
+      const int ec = L.ch_xe[cand];
+      k0 = L.ept[0][ec]; k1 = L.ept[1][ec]; k2 = L.ept[2][ec];
     }
     double vi = 0, t0 = 0, t1 = 0, t2 = 0;
     for (int c = lane; c < nch; c += W) {
       if (L.lab[cur][c] != cand) continue;
       const int n = L.by_entry[L.ch_xe[c]];
-      const double a0 = L.ps[0][c], a1 = L.ps[1][c], a2 = L.ps[2][c];
-      const double b0 = L.ps[0][n], b1 = L.ps[1][n], b2 = L.ps[2][n];
+      const int ea = L.ch_xe[c], eb = L.ch_xe[n];
+      const double a0 = L.ept[0][ea], a1 = L.ept[1][ea], a2 = L.ept[2][ea];
+      const double b0 = L.ept[0][eb], b1 = L.ept[1][eb], b2 = L.ept[2][eb];
       vi += det3(k0, k1, k2, a0, a1, a2, b0, b1, b2);
       const double u0 = a0 - k0, u1 = a1 - k1, u2 = a2 - k2;
       const double w0 = b0 - k0, w1 = b1 - k1, w2 = b2 - k2;
@@ -474,7 +476,6 @@ __device__ CutRes cut_full(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, 
       const double e0 = L.ept[0][ne], e1 = L.ept[1][ne], e2 = L.ept[2][ne];
       vcut += det3(L.cf[0][f], L.cf[1][f], L.cf[2][f], s0, s1, s2, e0, e1, e2);
       if (c < NCH) {
-        L.ps[0][c] = s0; L.ps[1][c] = s1; L.ps[2][c] = s2;
         L.ch_xe[c] = (uint16_t)xe;
         L.ch_ne[c] = (uint16_t)ne;
         L.ch_face[c] = (uint16_t)f;
@@ -498,8 +499,9 @@ __device__ CutRes cut_full(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, 
     double p0 = 0, p1 = 0, p2 = 0;
     int next = lane;
     if (valid) {
-      p0 = L.ps[0][lane]; p1 = L.ps[1][lane]; p2 = L.ps[2][lane];
-      next = L.by_entry[L.ch_xe[lane]];
+      const int e = L.ch_xe[lane];
+      p0 = L.ept[0][e]; p1 = L.ept[1][e]; p2 = L.ept[2][e];
+      next = L.by_entry[e];
     }
     int lab, nloops;
     if (nch <= 16) {
@@ -550,7 +552,7 @@ __device__ CutRes cut_full(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, 
       }
     }
   } else {
-    loops_lds<W>(L, lane, nch, R);
+    if constexpr (NCH > 64) loops_lds<W>(L, lane, nch, R);
   }
   R.err = gsum_i<W>(err ? 1 : 0) != 0;
   wave_sync();
@@ -700,7 +702,8 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
     } else {
       const double xP0 = m.xc[P], xP1 = m.xc[N + P], xP2 = m.xc[2 * N + P];
       const double VP = m.V[P];
-      // ---- stage the polyhedron (vertex field by inverse-distance weights)
+      // ---- stage the polyhedron (vertex field by inverse-distance weights;
+      // the incidences of a vertex are read four at a time, summed in order)
       for (int i = lane; i < nv; i += W) {
         const int gv = m.cv_gid[v0 + i];
         L.X[0][i] = m.xyz[gv] - xP0;
@@ -712,13 +715,32 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
         } else {
           const double *w = p.vertex_mode ? m.vc_wmean : m.vc_w;
           ph = 0.0;
-          for (int64_t j = m.vc_off[gv]; j < m.vc_off[gv + 1]; ++j) ph += w[j] * p.alpha[m.vc_cell[j]];
+          const int64_t j1 = m.vc_off[gv + 1];
+          for (int64_t j = m.vc_off[gv]; j < j1; j += 4) {
+            int cc[4];
+            double ww[4], aa[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const bool in = j + t < j1;
+              cc[t] = in ? m.vc_cell[j + t] : 0;
+              ww[t] = in ? w[j + t] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) aa[t] = (j + t < j1) ? p.alpha[cc[t]] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (j + t < j1) ph += ww[t] * aa[t];
+          }
         }
         L.phi[i] = ph;
       }
       for (int i = lane; i < nl; i += W) {
+        const uint32_t info = m.cl_info[l0 + i];
         L.lv[i] = m.cl_lv[l0 + i];
         L.eid[i] = m.cl_eid[l0 + i];
+        L.pface[i] = (uint8_t)(info & 0xffu);
+        L.pk[i] = (uint8_t)((info >> 8) & 0xffu);
+        L.pnext[i] = (uint16_t)(info >> 16);
       }
       for (int f = lane; f < nf; f += W) {
         L.floff[f] = m.cf_loff[f0 + f];
@@ -781,19 +803,13 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
           double c0 = 0, c1 = 0, c2 = 0, fm = 0;
           for (int k2 = 0; k2 < n; ++k2) {
             const int v = L.lv[o + k2];
-            const int vn = L.lv[o + (k2 + 1 == n ? 0 : k2 + 1)];
             c0 += L.X[0][v]; c1 += L.X[1][v]; c2 += L.X[2][v];
             fm += L.phi[v];
-            L.inv[o + k2] = 1.0 / (L.phi[vn] - L.phi[v]);
           }
           L.cf[0][f] = c0 / n; L.cf[1][f] = c1 / n; L.cf[2][f] = c2 / n;
           L.fmean[f] = fm / n;
-          for (int k2 = 0; k2 < n; ++k2) {
-            L.pface[o + k2] = (uint8_t)f;
-            L.pk[o + k2] = (uint8_t)k2;
-            L.pnext[o + k2] = (uint16_t)(o + (k2 + 1 == n ? 0 : k2 + 1));
-          }
         }
+        for (int i = lane; i < nl; i += W) L.inv[i] = 1.0 / (L.phi[L.lv[L.pnext[i]]] - L.phi[L.lv[i]]);
         if (lane == 0) {
           L.fs[0].valid = 0;
           L.fs[1].valid = 0;
@@ -898,7 +914,7 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
             // a ladder around the estimate and the bracket midpoint
             const double blo = L.fs[u].bp_lo, bhi = L.fs[u].bp_hi;
             const int nch = L.fs[u].nch;
-            const int C = nch <= 8 ? 8 : (nch <= 16 ? 16 : 32);
+            const int C = nch <= 8 ? 8 : 16;
             const int K = 64 / C;
             // candidates in lanes 0..7 (estimate, left and right interval
             // ends, ladder -d/16, +d/16, -d, +d, midpoint); the first K that
@@ -925,8 +941,7 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
             CutRes Rj;
             bool vj;
             if (C == 8) vj = fast_round<8>(L, lane, u, np, xj, Rj);
-            else if (C == 16) vj = fast_round<16>(L, lane, u, np, xj, Rj);
-            else vj = fast_round<32>(L, lane, u, np, xj, Rj);
+            else vj = fast_round<16>(L, lane, u, np, xj, Rj);
             it += np;
             // the point nearest to alpha V_P ends the search; otherwise the
             // tightest sign change becomes the bracket.  Segment j's point and

@@ -57,6 +57,8 @@ struct DevMesh {
   const int64_t *cl_off;
   const uint8_t *cl_lv;
   const uint16_t *cl_eid;  // local undirected edge id of each loop position
+  const uint32_t *cl_info; // face within the cell (bits 0-7), index within the face
+                           // (8-15) and cell-local next loop position (16-31)
   // vertex -> cell incidence with normalised inverse-distance weights
   const int64_t *vc_off;
   const int32_t *vc_cell;
