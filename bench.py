@@ -6,6 +6,11 @@ HIP graph with inputs resident in HBM.  Default workload: 194,672-cell
 box-clipped jittered-BCC Voronoi mesh of the unit cube with one vapour bubble
 (r = 0.25) and a Scriven-like erf temperature profile, FP64.
 
+Both forms are timed on the same inputs: plain (search from the cell's full
+vertex-value range) and learned (the bracket network inside the
+reconstruction kernel gives the first guess).  The headline value is the
+learned form when trained weights are present, else the plain one.
+
 Prints one JSON line (see the README of the repository for the fields).
 """
 from __future__ import annotations
@@ -89,20 +94,30 @@ def step_bytes(mesh, mixed, band, recon_b) -> int:
     return int(b)
 
 
-def measured_traffic():
-    """HBM bytes per reconstruction launch from the committed rocprofv3
-    counter summary, if the kernel source has not changed since; else None."""
+RECON_SOURCES = ("recon.hip", "mlp_core.h", "vofpc_internal.h")
+
+
+def recon_source_hash() -> str:
     import hashlib
+    h = hashlib.sha256()
+    for f in RECON_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2604_14938_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(form: str):
+    """HBM bytes per reconstruction launch of `form` from the committed
+    rocprofv3 counter summary, if the kernel sources have not changed since;
+    else None."""
     path = os.path.join(ROOT, "profiles", "recon_kernel_voronoi195k_traffic.json")
-    src = os.path.join(ROOT, "paper_2604_14938_amd", "csrc", "recon.hip")
     try:
         info = json.load(open(path))
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        cur = recon_source_hash()
     except (OSError, ValueError):
         return None
-    if info.get("recon_source_sha256") != cur:
+    if info.get("recon_sources_sha256") != cur or form not in info.get("traffic_bytes_per_launch", {}):
         return None
-    return float(info["traffic_bytes_per_launch"])
+    return float(info["traffic_bytes_per_launch"][form])
 
 
 def cpu_baseline(wl, budget_s: float = 10.0) -> dict:
@@ -158,52 +173,109 @@ def main() -> int:
     t0 = time.time()
     wl = workloads.voronoi_bubble()
     log(f"workload ready in {time.time() - t0:.1f} s: {wl.mesh.n_cells} cells, {wl.n_mixed} mixed")
-    run = runner.PathRun(wl, device=0)
-    stream = run.ctx.stream
-    run.step()
-    first = run.results()
-    ok = first["status"] == 0
-    parity_alpha = float(np.abs(first["alpha_got"][ok] - wl.alpha[first["mixed_idx"][ok]]).max(initial=0))
-    g = run.capture()
-    for _ in range(args.warmup):
-        g.launch()
-    torch.cuda.synchronize()
-    log(f"warmup done, timing {args.steps} graph replays")
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    ev[0].record(stream)
-    for i in range(args.steps):
-        g.launch()
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
-    ms_total = ev[0].elapsed_time(ev[-1])
-    ms_per_step = ms_total / args.steps
-    M = first["n_mixed"]
-    log(f"step: {ms_per_step * 1e3:.1f} us mean, {statistics.median(per) * 1e3:.1f} us median, wall {wall:.3f} s")
-
-    # dominant kernel alone (reconstruction), same launch, events on its stream
     from paper_2604_14938_amd import vofpc as V
-    b = run.buf
-    reps = max(10, args.steps)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    V.reconstruct(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, b.itf, b.opts)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        V.reconstruct(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, b.itf, b.opts)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    recon_ms = e0.elapsed_time(e1) / reps
-    mixed = first["mixed_idx"]
-    rb = recon_bytes(wl.mesh, mixed)
-    sb = step_bytes(wl.mesh, mixed, first["band_idx"], rb)
-    achieved = rb / (recon_ms * 1e-3) / 1e9
-    log(f"reconstruction kernel: {recon_ms * 1e3:.1f} us, {rb / 1e6:.2f} MB algorithmic -> {achieved:.1f} GB/s")
+    from paper_2604_14938_amd import train
 
+    def time_form(mlp=None, dscale=0.0):
+        """Capture the step of one form, warm up, time exactly `steps` graph
+        replays (HIP events on the context stream), then time the
+        reconstruction launch alone the same way."""
+        run = runner.PathRun(wl, device=0, ctx=V.Context(0, stream=torch.cuda.Stream()), mlp=mlp,
+                             delta_scale=dscale)
+        stream = run.ctx.stream
+        run.step()
+        res = run.results()
+        g = run.capture()
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(args.steps):
+            g.launch()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+        ms = ev[0].elapsed_time(ev[-1]) / args.steps
+        b = run.buf
+        if mlp is None:
+            rec = lambda: V.reconstruct(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, b.itf, b.opts)
+        else:
+            rec = lambda: V.reconstruct_learned(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, b.itf, mlp,
+                                                dscale, b.opts)
+        reps = max(10, args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        rec()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            rec()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        recon_ms = e0.elapsed_time(e1) / reps
+        run.close()
+        return res, ms, statistics.median(per), wall, recon_ms
+
+    plain, ms_p, med_p, wall_p, rms_p = time_form()
+    M = plain["n_mixed"]
+    log(f"plain step: {ms_p * 1e3:.1f} us mean, {med_p * 1e3:.1f} us median (wall {wall_p:.3f} s); "
+        f"reconstruction {rms_p * 1e3:.1f} us")
+    learned = None
+    if os.path.exists(train.DEFAULT_WEIGHTS):
+        params, dscale, tinfo = train.load()
+        ctx_m = V.Context(0, stream=torch.cuda.Stream())
+        mlp = V.Mlp(ctx_m)
+        mlp.set_params(params)
+        learned, ms_l, med_l, wall_l, rms_l = time_form(mlp, dscale)
+        log(f"learned step: {ms_l * 1e3:.1f} us mean, {med_l * 1e3:.1f} us median (wall {wall_l:.3f} s); "
+            f"reconstruction {rms_l * 1e3:.1f} us")
+    head = learned if learned is not None else plain
+    ms_per_step = ms_l if learned is not None else ms_p
+    recon_ms = rms_l if learned is not None else rms_p
+    form = "learned" if learned is not None else "plain"
+    ok = head["status"] != 1
+    parity_alpha = float(np.abs(head["alpha_got"][head["status"] == 0] -
+                                wl.alpha[head["mixed_idx"][head["status"] == 0]]).max(initial=0))
+    mixed = plain["mixed_idx"]
+    rb = recon_bytes(wl.mesh, mixed)
+    if learned is not None:
+        cfo = wl.mesh.cell_face_off
+        rb += int((cfo[mixed + 1] - cfo[mixed]).sum()) * (4 + 4 + 24) + 6 * 6532   # faces read by the features, weights
+    sb = step_bytes(wl.mesh, mixed, plain["band_idx"], rb)
+    achieved = rb / (recon_ms * 1e-3) / 1e9
+    log(f"{form} reconstruction kernel: {recon_ms * 1e3:.1f} us, {rb / 1e6:.2f} MB algorithmic -> {achieved:.1f} GB/s")
+    cfg = {
+        "workload": "voronoi_bubble: 194,672-cell box-clipped jittered-BCC Voronoi mesh of the unit cube "
+                    "(seed 2), vapour bubble r=0.25 at the centre, T_sat + 1.25 K erf((rho-0.25)/0.05) outside",
+        "n_cells": int(wl.mesh.n_cells),
+        "n_mixed": int(M),
+        "n_band": int(plain["n_band"]),
+        "form": form,
+        "max_abs_dalpha_vs_input": parity_alpha,
+        "step_algorithmic_bytes": sb,
+        "step_GBps": sb / (ms_per_step * 1e-3) / 1e9,
+        "plain": {"cells_per_s": M / (ms_p * 1e-3), "ms_per_step": ms_p, "recon_us": rms_p * 1e3,
+                  "evals_per_cell_mean": float(plain["iters"].mean()),
+                  "evals_per_cell_p99": float(np.percentile(plain["iters"], 99))},
+    }
+    if learned is not None:
+        same = learned["status"] == plain["status"]
+        both = same & (plain["status"] != 1)
+        cfg["learned"] = {
+            "cells_per_s": M / (ms_l * 1e-3), "ms_per_step": ms_l, "recon_us": rms_l * 1e3,
+            "evals_per_cell_mean": float(learned["iters"].mean()),
+            "evals_per_cell_p99": float(np.percentile(learned["iters"], 99)),
+            "fallback_rate": float(np.mean(learned["status"] == 2)),
+            "speedup_vs_plain": ms_p / ms_l,
+            "max_abs_dalpha_vs_plain": float(np.abs(learned["alpha_got"] - plain["alpha_got"])[both].max(initial=0)),
+            "bitwise_equal_fraction": float(np.mean((learned["alpha_got"] == plain["alpha_got"]) &
+                                                    (learned["A"] == plain["A"]))),
+            "delta_scale": dscale, "weights_sigma_val": tinfo.get("sigma_val"),
+        }
     out = {
         "metric": METRIC,
         "value": M / (ms_per_step * 1e-3),
@@ -217,18 +289,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": "voronoi_bubble: 194,672-cell box-clipped jittered-BCC Voronoi mesh of the unit cube "
-                        "(seed 2), vapour bubble r=0.25 at the centre, T_sat + 1.25 K erf((rho-0.25)/0.05) outside",
-            "n_cells": int(wl.mesh.n_cells),
-            "n_mixed": int(M),
-            "n_band": int(first["n_band"]),
-            "form": "plain",
-            "mean_evals_per_cell": float(first["iters"].mean()),
-            "max_abs_dalpha_vs_input": parity_alpha,
-            "step_algorithmic_bytes": sb,
-            "step_GBps": sb / (ms_per_step * 1e-3) / 1e9,
-        },
+        "config": cfg,
         "roofline": {
             "bound": "hbm",
             "kernel": "recon_kernel",
@@ -236,12 +297,11 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(form),
             "kernel_us": recon_ms * 1e3,
             "algorithmic_bytes": rb,
         },
     }
-    run.close()
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

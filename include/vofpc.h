@@ -137,15 +137,15 @@ vofpc_status vofpc_compact(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, 
                            int32_t *mixed_idx, int32_t *band_idx, int32_t *counts);
 
 /* --------------------------------------------------------- reconstruction */
-#define VOFPC_BRACKET_PLAIN 0   /* bisect on [phi_min, phi_max] of the cell */
-#define VOFPC_BRACKET_HINT 1    /* start from hint_lo/hint_hi, verified */
+#define VOFPC_BRACKET_PLAIN 0   /* search [phi_min, phi_max] of the cell */
+#define VOFPC_BRACKET_HINT 1    /* first guess from hint_lo/hint_hi (see vofpc_reconstruct) */
 #define VOFPC_VERTEX_IDW 0      /* vertex value: inverse-distance cell average */
 #define VOFPC_VERTEX_MEAN 1     /* vertex value: plain average of the cells */
 
 typedef struct {
   double eps_mixed;   /* mixed when eps < alpha < 1-eps (default 1e-8) */
   double tol_rel;     /* stop when |V/V_P - alpha| <= tol_rel min(alpha,1-alpha) (1e-13) */
-  int32_t max_iter;   /* bisection evaluations per cell (100) */
+  int32_t max_iter;   /* volume evaluations per cell before VOFPC_CELL_MAX_ITER (100) */
   int32_t vertex_mode;/* VOFPC_VERTEX_* */
   int32_t fixed_iso;  /* nonzero: no root-find, cut at `iso` (paper's isoap mode) */
   int32_t bracket;    /* VOFPC_BRACKET_* */
@@ -171,17 +171,39 @@ typedef struct {
   int64_t cap;
 } vofpc_interface;
 
-/* Reconstruct the interface in every listed mixed cell.  alpha: DEVICE
- * [n_cells]; mixed_idx/counts from vofpc_compact.  hint_lo/hint_hi: DEVICE
- * [cap] narrowed brackets per mixed entry, read only when opts->bracket is
- * VOFPC_BRACKET_HINT (NaN entries use the plain bracket).  A narrowed bracket
- * is checked with two volume evaluations; if the root is outside it the
- * bisection continues on the remaining part of the plain bracket and the cell
- * is flagged VOFPC_CELL_LEARNED_FALLBACK, so the result stays in the same
- * stopping window either way. */
+/* Reconstruct the interface in every listed mixed cell (Sec. 2.3: the
+ * isovalue of the vertex field is iterated until the cut liquid volume
+ * matches alpha V_P; Eq. edge_intersection for the cut points, divergence
+ * theorem for the volume).  alpha: DEVICE [n_cells]; mixed_idx/counts from
+ * vofpc_compact.
+ * The isovalue search keeps a bracket [lo, hi] of [phi_min, phi_max] with
+ * V(lo) > alpha V_P > V(hi) and stops at the first isovalue whose residual
+ * |V/V_P - alpha| is within tol_rel min(alpha, 1-alpha); when the bracket
+ * shrinks to two ulps first, the end nearer to alpha V_P is taken
+ * (VOFPC_CELL_NO_ROOT when its residual exceeds 1e-10).  Guesses come from
+ * regula falsi / inverse quadratic interpolation with bisection safeguards;
+ * between two breakpoints of the cut topology several guesses are evaluated
+ * at once.  Any isovalue in the stopping window is a valid result; the
+ * oracle's bisection may stop at another one of the same window.
+ * hint_lo/hint_hi: DEVICE [cap] per mixed entry, read only when
+ * opts->bracket is VOFPC_BRACKET_HINT: the midpoint is the first guess and
+ * a cell whose result falls outside [hint_lo, hint_hi] is flagged
+ * VOFPC_CELL_LEARNED_FALLBACK (NaN entries: plain search, no flag). */
 vofpc_status vofpc_reconstruct(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed_idx,
                                const int32_t *counts, const vofpc_recon_opts *opts, const double *hint_lo,
                                const double *hint_hi, const vofpc_interface *out);
+
+/* Reconstruction with the bracket network run inside the same kernel: each
+ * mixed cell's 32 inputs (as vofpc_features defines them) and the forward
+ * pass on MFMA give the bracket phi_min + clamp(u,0,1) W +- delta_scale W,
+ * used as with VOFPC_BRACKET_HINT.  opts->bracket must be
+ * VOFPC_BRACKET_PLAIN.  hint_lo/hint_hi: optional DEVICE double[cap]
+ * receiving the network's brackets (both or neither; NaN where the network
+ * gives none).  Cells whose vertex field is degenerate skip the network. */
+vofpc_status vofpc_reconstruct_learned(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha,
+                                       const int32_t *mixed_idx, const int32_t *counts,
+                                       const vofpc_recon_opts *opts, vofpc_mlp mlp, double delta_scale,
+                                       double *hint_lo, double *hint_hi, const vofpc_interface *out);
 
 /* ----------------------------------------------------------------- gradient */
 #define VOFPC_SCOPE_BAND 0  /* write grad at band cells only (others untouched) */
@@ -215,11 +237,10 @@ vofpc_status vofpc_mass_transfer(vofpc_ctx ctx, vofpc_mesh mesh, const double *a
                                  double *Qdot_cells);
 
 /* ---------------------------------------------------------- bracket network */
-/* A small network narrows the initial bisection bracket of every mixed cell;
- * the reconstruction verifies the narrowed bracket with two volume
- * evaluations and falls back to the rest of the plain bracket when it does
- * not hold the root, so the network changes only how many evaluations a cell
- * needs.  Architecture: 32 features -> 64 -> 64 -> 4 (tanh hidden layers),
+/* A small network predicts the isovalue of every mixed cell; the
+ * reconstruction takes it as the first guess of its bracketed search, whose
+ * stopping rule alone decides the result, so the network changes only how
+ * many volume evaluations a cell needs.  Architecture: 32 features -> 64 -> 64 -> 4 (tanh hidden layers),
  * BF16 weights and activations on MFMA with FP32 accumulation, FP32 master
  * weights updated by Adam.  Outputs per cell: u, the isovalue normalised to
  * the cell's vertex-value range, (s - phi_min)/(phi_max - phi_min), and a
@@ -274,19 +295,17 @@ typedef struct {
   const double *alpha, *T, *T_bface;
   double T_sat, k_l, k_v, h_lv;
   vofpc_recon_opts opts;
-  double *hint_lo, *hint_hi; /* read with opts.bracket == VOFPC_BRACKET_HINT; written by the learned form */
+  double *hint_lo, *hint_hi; /* read with opts.bracket == VOFPC_BRACKET_HINT; with mlp set:
+                              * optional outputs of the network's brackets */
   int32_t *mixed_idx, *band_idx, *counts;
   vofpc_interface itf;
   double *gradT;          /* [3][n_cells], written on the band */
   int32_t *grad_status;   /* optional [n_cells] */
   double *mdot, *Qdot;    /* [cap] over the mixed list */
-  /* learned form: with mlp set, the step computes features into `features`
-   * (float[cap][32]) and `phi_range` (double[cap][2]), writes the network's
-   * brackets into hint_lo/hint_hi and reconstructs from them */
+  /* learned form: with mlp set, the reconstruction runs the network inside
+   * its kernel (vofpc_reconstruct_learned with delta_scale) */
   vofpc_mlp mlp;
   double delta_scale;
-  float *features;
-  double *phi_range;
 } vofpc_step_args;
 
 /* Issue one step on the context stream. */

@@ -110,6 +110,20 @@ extern "C" vofpc_status vofpc_reconstruct(vofpc_ctx ctx, vofpc_mesh mesh, const 
   return launch_reconstruct(ctx, mesh, alpha, mixed_idx, counts, opts, hint_lo, hint_hi, out);
 }
 
+extern "C" vofpc_status vofpc_reconstruct_learned(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha,
+                                                  const int32_t *mixed_idx, const int32_t *counts,
+                                                  const vofpc_recon_opts *opts, vofpc_mlp mlp, double delta_scale,
+                                                  double *hint_lo, double *hint_hi, const vofpc_interface *out) {
+  clear_error();
+  vofpc_status s = check_pair(ctx, mesh);
+  if (s) return s;
+  VOFPC_REQUIRE(mlp, VOFPC_E_INVALID_ARG, "reconstruct_learned: null network");
+  VOFPC_REQUIRE((hint_lo == nullptr) == (hint_hi == nullptr), VOFPC_E_INVALID_ARG,
+                "reconstruct_learned: give both bracket outputs or neither");
+  return launch_reconstruct(ctx, mesh, alpha, mixed_idx, counts, opts, nullptr, nullptr, out, mlp, delta_scale,
+                            hint_lo, hint_hi);
+}
+
 extern "C" vofpc_status vofpc_grad_T(vofpc_ctx ctx, vofpc_mesh mesh, const double *T, const double *T_bface,
                                      double T_sat, const double *alpha, const int32_t *band_idx,
                                      const int32_t *counts, int32_t scope, int32_t variant, double *grad,
@@ -138,17 +152,13 @@ static vofpc_status issue_step(vofpc_ctx ctx, vofpc_mesh mesh, const vofpc_step_
   vofpc_status s = launch_compact(ctx, mesh, a->alpha, a->opts.eps_mixed, a->mixed_idx, a->band_idx, a->counts);
   if (s) return s;
   if (a->mlp) {
-    VOFPC_REQUIRE(a->features && a->phi_range && a->hint_lo && a->hint_hi, VOFPC_E_INVALID_ARG,
-                  "step: the learned form needs features, phi_range, hint_lo and hint_hi buffers");
-    s = launch_features(ctx, mesh, a->alpha, a->mixed_idx, a->counts, a->itf.cap, &a->opts, a->features,
-                        a->phi_range);
-    if (s) return s;
-    s = launch_bracket(ctx, a->mlp, a->features, a->phi_range, a->counts, a->itf.cap, a->delta_scale, a->hint_lo,
-                       a->hint_hi);
-    if (s) return s;
-    vofpc_recon_opts o = a->opts;
-    o.bracket = VOFPC_BRACKET_HINT;
-    s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &o, a->hint_lo, a->hint_hi, &a->itf);
+    // learned form: the network runs inside the reconstruction kernel
+    VOFPC_REQUIRE(a->opts.bracket == VOFPC_BRACKET_PLAIN, VOFPC_E_INVALID_ARG,
+                  "step: the learned form takes opts.bracket = VOFPC_BRACKET_PLAIN");
+    VOFPC_REQUIRE((a->hint_lo == nullptr) == (a->hint_hi == nullptr), VOFPC_E_INVALID_ARG,
+                  "step: give both hint_lo and hint_hi or neither");
+    s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, nullptr, nullptr, &a->itf, a->mlp,
+                           a->delta_scale, a->hint_lo, a->hint_hi);
   } else {
     s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, a->hint_lo, a->hint_hi, &a->itf);
   }

@@ -7,8 +7,6 @@
 // The reconstruction checks the bracket and falls back, so the network only
 // changes how many volume evaluations a cell needs, never its result.
 //
-// MFMA tiles: v_mfma_f32_16x16x16_bf16 on one wavefront.  Lane l holds
-// A[l%16][4(l/16)+j], B[4(l/16)+j][l%16] and D[4(l/16)+j][l%16], j = 0..3.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -16,30 +14,13 @@
 #include <vector>
 
 #include "vofpc_internal.h"
+#include "mlp_core.h"
 
 namespace vofpc {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// parameter layout (FP32 master and BF16 copy share it)
-constexpr int kIn = 32, kHid = 64, kOut = 4;
-constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid, oW3 = oB2 + kHid,
-              oB3 = oW3 + kOut * kHid, kParams = oB3 + kOut;
+using namespace net;
 constexpr float kNormalWeight = 0.1f;
 constexpr int kTilesPerBlock = 4;  // 64 rows per training block
-
-__device__ __forceinline__ uint16_t to_bf16(float x) {
-  uint32_t b = __float_as_uint(x);
-  if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40);  // NaN stays NaN
-  b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(b >> 16);
-}
-__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
 
 __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -65,19 +46,6 @@ __device__ __forceinline__ bf16x4 a_rows(const uint16_t (*t)[LD], int lane, int 
   v[0] = (short)t[r][k]; v[1] = (short)t[r][k + 1]; v[2] = (short)t[r][k + 2]; v[3] = (short)t[r][k + 3];
   return v;
 }
-// B operand from a row-major weight matrix W[n][k] (B[k][n] = W[n][k])
-__device__ __forceinline__ bf16x4 b_weightT(const uint16_t *W, int ldk, int lane, int n0, int k0, int nmax) {
-  const int n = n0 + (lane & 15), k = k0 + 4 * (lane >> 4);
-  bf16x4 v;
-  if (n < nmax) {
-    const uint16_t *p = W + n * ldk + k;
-    v[0] = (short)p[0]; v[1] = (short)p[1]; v[2] = (short)p[2]; v[3] = (short)p[3];
-  } else {
-    v[0] = v[1] = v[2] = v[3] = 0;
-  }
-  return v;
-}
-
 // Forward pass of one 16-row tile (rows past nrows are zero inputs).
 __device__ void tile_forward(TileMem &T, const float *X, int64_t row0, int nrows, const uint16_t *wb,
                              const float *master, int lane) {
@@ -405,30 +373,8 @@ __global__ __launch_bounds__(64) void features_kernel(DevMesh m, const double *a
     }
     if (lane == 0) {
       float *out = feat + k * 32;
-      const double iW = Wd > 0 ? 1.0 / Wd : 0.0;
-      out[0] = (float)aP;
-      for (int qi = 0; qi < 7; ++qi) {
-        const double t = (qi + 1) / 8.0 * (nvv - 1);
-        const int i = (int)floor(t);
-        const double fr = t - i;
-        const double val = (i + 1 >= nvv) ? L.sorted[i] : L.sorted[i] + fr * (L.sorted[i + 1] - L.sorted[i]);
-        out[1 + qi] = (float)((val - pmin) * iW);
-      }
-      out[8] = (float)((lsum / nvv - pmin) * iW);
-      out[9] = (float)Wd;
-      const double iA = 1.0 / s[0];
-      for (int c = 0; c < 3; ++c) out[10 + c] = (float)(s[1 + c] * iA);
-      for (int c = 0; c < 6; ++c) out[13 + c] = (float)(s[4 + c] * iA);
-      for (int c = 0; c < 6; ++c) out[19 + c] = (float)(s[10 + c] * iA);
-      out[25] = (float)(nf / 32.0);
-      if (s[17] > 0) {
-        out[26] = (float)(s[16] / s[17]);
-        out[27] = (float)amin;
-        out[28] = (float)amax;
-      } else {
-        out[26] = out[27] = out[28] = (float)aP;
-      }
-      out[29] = out[30] = out[31] = 0.f;
+      auto sorted = [&](int j) { return L.sorted[j]; };
+      for (int i = 0; i < 32; ++i) out[i] = feature(i, aP, sorted, nvv, lsum, pmin, Wd, s, amin, amax, nf);
       prange[2 * k] = pmin;
       prange[2 * k + 1] = Wd;
     }
@@ -568,6 +514,10 @@ extern "C" vofpc_status vofpc_mlp_train_step(vofpc_ctx ctx, vofpc_mlp M, const f
 }
 
 namespace vofpc {
+const uint16_t *mlp_weights_bf16(vofpc_mlp M) { return M->wb; }
+const float *mlp_params_f32(vofpc_mlp M) { return M->master; }
+int mlp_device(vofpc_mlp M) { return M->ctx->device; }
+
 vofpc_status launch_features(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed,
                              const int32_t *counts, int64_t cap, const vofpc_recon_opts *o, float *feat,
                              double *prange) {

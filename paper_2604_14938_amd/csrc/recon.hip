@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include "vofpc_internal.h"
+#include "mlp_core.h"
 
 namespace vofpc {
 
@@ -188,6 +189,11 @@ struct GroupMem {
   uint8_t pk[NL];                         // index of the position within its face
   uint8_t fsz[NF];
   uint8_t lv[NL];
+  // bracket network: face sums, input row and hidden activations
+  double nsum[20];
+  alignas(16) uint16_t nx[net::kIn];
+  alignas(16) uint16_t nh1[net::kHid];
+  alignas(16) uint16_t nh2[net::kHid];
 };
 
 struct CutRes {
@@ -206,6 +212,12 @@ struct ReconParams {
   double eps, tol_rel, iso;
   int max_iter, vertex_mode, fixed_iso, use_hint;
   int *queue;   // claim counter of the cells beyond the first grid-size ones
+  // bracket network run inside the kernel (null: none): BF16 weights, FP32
+  // parameters, half-width factor, optional outputs of the bracket
+  const uint16_t *net_wb;
+  const float *net_master;
+  double net_delta;
+  double *net_lo, *net_hi;
   vofpc_interface out;
 };
 
@@ -668,6 +680,112 @@ __device__ __forceinline__ void store_end(GM &L, int lane, int side, const CutRe
   }
 }
 
+// The bracket network's normalised isovalue for the staged cell: its 32
+// inputs from the staged vertex values and the cell's faces, then the
+// forward pass on MFMA.
+template <int NF, class GM>
+__device__ float net_guess(GM &L, int lane, const ReconParams &p, int64_t k, int P, double aP, int nv, int nf,
+                           int64_t f0, double pmin, double Wd) {
+  constexpr int W = 64;
+  const DevMesh &m = p.m;
+  const int64_t NFg = m.n_faces;
+  // face sums (see the feature definitions) into L.nsum
+  double amin = __builtin_inf(), amax = -__builtin_inf();
+  auto face = [&](int f, double &A, double &n0, double &n1, double &n2, double &aQ, bool &inner) {
+    const int fid = m.cell_face[f0 + f];
+    const double sg = (m.face_owner[fid] == P) ? 1.0 : -1.0;
+    const double S0 = sg * m.Sf[fid], S1 = sg * m.Sf[NFg + fid], S2 = sg * m.Sf[2 * NFg + fid];
+    A = sqrt(S0 * S0 + S1 * S1 + S2 * S2);
+    n0 = S0 / A; n1 = S1 / A; n2 = S2 / A;
+    const int q = m.cf_nbr[f0 + f];
+    inner = q >= 0;
+    aQ = inner ? p.alpha[q] : aP;
+  };
+  if constexpr (NF <= W) {
+    // one face per lane: each sum is reduced as soon as it is formed
+    double A = 0, n0 = 0, n1 = 0, n2 = 0, aQ = aP;
+    bool inner = false;
+    if (lane < nf) face(lane, A, n0, n1, n2, aQ, inner);
+    const double da = A * (aQ - aP);
+    if (inner) {
+      amin = aQ;
+      amax = aQ;
+    }
+    const bool row = nf <= 16;   // faces within the first row: DPP sums only
+    auto red = [&](int i, double v) {
+      v = row ? gsum<16>(v) : gsum<W>(v);
+      if (lane == 0) L.nsum[i] = v;
+    };
+    red(0, A);
+    red(1, da * n0); red(2, da * n1); red(3, da * n2);
+    red(4, da * n0 * n0); red(5, da * n1 * n1); red(6, da * n2 * n2);
+    red(7, da * n0 * n1); red(8, da * n0 * n2); red(9, da * n1 * n2);
+    red(10, A * n0 * n0); red(11, A * n1 * n1); red(12, A * n2 * n2);
+    red(13, A * n0 * n1); red(14, A * n0 * n2); red(15, A * n1 * n2);
+    red(16, inner ? aQ : 0.0);
+    red(17, inner ? 1.0 : 0.0);
+    amin = row ? readlane_d(gmin<16>(amin), 0) : gmin<W>(amin);
+    amax = row ? readlane_d(gmax<16>(amax), 0) : gmax<W>(amax);
+  } else {
+    double t[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) t[i] = 0.0;
+    for (int f = lane; f < nf; f += W) {
+      double A, n0, n1, n2, aQ;
+      bool inner;
+      face(f, A, n0, n1, n2, aQ, inner);
+      const double da = A * (aQ - aP);
+      const double o[6] = {n0 * n0, n1 * n1, n2 * n2, n0 * n1, n0 * n2, n1 * n2};
+      t[0] += A;
+      t[1] += da * n0; t[2] += da * n1; t[3] += da * n2;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        t[4 + c] += da * o[c];
+        t[10 + c] += A * o[c];
+      }
+      if (inner) {
+        t[16] += aQ;
+        t[17] += 1.0;
+        amin = fmin(amin, aQ);
+        amax = fmax(amax, aQ);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+      const double v = gsum<W>(t[i]);
+      if (lane == 0) L.nsum[i] = v;
+    }
+    amin = gmin<W>(amin);
+    amax = gmax<W>(amax);
+  }
+  // vertex values sorted by rank (ties by index) into the crossing-point
+  // scratch, which holds at least as many values as the cell has vertices
+  double *srt = &L.ept[0][0];
+  double lsum = 0.0;
+  for (int i = lane; i < nv; i += W) {
+    const double v = L.phi[i];
+    int r = 0;
+    for (int j = 0; j < nv; ++j) {
+      const double u = L.phi[j];
+      r += (u < v) || (u == v && j < i);
+    }
+    srt[r] = v;
+    lsum += v;
+  }
+  lsum = gsum<W>(lsum);
+  wave_sync();
+  if (lane < net::kIn) {
+    auto sorted = [&](int j) { return srt[j]; };
+    const float x = net::feature(lane, aP, sorted, nv, lsum, pmin, Wd, L.nsum, amin, amax, nf);
+    L.nx[lane] = net::to_bf16(x);
+  }
+  wave_sync();
+  const float u = net::row_forward(p.net_wb, p.net_master, L.nx, L.nh1, L.nh2, lane, [] { wave_sync(); });
+  wave_sync();
+  (void)k;
+  return u;
+}
+
 // One cell per wavefront (block of 64 lanes).
 template <int NV, int NF, int NL, int NCH>
 __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
@@ -837,7 +955,26 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
           // status records whether the root fell outside it
           bool hint = false, first = true;
           double hl = 0, hh = 0;
-          if (p.use_hint) {
+          if (p.net_wb && st == VOFPC_CELL_OK) {
+            const double Wd = pmax - pmin;
+            const float u = net_guess<NF>(L, lane, p, k, P, a, nv, nf, f0, pmin, Wd);
+            if (!isnan(u)) {
+              const double uc = u < 0.f ? 0.0 : (u > 1.f ? 1.0 : (double)u);
+              const double sh = pmin + uc * Wd, dl = p.net_delta * Wd;
+              hl = sh - dl;
+              hh = sh + dl;
+              if (lane == 0 && p.net_lo) {
+                p.net_lo[k] = hl;
+                p.net_hi[k] = hh;
+              }
+              hl = hl > pmin ? hl : pmin;
+              hh = hh < pmax ? hh : pmax;
+              hint = hl <= hh;
+            } else if (lane == 0 && p.net_lo) {
+              p.net_lo[k] = __builtin_nan("");
+              p.net_hi[k] = __builtin_nan("");
+            }
+          } else if (p.use_hint) {
             hl = p.hint_lo[k];
             hh = p.hint_hi[k];
             if (!isnan(hl) && !isnan(hh)) {
@@ -1078,7 +1215,8 @@ vofpc_status launch_t(vofpc_ctx ctx, const ReconParams &p, int64_t n_cells) {
 
 vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, const int32_t *mixed,
                                 const int32_t *counts, const vofpc_recon_opts *o, const double *hlo,
-                                const double *hhi, const vofpc_interface *out) {
+                                const double *hhi, const vofpc_interface *out, vofpc_mlp net, double delta,
+                                double *net_lo, double *net_hi) {
   VOFPC_REQUIRE(alpha && mixed && counts && o && out, VOFPC_E_INVALID_ARG, "reconstruct: null argument");
   VOFPC_REQUIRE(out->s && out->n && out->A && out->d && out->alpha_got && out->status && out->iters,
                 VOFPC_E_INVALID_ARG, "reconstruct: null output array");
@@ -1108,6 +1246,17 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   p.fixed_iso = o->fixed_iso ? 1 : 0;
   p.use_hint = (o->bracket == VOFPC_BRACKET_HINT) ? 1 : 0;
   p.queue = ctx->queue;
+  p.net_wb = net ? mlp_weights_bf16(net) : nullptr;
+  p.net_master = net ? mlp_params_f32(net) : nullptr;
+  p.net_delta = delta;
+  p.net_lo = net ? net_lo : nullptr;
+  p.net_hi = net ? net_hi : nullptr;
+  VOFPC_REQUIRE(!net || mlp_device(net) == ctx->device, VOFPC_E_STATE,
+                "reconstruct_learned: the network lives on another device");
+  VOFPC_REQUIRE(!net || (delta >= 0 && delta < 1e300), VOFPC_E_INVALID_ARG,
+                "reconstruct_learned: delta_scale must be finite and >= 0");
+  VOFPC_REQUIRE(!net || !p.use_hint, VOFPC_E_INVALID_ARG,
+                "reconstruct_learned: the network replaces hint brackets (use VOFPC_BRACKET_PLAIN)");
   p.out = *out;
   const int64_t nf = M->max_nf, nv = M->max_nv, nl = M->max_loop, ne = M->max_ne, fv = M->max_fv;
   VOFPC_REQUIRE(fv <= 64, VOFPC_E_MESH, "reconstruct: faces with more than 64 vertices are not supported");

@@ -109,9 +109,16 @@ namespace vofpc {
 // launchers (return VOFPC_OK or an error code with the message set)
 vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, double eps, int32_t *mixed,
                             int32_t *band, int32_t *counts);
+// net (optional): bracket network run inside the reconstruction, with
+// half-width factor delta; net_lo/net_hi (optional) receive its brackets
 vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, const int32_t *mixed,
                                 const int32_t *counts, const vofpc_recon_opts *o, const double *hlo,
-                                const double *hhi, const vofpc_interface *out);
+                                const double *hhi, const vofpc_interface *out, vofpc_mlp net = nullptr,
+                                double delta = 0.0, double *net_lo = nullptr, double *net_hi = nullptr);
+// device parameters of a network: BF16 weights and FP32 master copy
+const uint16_t *mlp_weights_bf16(vofpc_mlp M);
+const float *mlp_params_f32(vofpc_mlp M);
+int mlp_device(vofpc_mlp M);
 vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh m, const double *T, const double *Tb, double T_sat,
                          const double *alpha, const int32_t *band, const int32_t *counts, int32_t scope,
                          int32_t variant, double *grad, int32_t *status);

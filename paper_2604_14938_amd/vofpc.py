@@ -56,7 +56,7 @@ class StepArgs(ctypes.Structure):
     _fields_ = [("alpha", P), ("T", P), ("T_bface", P), ("T_sat", D), ("k_l", D), ("k_v", D), ("h_lv", D),
                 ("opts", ReconOpts), ("hint_lo", P), ("hint_hi", P), ("mixed_idx", P), ("band_idx", P),
                 ("counts", P), ("itf", CInterface), ("gradT", P), ("grad_status", P), ("mdot", P), ("Qdot", P),
-                ("mlp", P), ("delta_scale", D), ("features", P), ("phi_range", P)]
+                ("mlp", P), ("delta_scale", D)]
 
 
 def _load():
@@ -92,6 +92,7 @@ def _load():
         "vofpc_mlp_train_step": ([P, P, P, P, I64, ctypes.c_float, P], ctypes.c_int),
         "vofpc_features": ([P, P, P, P, P, P, P, P, I64], ctypes.c_int),
         "vofpc_mlp_bracket": ([P, P, P, P, P, I64, D, P, P], ctypes.c_int),
+        "vofpc_reconstruct_learned": ([P, P, P, P, P, P, P, D, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -255,6 +256,15 @@ def reconstruct(ctx: Context, mesh: Mesh, alpha, mixed_idx, counts, itf: Interfa
                                  _ptr(hint_lo), _ptr(hint_hi), ctypes.byref(ci)), "vofpc_reconstruct")
 
 
+def reconstruct_learned(ctx: Context, mesh: Mesh, alpha, mixed_idx, counts, itf: Interface, mlp: "Mlp",
+                        delta_scale: float, opts: ReconOpts | None = None, hint_lo=None, hint_hi=None) -> None:
+    opts = opts or recon_opts()
+    ci = itf.c()
+    _check(lib.vofpc_reconstruct_learned(ctx.h, mesh.h, _ptr(alpha), _ptr(mixed_idx), _ptr(counts), ctypes.byref(opts),
+                                         mlp.h, float(delta_scale), _ptr(hint_lo), _ptr(hint_hi), ctypes.byref(ci)),
+           "vofpc_reconstruct_learned")
+
+
 def grad_T(ctx: Context, mesh: Mesh, T, T_bface, T_sat: float, alpha, band_idx, counts, grad, status=None,
            scope: int = SCOPE_BAND, variant: int = GRAD_MODIFIED) -> None:
     _check(lib.vofpc_grad_T(ctx.h, mesh.h, _ptr(T), _ptr(T_bface), float(T_sat), _ptr(alpha), _ptr(band_idx),
@@ -324,8 +334,8 @@ def features(ctx: Context, mesh: Mesh, alpha, mixed_idx, counts, feat, phi_range
 
 class StepBuffers:
     """Every device buffer of one step, sized for a mesh (capacity n_cells).
-    With `mlp` set the step runs the learned form (features, network bracket,
-    reconstruction from the bracket)."""
+    With `mlp` set the step runs the learned form (the reconstruction kernel
+    runs the network; hint_lo/hint_hi receive its brackets)."""
 
     def __init__(self, ctx: Context, mesh: Mesh, alpha, T, T_bface, T_sat, k_l, k_v, h_lv,
                  opts: ReconOpts | None = None, hint_lo=None, hint_hi=None, mlp: "Mlp | None" = None,
@@ -347,10 +357,7 @@ class StepBuffers:
         self.Qdot = torch.zeros(N, dtype=torch.float64, device=dev)
         self.mlp = mlp
         self.delta_scale = float(delta_scale)
-        self.features = self.phi_range = None
         if mlp is not None:
-            self.features = torch.zeros(N, 32, dtype=torch.float32, device=dev)
-            self.phi_range = torch.zeros(N, 2, dtype=torch.float64, device=dev)
             if self.hint_lo is None:
                 self.hint_lo = torch.zeros(N, dtype=torch.float64, device=dev)
                 self.hint_hi = torch.zeros(N, dtype=torch.float64, device=dev)
@@ -367,7 +374,6 @@ class StepBuffers:
         a.mdot, a.Qdot = _ptr(self.mdot), _ptr(self.Qdot)
         a.mlp = self.mlp.h if self.mlp is not None else None
         a.delta_scale = self.delta_scale
-        a.features, a.phi_range = _ptr(self.features), _ptr(self.phi_range)
         return a
 
 

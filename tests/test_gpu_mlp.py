@@ -193,3 +193,42 @@ def test_learned_step_gives_the_plain_results(V, which):
         assert fb.mean() < 0.2
     run.close()
     mlp.close()
+
+
+def test_fused_network_bracket_matches_the_separate_kernels(V):
+    """The reconstruction kernel's in-wave features and forward pass give the
+    brackets of the features kernel followed by the bracket kernel (up to the
+    summation order of the feature sums)."""
+    import torch
+    from paper_2604_14938_amd import runner
+    w = _weights()
+    if w is None:
+        pytest.skip("no trained weights")
+    params, dscale, _ = w
+    wl = workloads.voronoi_bubble(n=12, seed=7, r=0.3)
+    _say("fused vs separate network bracket vor12")
+    ctx = V.Context(0, stream=torch.cuda.Stream())
+    mlp = V.Mlp(ctx)
+    mlp.set_params(params)
+    run = runner.PathRun(wl, ctx=ctx, mlp=mlp, delta_scale=dscale)
+    run.step()
+    b = run.buf
+    N = wl.mesh.n_cells
+    feat = torch.zeros(N, 32, dtype=torch.float32, device="cuda")
+    pr = torch.zeros(N, 2, dtype=torch.float64, device="cuda")
+    hl = torch.zeros(N, dtype=torch.float64, device="cuda")
+    hh = torch.zeros(N, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    V.features(ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, feat, pr)
+    mlp.bracket(feat, pr, b.counts, N, dscale, hl, hh)
+    torch.cuda.synchronize()
+    M = int(b.counts[0].item())
+    W = pr[:M, 1].cpu().numpy()
+    ok = W > 1e-12
+    d_lo = np.abs(b.hint_lo[:M].cpu().numpy() - hl[:M].cpu().numpy())[ok] / W[ok]
+    d_hi = np.abs(b.hint_hi[:M].cpu().numpy() - hh[:M].cpu().numpy())[ok] / W[ok]
+    assert ok.sum() > 0.9 * M
+    assert np.median(d_lo) <= 1e-6 and np.median(d_hi) <= 1e-6
+    assert np.percentile(d_lo, 99) <= 1e-3 and np.percentile(d_hi, 99) <= 1e-3
+    run.close()
+    mlp.close()
