@@ -148,6 +148,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--form", choices=("both", "plain", "learned"), default="both",
+                    help="which forms to time (profiling runs time one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -220,12 +222,12 @@ def main() -> int:
         run.close()
         return res, ms, statistics.median(per), wall, recon_ms
 
-    plain, ms_p, med_p, wall_p, rms_p = time_form()
-    M = plain["n_mixed"]
-    log(f"plain step: {ms_p * 1e3:.1f} us mean, {med_p * 1e3:.1f} us median (wall {wall_p:.3f} s); "
-        f"reconstruction {rms_p * 1e3:.1f} us")
-    learned = None
-    if os.path.exists(train.DEFAULT_WEIGHTS):
+    plain = learned = None
+    if args.form in ("both", "plain"):
+        plain, ms_p, med_p, wall_p, rms_p = time_form()
+        log(f"plain step: {ms_p * 1e3:.1f} us mean, {med_p * 1e3:.1f} us median (wall {wall_p:.3f} s); "
+            f"reconstruction {rms_p * 1e3:.1f} us")
+    if args.form in ("both", "learned") and os.path.exists(train.DEFAULT_WEIGHTS):
         params, dscale, tinfo = train.load()
         ctx_m = V.Context(0, stream=torch.cuda.Stream())
         mlp = V.Mlp(ctx_m)
@@ -233,19 +235,23 @@ def main() -> int:
         learned, ms_l, med_l, wall_l, rms_l = time_form(mlp, dscale)
         log(f"learned step: {ms_l * 1e3:.1f} us mean, {med_l * 1e3:.1f} us median (wall {wall_l:.3f} s); "
             f"reconstruction {rms_l * 1e3:.1f} us")
+    if plain is None and learned is None:
+        print(json.dumps({"error": "no trained weights for the learned form"}))
+        return 2
     head = learned if learned is not None else plain
+    M = head["n_mixed"]
     ms_per_step = ms_l if learned is not None else ms_p
     recon_ms = rms_l if learned is not None else rms_p
     form = "learned" if learned is not None else "plain"
     ok = head["status"] != 1
     parity_alpha = float(np.abs(head["alpha_got"][head["status"] == 0] -
                                 wl.alpha[head["mixed_idx"][head["status"] == 0]]).max(initial=0))
-    mixed = plain["mixed_idx"]
+    mixed = head["mixed_idx"]
     rb = recon_bytes(wl.mesh, mixed)
     if learned is not None:
         cfo = wl.mesh.cell_face_off
         rb += int((cfo[mixed + 1] - cfo[mixed]).sum()) * (4 + 4 + 24) + 6 * 6532   # faces read by the features, weights
-    sb = step_bytes(wl.mesh, mixed, plain["band_idx"], rb)
+    sb = step_bytes(wl.mesh, mixed, head["band_idx"], rb)
     achieved = rb / (recon_ms * 1e-3) / 1e9
     log(f"{form} reconstruction kernel: {recon_ms * 1e3:.1f} us, {rb / 1e6:.2f} MB algorithmic -> {achieved:.1f} GB/s")
     cfg = {
@@ -253,29 +259,34 @@ def main() -> int:
                     "(seed 2), vapour bubble r=0.25 at the centre, T_sat + 1.25 K erf((rho-0.25)/0.05) outside",
         "n_cells": int(wl.mesh.n_cells),
         "n_mixed": int(M),
-        "n_band": int(plain["n_band"]),
+        "n_band": int(head["n_band"]),
         "form": form,
         "max_abs_dalpha_vs_input": parity_alpha,
         "step_algorithmic_bytes": sb,
         "step_GBps": sb / (ms_per_step * 1e-3) / 1e9,
-        "plain": {"cells_per_s": M / (ms_p * 1e-3), "ms_per_step": ms_p, "recon_us": rms_p * 1e3,
-                  "evals_per_cell_mean": float(plain["iters"].mean()),
-                  "evals_per_cell_p99": float(np.percentile(plain["iters"], 99))},
     }
+    if plain is not None:
+        cfg["plain"] = {"cells_per_s": M / (ms_p * 1e-3), "ms_per_step": ms_p, "recon_us": rms_p * 1e3,
+                        "evals_per_cell_mean": float(plain["iters"].mean()),
+                        "evals_per_cell_p99": float(np.percentile(plain["iters"], 99))}
     if learned is not None:
-        same = learned["status"] == plain["status"]
-        both = same & (plain["status"] != 1)
         cfg["learned"] = {
             "cells_per_s": M / (ms_l * 1e-3), "ms_per_step": ms_l, "recon_us": rms_l * 1e3,
             "evals_per_cell_mean": float(learned["iters"].mean()),
             "evals_per_cell_p99": float(np.percentile(learned["iters"], 99)),
             "fallback_rate": float(np.mean(learned["status"] == 2)),
+            "delta_scale": dscale, "weights_sigma_val": tinfo.get("sigma_val"),
+        }
+    if learned is not None and plain is not None:
+        same = (learned["status"] == plain["status"]) | ((learned["status"] == 2) & (plain["status"] == 0))
+        both = same & (plain["status"] != 1)
+        cfg["learned"].update({
             "speedup_vs_plain": ms_p / ms_l,
+            "statuses_agree_fraction": float(np.mean(same)),
             "max_abs_dalpha_vs_plain": float(np.abs(learned["alpha_got"] - plain["alpha_got"])[both].max(initial=0)),
             "bitwise_equal_fraction": float(np.mean((learned["alpha_got"] == plain["alpha_got"]) &
                                                     (learned["A"] == plain["A"]))),
-            "delta_scale": dscale, "weights_sigma_val": tinfo.get("sigma_val"),
-        }
+        })
     out = {
         "metric": METRIC,
         "value": M / (ms_per_step * 1e-3),

@@ -7,7 +7,7 @@
 
 namespace vofpc {
 
-constexpr int kCompactBlock = 1024;
+constexpr int kCompactBlock = kCompactBlockCells;
 constexpr int kWaves = kCompactBlock / 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }

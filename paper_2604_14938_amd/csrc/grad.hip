@@ -2,14 +2,15 @@
 // modification of Sec. 2.4.4) and the mass transfer rate (Eq. mass_transfer,
 // Eq. latent_source).
 //
-// One thread per cell.  The gradient gathers, for every face of the cell, the
-// neighbour centroid, alpha and T (or the boundary face centroid and value),
-// so the least-squares matrix is accumulated from data the right-hand side
-// needs anyway; cells without a crossing face may instead use the stored
-// inverse (VOFPC_SCOPE_ALL).
+// Sixteen lanes per cell, one face per lane.  The gradient gathers, for every
+// face of the cell, the neighbour centroid, alpha and T (or the boundary face
+// centroid and value), so the least-squares matrix is accumulated from data
+// the right-hand side needs anyway; cells without a crossing face may instead
+// use the stored inverse (VOFPC_SCOPE_ALL).
 #include <hip/hip_runtime.h>
 
 #include "vofpc_internal.h"
+#include "wave_ops.h"
 
 namespace vofpc {
 
@@ -23,7 +24,11 @@ struct GradParams {
   int32_t *status;
 };
 
-__device__ __forceinline__ void grad_cell(const GradParams &p, int P) {
+constexpr int kGradLanes = 16;   // lanes per cell (one DPP row)
+
+// Gradient of cell P by the 16 lanes of one row: lane j takes faces j,
+// j+16, ...; the least-squares sums are reduced over the row.
+__device__ __forceinline__ void grad_cell(const GradParams &p, int P, int j) {
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells, NF = m.n_faces;
   const double xP0 = m.xc[P], xP1 = m.xc[N + P], xP2 = m.xc[2 * N + P];
@@ -31,8 +36,9 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P) {
   const bool modify = p.variant != VOFPC_GRAD_STANDARD;
   const bool printed = p.variant == VOFPC_GRAD_PRINTED;
   double xx = 0, yy = 0, zz = 0, xy = 0, xz = 0, yz = 0, b0 = 0, b1 = 0, b2 = 0;
-  bool crossed = false;
-  for (int64_t i = m.cell_face_off[P]; i < m.cell_face_off[P + 1]; ++i) {
+  int crossed = 0;
+  const int64_t i1 = m.cell_face_off[P + 1];
+  for (int64_t i = m.cell_face_off[P] + j; i < i1; i += kGradLanes) {
     const int q = m.cf_nbr[i];
     double r0, r1, r2, val;
     if (q >= 0) {
@@ -44,7 +50,7 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P) {
         const double t = printed ? fabs(aQ - 0.5) / fabs(aP - aQ) : (aP - 0.5) / (aP - aQ);
         r0 *= t; r1 *= t; r2 *= t;
         val = p.T_sat;
-        crossed = true;
+        crossed = 1;
       }
     } else if (q == -1) {
       const int f = m.cell_face[i];
@@ -57,6 +63,11 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P) {
     xx += r0 * r0; yy += r1 * r1; zz += r2 * r2; xy += r0 * r1; xz += r0 * r2; yz += r1 * r2;
     b0 += r0 * dv; b1 += r1 * dv; b2 += r2 * dv;
   }
+  xx = gsum<kGradLanes>(xx); yy = gsum<kGradLanes>(yy); zz = gsum<kGradLanes>(zz);
+  xy = gsum<kGradLanes>(xy); xz = gsum<kGradLanes>(xz); yz = gsum<kGradLanes>(yz);
+  b0 = gsum<kGradLanes>(b0); b1 = gsum<kGradLanes>(b1); b2 = gsum<kGradLanes>(b2);
+  crossed = gsum_i<kGradLanes>(crossed);
+  if (j != 0) return;
   double g0, g1, g2;
   int st = VOFPC_CELL_OK;
   if (p.scope == VOFPC_SCOPE_ALL && !crossed) {
@@ -88,12 +99,16 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P) {
   if (p.status) p.status[P] = st;
 }
 
+// A block of 256 lanes serves 16 cells at a time; every lane of a row
+// iterates the same cells, so the row's reductions see all its lanes.
 __global__ __launch_bounds__(256) void grad_kernel(GradParams p) {
   const int64_t n = (p.scope == VOFPC_SCOPE_ALL) ? p.m.n_cells : (int64_t)p.counts[1];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
+  constexpr int kCellsPerBlock = 256 / kGradLanes;
+  const int j = threadIdx.x % kGradLanes;
+  const int64_t stride = (int64_t)gridDim.x * kCellsPerBlock;
+  for (int64_t k = blockIdx.x * (int64_t)kCellsPerBlock + threadIdx.x / kGradLanes; k < n; k += stride) {
     const int P = (p.scope == VOFPC_SCOPE_ALL) ? (int)k : p.band[k];
-    grad_cell(p, P);
+    grad_cell(p, P, j);
   }
 }
 
@@ -113,7 +128,7 @@ vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh M, const double *T, const dou
   p.scope = scope; p.variant = variant;
   p.grad = grad; p.status = status;
   const int64_t N = M->d.n_cells;
-  int64_t grid = (N + 255) / 256;
+  int64_t grid = (N + 15) / 16;
   const int64_t cap = (int64_t)ctx->n_cu * 16;
   if (grid > cap) grid = cap;
   grad_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(p);

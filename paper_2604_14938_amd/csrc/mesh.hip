@@ -339,7 +339,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   COPY(Sf, (const double *)nullptr, 3 * NF, double);
   COPY(xf, (const double *)nullptr, 3 * NF, double);
   COPY(ginv, (const double *)nullptr, 6 * N, double);
-  M->n_blk = (N + 1023) / 1024;
+  M->n_blk = (N + kCompactBlockCells - 1) / kCompactBlockCells;
   {
     uint8_t *fl = nullptr;
     int32_t *bc = nullptr, *bo = nullptr;

@@ -74,6 +74,9 @@ struct DevMesh {
 
 }  // namespace vofpc
 
+// cells per block of the compaction kernels (sizes a mesh's block arrays)
+constexpr int kCompactBlockCells = 256;
+
 struct vofpc_ctx_s {
   int device;
   hipStream_t stream;
