@@ -118,6 +118,14 @@ typedef struct {
  * cell values to vertices.  Synchronises the context stream.  Returns
  * VOFPC_E_MESH for inconsistent topology, open or inverted cells. */
 vofpc_status vofpc_mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *desc, vofpc_mesh *out);
+/* Disjoint union of n uploaded meshes (multi-instance batches, several
+ * meshes in one step): cells, faces and vertices of mesh i follow those of
+ * meshes 0..i-1 in order, ids and offsets shifted accordingly; geometry is
+ * copied, not recomputed.  Fields over the union are the per-mesh fields laid
+ * end to end (vector fields per component: [3][total]).  The inputs stay
+ * valid and unchanged; all must live on the context's device.  Synchronises
+ * the context stream.  Totals must fit in int32. */
+vofpc_status vofpc_mesh_concat(vofpc_ctx ctx, const vofpc_mesh *meshes, int32_t n, vofpc_mesh *out);
 /* Free a mesh and its device memory.  NULL is accepted. */
 vofpc_status vofpc_mesh_free(vofpc_mesh mesh);
 /* info[0..7] = n_cells, n_faces, n_verts, max faces per cell, max vertices

@@ -357,6 +357,8 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   }
 #undef COPY
   M->max_nf = max_nf; M->max_nv = max_nv; M->max_fv = max_fv; M->max_ne = max_ne; M->max_loop = max_loop;
+  M->ncf = ncf; M->nfv = nfv; M->ncv = (int64_t)cv_gid.size(); M->ncl = (int64_t)cl_lv.size();
+  M->nvc = (int64_t)vc_cell.size();
 
   hipStream_t s = ctx->stream;
   const int B = 256;
@@ -378,7 +380,157 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   return VOFPC_OK;
 }
 
+// ------------------------------------------------------------- concatenation
+// dst[i] = src[i] + add (mode 1), + add where src >= 0 (mode 2), or a copy (0)
+template <class T>
+__global__ __launch_bounds__(256) void concat_copy_kernel(T *dst, const T *src, int64_t n, int64_t add, int mode) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const T v = src[i];
+    dst[i] = (mode == 1 || (mode == 2 && v >= 0)) ? (T)(v + add) : v;
+  }
+}
+
+namespace {
+template <class T>
+vofpc_status concat_copy(hipStream_t s, T *dst, const T *src, int64_t n, int64_t add, int mode) {
+  if (n <= 0) return VOFPC_OK;
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  concat_copy_kernel<T><<<(unsigned)g, 256, 0, s>>>(dst, src, n, add, mode);
+  VOFPC_HIP(hipGetLastError());
+  return VOFPC_OK;
+}
+}  // namespace
+
+vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_mesh *out) {
+  VOFPC_REQUIRE(ctx && ms && out && n >= 1, VOFPC_E_INVALID_ARG, "mesh_concat: bad argument");
+  int64_t N = 0, NF = 0, NV = 0, ncf = 0, nfv = 0, ncv = 0, ncl = 0, nvc = 0;
+  int64_t mx[5] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    const vofpc_mesh a = ms[i];
+    VOFPC_REQUIRE(a, VOFPC_E_INVALID_ARG, "mesh_concat: null mesh in the list");
+    VOFPC_REQUIRE(a->ctx && a->ctx->device == ctx->device, VOFPC_E_STATE, "mesh_concat: mesh on another device");
+    N += a->d.n_cells; NF += a->d.n_faces; NV += a->d.n_verts;
+    ncf += a->ncf; nfv += a->nfv; ncv += a->ncv; ncl += a->ncl; nvc += a->nvc;
+    mx[0] = std::max(mx[0], a->max_nf); mx[1] = std::max(mx[1], a->max_nv); mx[2] = std::max(mx[2], a->max_fv);
+    mx[3] = std::max(mx[3], a->max_ne); mx[4] = std::max(mx[4], a->max_loop);
+  }
+  VOFPC_REQUIRE(N < INT32_MAX && NF < INT32_MAX && NV < INT32_MAX && ncf < INT32_MAX && nvc < INT32_MAX,
+                VOFPC_E_INVALID_ARG, "mesh_concat: totals must fit in int32");
+  VOFPC_HIP(hipSetDevice(ctx->device));
+  vofpc_mesh M = new (std::nothrow) vofpc_mesh_s();
+  VOFPC_REQUIRE(M, VOFPC_E_OOM, "mesh_concat: host allocation failed");
+  M->ctx = ctx;
+  DevMesh &m = M->d;
+  m.n_cells = N; m.n_faces = NF; m.n_verts = NV;
+  vofpc_status st = VOFPC_OK;
+#define ALLOC(field, n_, T)                                        \
+  do {                                                             \
+    T *p_ = nullptr;                                               \
+    st = dev_copy<T>(M, (const T *)nullptr, (size_t)(n_), &p_);    \
+    if (st) { vofpc_mesh_free(M); return st; }                     \
+    m.field = p_;                                                  \
+  } while (0)
+  ALLOC(cell_face_off, N + 1, int64_t);
+  ALLOC(cell_face, ncf, int32_t);
+  ALLOC(face_vert_off, NF + 1, int64_t);
+  ALLOC(face_vert, nfv, int32_t);
+  ALLOC(face_owner, NF, int32_t);
+  ALLOC(face_neigh, NF, int32_t);
+  ALLOC(face_bc, NF, int8_t);
+  ALLOC(xyz, 3 * NV, double);
+  ALLOC(cf_nbr, ncf, int32_t);
+  ALLOC(cf_loff, ncf, uint16_t);
+  ALLOC(cf_lsz, ncf, uint8_t);
+  ALLOC(cv_off, N + 1, int64_t);
+  ALLOC(cv_gid, ncv, int32_t);
+  ALLOC(cl_off, N + 1, int64_t);
+  ALLOC(cl_lv, ncl, uint8_t);
+  ALLOC(cl_eid, ncl, uint16_t);
+  ALLOC(cl_info, ncl, uint32_t);
+  ALLOC(vc_off, NV + 1, int64_t);
+  ALLOC(vc_cell, nvc, int32_t);
+  ALLOC(vc_w, nvc, double);
+  ALLOC(vc_wmean, nvc, double);
+  ALLOC(V, N, double);
+  ALLOC(xc, 3 * N, double);
+  ALLOC(Sf, 3 * NF, double);
+  ALLOC(xf, 3 * NF, double);
+  ALLOC(ginv, 6 * N, double);
+#undef ALLOC
+  M->n_blk = (N + kCompactBlockCells - 1) / kCompactBlockCells;
+  {
+    uint8_t *fl = nullptr;
+    int32_t *bc = nullptr, *bo = nullptr;
+    if ((st = dev_copy<uint8_t>(M, nullptr, N, &fl)) || (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bc)) ||
+        (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bo))) {
+      vofpc_mesh_free(M);
+      return st;
+    }
+    M->flags = fl; M->blk_cnt = bc; M->blk_off = bo;
+  }
+  M->max_nf = mx[0]; M->max_nv = mx[1]; M->max_fv = mx[2]; M->max_ne = mx[3]; M->max_loop = mx[4];
+  M->ncf = ncf; M->nfv = nfv; M->ncv = ncv; M->ncl = ncl; M->nvc = nvc;
+  hipStream_t s = ctx->stream;
+  int64_t bN = 0, bF = 0, bV = 0, bcf = 0, bfv = 0, bcv = 0, bcl = 0, bvc = 0;
+#define CC(dst, src, cnt, add, mode)                                                        \
+  do {                                                                                      \
+    st = concat_copy(s, (dst), (src), (cnt), (add), (mode));                                \
+    if (st) { vofpc_mesh_free(M); return st; }                                              \
+  } while (0)
+  for (int i = 0; i < n; ++i) {
+    const DevMesh &a = ms[i]->d;
+    const vofpc_mesh_s &A = *ms[i];
+    const int64_t n_ = a.n_cells, nf_ = a.n_faces, nv_ = a.n_verts;
+    // offset arrays (n+1 entries; the last entry of one mesh equals the first of the next)
+    CC((int64_t *)m.cell_face_off + bN, a.cell_face_off, n_ + 1, bcf, 1);
+    CC((int64_t *)m.face_vert_off + bF, a.face_vert_off, nf_ + 1, bfv, 1);
+    CC((int64_t *)m.cv_off + bN, a.cv_off, n_ + 1, bcv, 1);
+    CC((int64_t *)m.cl_off + bN, a.cl_off, n_ + 1, bcl, 1);
+    CC((int64_t *)m.vc_off + bV, a.vc_off, nv_ + 1, bvc, 1);
+    // ids
+    CC((int32_t *)m.cell_face + bcf, a.cell_face, A.ncf, bF, 1);
+    CC((int32_t *)m.face_vert + bfv, a.face_vert, A.nfv, bV, 1);
+    CC((int32_t *)m.face_owner + bF, a.face_owner, nf_, bN, 1);
+    CC((int32_t *)m.face_neigh + bF, a.face_neigh, nf_, bN, 2);
+    CC((int32_t *)m.cf_nbr + bcf, a.cf_nbr, A.ncf, bN, 2);
+    CC((int32_t *)m.cv_gid + bcv, a.cv_gid, A.ncv, bV, 1);
+    CC((int32_t *)m.vc_cell + bvc, a.vc_cell, A.nvc, bN, 1);
+    // plain copies
+    CC((int8_t *)m.face_bc + bF, a.face_bc, nf_, 0, 0);
+    CC((uint16_t *)m.cf_loff + bcf, a.cf_loff, A.ncf, 0, 0);
+    CC((uint8_t *)m.cf_lsz + bcf, a.cf_lsz, A.ncf, 0, 0);
+    CC((uint8_t *)m.cl_lv + bcl, a.cl_lv, A.ncl, 0, 0);
+    CC((uint16_t *)m.cl_eid + bcl, a.cl_eid, A.ncl, 0, 0);
+    CC((uint32_t *)m.cl_info + bcl, a.cl_info, A.ncl, 0, 0);
+    CC((double *)m.vc_w + bvc, a.vc_w, A.nvc, 0, 0);
+    CC((double *)m.vc_wmean + bvc, a.vc_wmean, A.nvc, 0, 0);
+    CC((double *)m.V + bN, a.V, n_, 0, 0);
+    // structure-of-arrays fields, one component at a time
+    for (int c = 0; c < 3; ++c) {
+      CC((double *)m.xyz + c * NV + bV, a.xyz + c * nv_, nv_, 0, 0);
+      CC((double *)m.xc + c * N + bN, a.xc + c * n_, n_, 0, 0);
+      CC((double *)m.Sf + c * NF + bF, a.Sf + c * nf_, nf_, 0, 0);
+      CC((double *)m.xf + c * NF + bF, a.xf + c * nf_, nf_, 0, 0);
+    }
+    for (int c = 0; c < 6; ++c) CC((double *)m.ginv + c * N + bN, a.ginv + c * n_, n_, 0, 0);
+    bN += n_; bF += nf_; bV += nv_;
+    bcf += A.ncf; bfv += A.nfv; bcv += A.ncv; bcl += A.ncl; bvc += A.nvc;
+  }
+#undef CC
+  VOFPC_HIP(hipStreamSynchronize(s));
+  *out = M;
+  return VOFPC_OK;
+}
+
 }  // namespace vofpc
+
+extern "C" vofpc_status vofpc_mesh_concat(vofpc_ctx ctx, const vofpc_mesh *meshes, int32_t n, vofpc_mesh *out) {
+  vofpc::clear_error();
+  if (out) *out = nullptr;
+  return vofpc::mesh_concat(ctx, meshes, n, out);
+}
 
 extern "C" vofpc_status vofpc_mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *desc, vofpc_mesh *out) {
   vofpc::clear_error();

@@ -91,6 +91,8 @@ struct vofpc_mesh_s {
   vofpc_ctx ctx;
   vofpc::DevMesh d;
   int64_t max_nf, max_nv, max_fv, max_ne, max_loop;
+  // array lengths: cell_face, face_vert, cv_gid, cl_lv (loop positions), vc_cell
+  int64_t ncf, nfv, ncv, ncl, nvc;
   int64_t bytes;
   // scratch for compaction (owned by the mesh; calls on one mesh must not
   // overlap in time)

@@ -16,12 +16,21 @@ class PathRun:
     """Device-resident inputs and buffers of one workload, ready to step."""
 
     def __init__(self, wl, device: int = 0, opts: V.ReconOpts | None = None, ctx: V.Context | None = None,
-                 hint_lo=None, hint_hi=None, mlp: "V.Mlp | None" = None, delta_scale: float = 0.0):
+                 hint_lo=None, hint_hi=None, mlp: "V.Mlp | None" = None, delta_scale: float = 0.0,
+                 parts: list | None = None):
+        """`parts`: the meshes whose disjoint union is wl.mesh; each is uploaded
+        on its own and the library concatenates them on the device."""
         self.dev = torch.device("cuda", device)
         # a stream of its own (default priority): graph capture needs a
         # non-null stream
         self.ctx = ctx or V.Context(device, stream=torch.cuda.Stream(self.dev))
-        self.mesh = V.Mesh(self.ctx, wl.mesh)
+        if parts:
+            ups = [V.Mesh(self.ctx, m) for m in parts]
+            self.mesh = V.Mesh.concat(self.ctx, ups)
+            for u in ups:
+                u.close()
+        else:
+            self.mesh = V.Mesh(self.ctx, wl.mesh)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.alpha = torch.as_tensor(np.ascontiguousarray(wl.alpha), **f64)
         self.T = torch.as_tensor(np.ascontiguousarray(wl.T), **f64)

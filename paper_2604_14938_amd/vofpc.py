@@ -93,6 +93,7 @@ def _load():
         "vofpc_features": ([P, P, P, P, P, P, P, P, I64], ctypes.c_int),
         "vofpc_mlp_bracket": ([P, P, P, P, P, I64, D, P, P], ctypes.c_int),
         "vofpc_reconstruct_learned": ([P, P, P, P, P, P, P, D, P, P, P], ctypes.c_int),
+        "vofpc_mesh_concat": ([P, P, ctypes.c_int32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -162,8 +163,13 @@ class Mesh:
     """A mesh uploaded to the device; built from any object with the CSR
     attributes of :class:`vofpc_mesh_desc` (host numpy arrays)."""
 
-    def __init__(self, ctx: Context, m):
+    def __init__(self, ctx: Context, m, _handle=None):
         self.ctx = ctx
+        if _handle is not None:   # built by the library (concat)
+            self.h = _handle
+            info = self.info()
+            self.n_cells, self.n_faces, self.n_verts = info["n_cells"], info["n_faces"], info["n_verts"]
+            return
         arrs = dict(
             cfo=np.ascontiguousarray(m.cell_face_off, np.int64), cf=np.ascontiguousarray(m.cell_face, np.int32),
             fvo=np.ascontiguousarray(m.face_vert_off, np.int64), fv=np.ascontiguousarray(m.face_vert, np.int32),
@@ -178,6 +184,14 @@ class Mesh:
         _check(lib.vofpc_mesh_upload(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "vofpc_mesh_upload")
         self.h = h
         self.n_cells, self.n_faces, self.n_verts = int(m.n_cells), int(m.n_faces), int(m.n_verts)
+
+    @classmethod
+    def concat(cls, ctx: Context, meshes: list) -> "Mesh":
+        """Disjoint union of uploaded meshes (see vofpc_mesh_concat)."""
+        arr = (P * len(meshes))(*[m.h for m in meshes])
+        h = P()
+        _check(lib.vofpc_mesh_concat(ctx.h, arr, len(meshes), ctypes.byref(h)), "vofpc_mesh_concat")
+        return cls(ctx, None, _handle=h)
 
     def info(self) -> dict:
         a = (ctypes.c_int64 * 8)()

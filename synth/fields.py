@@ -207,15 +207,42 @@ def radial_erf_T(points: np.ndarray, c, r0: float, width: float, dT: float, T_sa
 
 
 def nearest_bubble_T(points: np.ndarray, spheres: np.ndarray, slopes: np.ndarray, T_sat: float,
-                     chunk: int = 1 << 16) -> np.ndarray:
+                     chunk: int = 1 << 16, k: int = 8) -> np.ndarray:
     """T_sat inside any bubble, else T_sat + g_b (|x - c_b| - r_b) for the bubble b
-    whose surface is nearest."""
+    whose surface is nearest (ties: lowest bubble index).
+
+    The k bubbles with the nearest centres are tried first; a point whose best
+    surface distance among them is not provably the global minimum (every other
+    bubble is at least |x - c_(k)| - r_max away) is checked against all."""
+    spheres = np.asarray(spheres, float).reshape(-1, 4)
+    S = len(spheres)
     out = np.empty(len(points))
+    if S == 0:
+        out[:] = T_sat
+        return out
+    kk = min(k, S)
+    from scipy.spatial import cKDTree
+    tree = cKDTree(spheres[:, :3])
+    rmax = spheres[:, 3].max()
     for s in range(0, len(points), chunk):
         p = points[s:s + chunk]
-        d = np.linalg.norm(p[:, None, :] - spheres[None, :, :3], axis=2) - spheres[None, :, 3]
-        b = np.argmin(d, 1)
-        dist = d[np.arange(len(p)), b]
+        dc, ic = tree.query(p, k=kk)
+        if kk == 1:
+            dc, ic = dc[:, None], ic[:, None]
+        order = np.argsort(ic, axis=1, kind="stable")        # candidates by bubble index
+        ic = np.take_along_axis(ic, order, 1)
+        d = np.linalg.norm(p[:, None, :] - spheres[ic, :3], axis=2) - spheres[ic, 3]
+        j = np.argmin(d, 1)
+        b = ic[np.arange(len(p)), j]
+        dist = d[np.arange(len(p)), j]
+        if kk < S:
+            unsure = np.nonzero(dist > dc.max(1) - rmax)[0]
+            if len(unsure):
+                q = p[unsure]
+                dd = np.linalg.norm(q[:, None, :] - spheres[None, :, :3], axis=2) - spheres[None, :, 3]
+                bb = np.argmin(dd, 1)
+                b[unsure] = bb
+                dist[unsure] = dd[np.arange(len(q)), bb]
         out[s:s + chunk] = np.where(dist > 0, T_sat + slopes[b] * dist, T_sat)
     return out
 

@@ -368,3 +368,35 @@ def voronoi_pipe_mesh(n_radial: int, R: float, L: float, seed: int, jitter: floa
     h = (np.prod(hi - lo) / N) ** (1.0 / 3.0)
     return _finish(owner, neigh, fo, fv, X, keep_idx, "voronoi-pipe", h, seeds,
                    extra={"R": R, "L": L}, other_pt=oth)
+
+
+def concat(meshes: list) -> Mesh:
+    """Disjoint union of meshes: cells, faces and vertices of mesh i follow
+    those of meshes 0..i-1, ids and offsets shifted (vertex coordinates per
+    component, [3][total])."""
+    cfo, cf, fvo, fv, ow, ne, bc, xyz = [], [], [], [], [], [], [], []
+    bN = bF = bV = bcf = bfv = 0
+    for i, m in enumerate(meshes):
+        cfo.append(np.asarray(m.cell_face_off[: (None if i == len(meshes) - 1 else -1)], np.int64) + bcf)
+        fvo.append(np.asarray(m.face_vert_off[: (None if i == len(meshes) - 1 else -1)], np.int64) + bfv)
+        cf.append(np.asarray(m.cell_face, np.int64) + bF)
+        fv.append(np.asarray(m.face_vert, np.int64) + bV)
+        ow.append(np.asarray(m.face_owner, np.int64) + bN)
+        ne.append(np.where(m.face_neigh >= 0, np.asarray(m.face_neigh, np.int64) + bN, m.face_neigh))
+        bc.append(np.asarray(m.face_bc, np.int8))
+        xyz.append(np.asarray(m.vert_xyz, np.float64))
+        bN += m.n_cells
+        bF += m.n_faces
+        bV += m.n_verts
+        bcf += len(m.cell_face)
+        bfv += len(m.face_vert)
+    hs = [m.h for m in meshes]
+    return Mesh(
+        n_cells=bN, n_faces=bF, n_verts=bV,
+        cell_face_off=np.concatenate(cfo), cell_face=np.concatenate(cf).astype(np.int32),
+        face_vert_off=np.concatenate(fvo), face_vert=np.concatenate(fv).astype(np.int32),
+        face_owner=np.concatenate(ow).astype(np.int32), face_neigh=np.concatenate(ne).astype(np.int32),
+        face_bc=np.concatenate(bc), vert_xyz=np.ascontiguousarray(np.concatenate(xyz, 1)),
+        kind="+".join(m.kind for m in meshes), h=float(min(hs)),
+        extra={"parts": [(m.n_cells, m.n_faces, m.n_verts) for m in meshes]},
+    )

@@ -12,6 +12,11 @@
   sequential addition (radii U[2h, 12h], clearance 2h), T rising from each
   bubble with its own slope U[1, 20] K per unit length.
 * ``pipe_film``      Voronoi cells of a pipe with a wavy liquid film on the wall.
+* ``batched``        several meshes with many bubbles each (a hexahedral and a
+  Voronoi mesh by default), stepped as one disjoint union.
+* ``multi_instance`` many independent Voronoi meshes of log-uniform sizes, each
+  with one bubble moving on a circle around the vertical axis through the box
+  centre (rigid rotation, one revolution over the time steps).
 
 Temperatures are evaluated at the mean of a cell's vertices and boundary
 temperatures at the mean of a face's vertices (input placement only).
@@ -23,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import fields
-from .meshes import Mesh, hex_mesh, voronoi_box_mesh, voronoi_pipe_mesh
+from .meshes import Mesh, concat, hex_mesh, voronoi_box_mesh, voronoi_pipe_mesh
 
 T_SAT = 373.15
 K_STEAM = 0.025
@@ -93,3 +98,64 @@ def pipe_film(n_radial: int = 40, seed: int = 4, R: float = 1.0, K: int = 16) ->
     Tb = fields.film_T(mesh.face_vertex_mean(), R, d0, amp, waves, L, 1.0, T_SAT)
     return Workload(f"pipe {mesh.n_cells} cells film", mesh, alpha, T, Tb,
                     meta={"R": R, "L": L, "d0": d0, "amp": amp, "waves": waves})
+
+
+def concat_workloads(wls: list, name: str | None = None) -> Workload:
+    """One workload over the disjoint union of the workloads' meshes (their
+    material constants must agree)."""
+    w0 = wls[0]
+    for w in wls[1:]:
+        assert (w.T_sat, w.k_l, w.k_v, w.h_lv) == (w0.T_sat, w0.k_l, w0.k_v, w0.h_lv)
+    mesh = concat([w.mesh for w in wls])
+    return Workload(name or " + ".join(w.name for w in wls), mesh,
+                    np.concatenate([w.alpha for w in wls]), np.concatenate([w.T for w in wls]),
+                    np.concatenate([w.T_bface for w in wls]), w0.T_sat, w0.k_l, w0.k_v, w0.h_lv,
+                    meta={"parts": [w.name for w in wls],
+                          "cell_offsets": np.cumsum([0] + [w.mesh.n_cells for w in wls])})
+
+
+def batched(hex_n: int = 128, vor_n: int = 79, seed: int = 3, n_max: int = 1000, K: int = 16,
+            r_hi_h: float = 12.0) -> list:
+    """A hexahedral mesh (hex_n^3 cells) and a jittered-BCC Voronoi mesh
+    (2 vor_n^3 cells), each with up to n_max bubbles r ~ U[2h, r_hi_h h] placed
+    by random sequential addition (the count that fits is used).  Returns the
+    two workloads; step them as one with ``concat_workloads``."""
+    out = []
+    for i, m in enumerate((hex_mesh(hex_n), voronoi_box_mesh(vor_n, seed))):
+        out.append(random_bubbles(m, seed=seed + 17 * i, n_max=n_max, K=K, r_hi_h=r_hi_h))
+    return out
+
+
+def _log_uniform_sizes(rng, n_inst: int, n_lo: float, n_hi: float) -> list:
+    N = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), n_inst))
+    return [max(2, int(round((x / 2.0) ** (1.0 / 3.0)))) for x in N]   # BCC seeds per axis
+
+
+def multi_instance(n_inst: int = 64, n_lo: float = 1e4, n_hi: float = 5e5, seed: int = 5,
+                   steps: int = 100, K: int = 16, width: float = 0.05, dT: float = 1.25):
+    """Meshes and per-step fields of the multi-instance batch: instance i is a
+    box-clipped Voronoi mesh of about N_i = exp(U[ln n_lo, ln n_hi]) cells with
+    one bubble r ~ U[0.10, 0.20] whose centre sits 0.15 from the vertical axis
+    through (0.5, 0.5) and turns once around it over `steps` steps; T is the
+    erf profile of ``voronoi_bubble`` around the moving centre.
+
+    Returns (meshes, radii, phases, field) where field(i, t) gives the
+    Workload of instance i at step t."""
+    rng = np.random.default_rng(seed)
+    ns = _log_uniform_sizes(rng, n_inst, n_lo, n_hi)
+    radii = rng.uniform(0.10, 0.20, n_inst)
+    phases = rng.uniform(0.0, 2.0 * np.pi, n_inst)
+    seeds = rng.integers(1 << 30, size=n_inst)
+    meshes = [voronoi_box_mesh(n, int(s)) for n, s in zip(ns, seeds)]
+
+    def field(i: int, t: int) -> Workload:
+        m = meshes[i]
+        th = phases[i] + 2.0 * np.pi * t / steps
+        c = (0.5 + 0.15 * np.cos(th), 0.5 + 0.15 * np.sin(th), 0.5)
+        r = radii[i]
+        alpha = fields.sphere_alpha(m, np.array([[*c, r]]), K=K)
+        T = fields.radial_erf_T(m.cell_vertex_mean(), c, r, width, dT, T_SAT)
+        Tb = fields.radial_erf_T(m.face_vertex_mean(), c, r, width, dT, T_SAT)
+        return Workload(f"instance {i} step {t}", m, alpha, T, Tb, meta={"spheres": np.array([[*c, r]])})
+
+    return meshes, radii, phases, field

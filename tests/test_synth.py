@@ -59,3 +59,19 @@ def test_alpha_fractions_match_the_sphere_volume():
     vap = (1 - wl.alpha).sum() / wl.mesh.n_cells
     assert vap == pytest.approx(4 / 3 * np.pi * 0.3 ** 3, rel=1e-4)
     assert 400 < wl.n_mixed < 440
+
+
+def test_host_concat_is_the_disjoint_union():
+    """Oracle geometry of the host-side union equals the parts' geometry laid
+    end to end (so batch tests compare against the right reference)."""
+    import oracle
+    from synth import meshes
+    parts = [meshes.hex_mesh(4), meshes.voronoi_box_mesh(4, seed=3)]
+    whole = meshes.concat(parts)
+    gw = oracle.geometry(whole)
+    gp = [oracle.geometry(p) for p in parts]
+    np.testing.assert_array_equal(gw.V, np.concatenate([g.V for g in gp]))
+    np.testing.assert_array_equal(gw.xc, np.concatenate([g.xc for g in gp], 1))
+    np.testing.assert_array_equal(gw.Sf, np.concatenate([g.Sf for g in gp], 1))
+    assert whole.n_cells == sum(p.n_cells for p in parts)
+    assert np.all(whole.face_owner[parts[0].n_faces:] >= parts[0].n_cells)
