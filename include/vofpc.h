@@ -131,6 +131,16 @@ vofpc_status vofpc_mesh_free(vofpc_mesh mesh);
 /* info[0..7] = n_cells, n_faces, n_verts, max faces per cell, max vertices
  * per cell, max vertices per face, max edges per cell, device bytes held. */
 vofpc_status vofpc_mesh_info(vofpc_mesh mesh, int64_t info[8]);
+/* Kernel classes of the mesh's cells (HOST outputs, any may be NULL): cells[c]
+ * = number of cells whose size (vertices, faces, loop positions, edges) fits
+ * class c = 0 (<= 16, 8, 48, 24), 1 (<= 48, 32, 128, 64), 2 (<= 64, 64, 256,
+ * 128) or 3 (larger); tune[c] = occupancy flavour (3 or 4 waves per SIMD) the
+ * reconstruction uses for class c; *bucketed = 1 when the cells spread over
+ * several classes (each with >= 1 % of the cells): then the reconstruction
+ * splits the mixed entries by class and launches each class's kernel on its
+ * own entries (face-count buckets), else one kernel sized for the largest
+ * cell runs. */
+vofpc_status vofpc_mesh_classes(vofpc_mesh mesh, int64_t cells[4], int32_t tune[4], int32_t *bucketed);
 /* Copy the computed geometry into caller DEVICE buffers (any may be NULL):
  * V[n_cells], xc[3][n_cells], Sf[3][n_faces], xf[3][n_faces]. */
 vofpc_status vofpc_mesh_geometry(vofpc_mesh mesh, double *V, double *xc, double *Sf, double *xf);
@@ -212,6 +222,18 @@ vofpc_status vofpc_reconstruct_learned(vofpc_ctx ctx, vofpc_mesh mesh, const dou
                                        const int32_t *mixed_idx, const int32_t *counts,
                                        const vofpc_recon_opts *opts, vofpc_mlp mlp, double delta_scale,
                                        double *hint_lo, double *hint_hi, const vofpc_interface *out);
+
+/* Autotune the reconstruction of a mesh: for each class that has two kernel
+ * flavours (classes 0 and 1: register budgets for 3 or 4 waves per SIMD),
+ * time both on the mixed cells of `alpha` (DEVICE [n_cells]; opts may be
+ * NULL) and keep the faster in the mesh.  cache_path (optional, a text file):
+ * a line for the same device, CU count, mesh sizes and class counts is used
+ * without timing (*from_cache = 1); otherwise the choice is appended.
+ * choice: optional HOST int32[4] receiving the flavour per class.  Allocates
+ * trial buffers and synchronises the context stream (a set-up call, not for
+ * capture). */
+vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const vofpc_recon_opts *opts,
+                            const char *cache_path, int32_t *choice, int32_t *from_cache);
 
 /* ----------------------------------------------------------------- gradient */
 #define VOFPC_SCOPE_BAND 0  /* write grad at band cells only (others untouched) */

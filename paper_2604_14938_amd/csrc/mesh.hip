@@ -160,6 +160,30 @@ vofpc_status dev_copy(vofpc_mesh M, const T *host, size_t n, T **out) {
 
 }  // namespace
 
+// Kernel classes of a mesh: the class of its largest cell, and whether its
+// cells spread over several classes (each holding at least 1 % of the cells),
+// in which case the reconstruction buckets its mixed entries by class.
+static vofpc_status setup_classes(vofpc_mesh M, const int64_t *class_cnt) {
+  const int64_t N = M->d.n_cells;
+  int big = 0;
+  M->max_class = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    M->class_cells[c] = class_cnt[c];
+    M->tune[c] = 3;
+    if (class_cnt[c] > 0) M->max_class = c;
+    if (class_cnt[c] > 0 && class_cnt[c] * 100 >= N) ++big;
+  }
+  M->bucketed = big >= 2;
+  M->bucket_lists = nullptr;
+  M->bucket_counts = nullptr;
+  if (M->bucketed) {
+    vofpc_status st = dev_copy<int32_t>(M, nullptr, (size_t)kClasses * N, &M->bucket_lists);
+    if (!st) st = dev_copy<int32_t>(M, nullptr, kClasses, &M->bucket_counts);
+    if (st) return st;
+  }
+  return VOFPC_OK;
+}
+
 vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *out) {
   VOFPC_REQUIRE(ctx && d && out, VOFPC_E_INVALID_ARG, "mesh_upload: null argument");
   const int64_t N = d->n_cells, NF = d->n_faces, NV = d->n_verts;
@@ -216,6 +240,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   cv_gid.reserve(ncf * 2);
   cl_lv.reserve(nfv * 2);
   int64_t max_nf = 0, max_nv = 0, max_fv = 0, max_ne = 0, max_loop = 0;
+  int64_t class_cnt[kClasses] = {0, 0, 0, 0};
   std::vector<int32_t> loc;
   std::vector<uint16_t> dedge;
   for (int64_t P = 0; P < N; ++P) {
@@ -285,6 +310,8 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
     max_nv = std::max<int64_t>(max_nv, (int64_t)loc.size());
     max_ne = std::max<int64_t>(max_ne, (int64_t)dedge.size() / 2);
     max_loop = std::max<int64_t>(max_loop, cl_off[P + 1] - cl_off[P]);
+    class_cnt[class_of((int64_t)loc.size(), cfo[P + 1] - cfo[P], cl_off[P + 1] - cl_off[P],
+                       (int64_t)dedge.size() / 2)]++;
   }
   // vertex -> cell incidence (cells ascending)
   std::vector<int64_t> vc_off(NV + 1, 0);
@@ -359,6 +386,10 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   M->max_nf = max_nf; M->max_nv = max_nv; M->max_fv = max_fv; M->max_ne = max_ne; M->max_loop = max_loop;
   M->ncf = ncf; M->nfv = nfv; M->ncv = (int64_t)cv_gid.size(); M->ncl = (int64_t)cl_lv.size();
   M->nvc = (int64_t)vc_cell.size();
+  if ((st = setup_classes(M, class_cnt))) {
+    vofpc_mesh_free(M);
+    return st;
+  }
 
   hipStream_t s = ctx->stream;
   const int B = 256;
@@ -472,6 +503,15 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
   }
   M->max_nf = mx[0]; M->max_nv = mx[1]; M->max_fv = mx[2]; M->max_ne = mx[3]; M->max_loop = mx[4];
   M->ncf = ncf; M->nfv = nfv; M->ncv = ncv; M->ncl = ncl; M->nvc = nvc;
+  {
+    int64_t cc[kClasses] = {0, 0, 0, 0};
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < kClasses; ++c) cc[c] += ms[i]->class_cells[c];
+    if ((st = setup_classes(M, cc))) {
+      vofpc_mesh_free(M);
+      return st;
+    }
+  }
   hipStream_t s = ctx->stream;
   int64_t bN = 0, bF = 0, bV = 0, bcf = 0, bfv = 0, bcv = 0, bcl = 0, bvc = 0;
 #define CC(dst, src, cnt, add, mode)                                                        \
@@ -552,6 +592,17 @@ extern "C" vofpc_status vofpc_mesh_info(vofpc_mesh m, int64_t info[8]) {
   VOFPC_REQUIRE(m && info, VOFPC_E_INVALID_ARG, "mesh_info: null argument");
   info[0] = m->d.n_cells; info[1] = m->d.n_faces; info[2] = m->d.n_verts;
   info[3] = m->max_nf; info[4] = m->max_nv; info[5] = m->max_fv; info[6] = m->max_ne; info[7] = m->bytes;
+  return VOFPC_OK;
+}
+
+extern "C" vofpc_status vofpc_mesh_classes(vofpc_mesh m, int64_t cells[4], int32_t tune[4], int32_t *bucketed) {
+  vofpc::clear_error();
+  VOFPC_REQUIRE(m, VOFPC_E_INVALID_ARG, "mesh_classes: null mesh");
+  for (int c = 0; c < vofpc::kClasses; ++c) {
+    if (cells) cells[c] = m->class_cells[c];
+    if (tune) tune[c] = m->tune[c];
+  }
+  if (bucketed) *bucketed = m->bucketed ? 1 : 0;
   return VOFPC_OK;
 }
 

@@ -36,6 +36,11 @@
 // when the bracket collapses first, the end nearer to alpha V_P is kept.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
 #include "vofpc_internal.h"
 #include "mlp_core.h"
 #include "wave_ops.h"
@@ -135,6 +140,10 @@ struct ReconParams {
   double eps, tol_rel, iso;
   int max_iter, vertex_mode, fixed_iso, use_hint;
   int *queue;   // claim counter of the cells beyond the first grid-size ones
+  // optional entry list of this launch (a face-count bucket): entries[j] for
+  // j < *entry_count instead of every mixed entry
+  const int32_t *entries;
+  const int32_t *entry_count;
   // bracket network run inside the kernel (null: none): BF16 weights, FP32
   // parameters, half-width factor, optional outputs of the bracket
   const uint16_t *net_wb;
@@ -710,20 +719,21 @@ __device__ float net_guess(GM &L, int lane, const ReconParams &p, int64_t k, int
 }
 
 // One cell per wavefront (block of 64 lanes).
-template <int NV, int NF, int NL, int NCH>
-__global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
+template <int NV, int NF, int NL, int NCH, int OCC>
+__global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
   constexpr int W = 64;
   __shared__ GroupMem<kSlotChords, NV, NF, NL, NCH> L;
   const int lane = threadIdx.x;
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells;
   const int64_t cap = p.out.cap;
-  int64_t count = p.counts[0];
+  int64_t count = p.entries ? (int64_t)*p.entry_count : (int64_t)p.counts[0];
   if (count > cap) count = cap;
-  // cells go to blocks through a counter: block b starts with cell b and
+  // cells go to blocks through a counter: block b starts with entry b and
   // then claims the next unclaimed one, so blocks that meet cheap cells do
   // more of them
-  for (int64_t k = blockIdx.x; k < count;) {
+  for (int64_t j = blockIdx.x; j < count;) {
+    const int64_t k = p.entries ? (int64_t)p.entries[j] : j;
     const int P = p.mixed[k];
     const double a = p.alpha[P];
     double s_out = __builtin_nan(""), A_out = 0, d_out = 0, n0 = 0, n1 = 0, n2 = 0, ag = a;
@@ -1116,23 +1126,74 @@ __global__ __launch_bounds__(64, 3) void recon_kernel(ReconParams p) {
       // the counter is back at zero when the launch ends
       nk = (int)atomicInc((unsigned int *)p.queue, (unsigned int)(count - 1));
     }
-    k = (int64_t)gridDim.x + __builtin_amdgcn_readfirstlane(nk);
+    j = (int64_t)gridDim.x + __builtin_amdgcn_readfirstlane(nk);
     wave_sync();
   }
 }
 
+// ----------------------------------------------------------------- buckets
+// Kernel class of a cell: the smallest template variant that holds it.
+__device__ __forceinline__ int cell_class(const DevMesh &m, int P) {
+  const int64_t nf = m.cell_face_off[P + 1] - m.cell_face_off[P];
+  const int64_t nv = m.cv_off[P + 1] - m.cv_off[P];
+  const int64_t nl = m.cl_off[P + 1] - m.cl_off[P];
+  return class_of(nv, nf, nl, nl / 2);
+}
+
+__global__ void bucket_zero_kernel(int32_t *c) {
+  if (threadIdx.x < kClasses) c[threadIdx.x] = 0;
+}
+
+// Split the mixed entries into one list per class (order within a list is
+// the order of the atomic claims; results do not depend on it).
+__global__ __launch_bounds__(256) void bucket_kernel(DevMesh m, const int32_t *mixed, const int32_t *counts,
+                                                     int64_t cap, int32_t *lists, int64_t stride, int32_t *bcount) {
+  int64_t count = counts[0];
+  if (count > cap) count = cap;
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = (k < count) ? cell_class(m, mixed[k]) : -1;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int q = 0; q < kClasses; ++q) {
+    const uint64_t bm = __ballot(c == q);
+    if (!bm) continue;
+    const int leader = __ffsll((long long)bm) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&bcount[q], __popcll(bm));
+    base = __shfl(base, leader);
+    if (c == q) lists[q * stride + base + __popcll(bm & below)] = (int32_t)k;
+  }
+}
+
 namespace {
-template <int NV, int NF, int NL, int NCH>
+template <int NV, int NF, int NL, int NCH, int OCC>
 vofpc_status launch_t(vofpc_ctx ctx, const ReconParams &p, int64_t n_cells) {
   int blocks_per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, recon_kernel<NV, NF, NL, NCH>, 64, 0);
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, recon_kernel<NV, NF, NL, NCH, OCC>, 64, 0);
   if (e != hipSuccess || blocks_per_cu <= 0) blocks_per_cu = 4;
   int64_t grid = (int64_t)ctx->n_cu * blocks_per_cu;
   if (grid > n_cells) grid = n_cells;
   if (grid < 1) grid = 1;
-  recon_kernel<NV, NF, NL, NCH><<<(unsigned)grid, 64, 0, ctx->stream>>>(p);
+  recon_kernel<NV, NF, NL, NCH, OCC><<<(unsigned)grid, 64, 0, ctx->stream>>>(p);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;
+}
+
+// Launch the variant of class c in flavour `occ` (waves per SIMD the
+// register budget is sized for; the two common classes have two flavours).
+vofpc_status launch_class(vofpc_ctx ctx, const ReconParams &p, int64_t n_cells, int c, int occ) {
+  switch (c) {
+    case 0:
+      return occ == 4 ? launch_t<16, 8, 48, 24, 4>(ctx, p, n_cells) : launch_t<16, 8, 48, 24, 3>(ctx, p, n_cells);
+    case 1:
+      return occ == 4 ? launch_t<48, 32, 128, 64, 4>(ctx, p, n_cells) : launch_t<48, 32, 128, 64, 3>(ctx, p, n_cells);
+    case 2:
+      return launch_t<64, 64, 256, 128, 3>(ctx, p, n_cells);
+    default:
+      return launch_t<255, 255, 1536, 768, 3>(ctx, p, n_cells);
+  }
 }
 }  // namespace
 
@@ -1181,13 +1242,137 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   VOFPC_REQUIRE(!net || !p.use_hint, VOFPC_E_INVALID_ARG,
                 "reconstruct_learned: the network replaces hint brackets (use VOFPC_BRACKET_PLAIN)");
   p.out = *out;
-  const int64_t nf = M->max_nf, nv = M->max_nv, nl = M->max_loop, ne = M->max_ne, fv = M->max_fv;
-  VOFPC_REQUIRE(fv <= 64, VOFPC_E_MESH, "reconstruct: faces with more than 64 vertices are not supported");
+  VOFPC_REQUIRE(M->max_fv <= 64, VOFPC_E_MESH, "reconstruct: faces with more than 64 vertices are not supported");
   const int64_t N = M->d.n_cells;
-  if (nv <= 16 && nf <= 8 && nl <= 48 && ne <= 24) return launch_t<16, 8, 48, 24>(ctx, p, N);
-  if (nv <= 48 && nf <= 32 && nl <= 128 && ne <= 64) return launch_t<48, 32, 128, 64>(ctx, p, N);
-  if (nv <= 64 && nf <= 64 && nl <= 256 && ne <= 128) return launch_t<64, 64, 256, 128>(ctx, p, N);
-  return launch_t<255, 255, 1536, 768>(ctx, p, N);
+  p.entries = nullptr;
+  p.entry_count = nullptr;
+  if (!M->bucketed) return launch_class(ctx, p, N, M->max_class, M->tune[M->max_class]);
+  // one launch per class present in the mesh, each over its own entries
+  bucket_zero_kernel<<<1, 64, 0, ctx->stream>>>(M->bucket_counts);
+  const int64_t span = std::min<int64_t>(out->cap, N);
+  bucket_kernel<<<(unsigned)((span + 255) / 256), 256, 0, ctx->stream>>>(M->d, mixed, counts, out->cap,
+                                                                        M->bucket_lists, N, M->bucket_counts);
+  VOFPC_HIP(hipGetLastError());
+  for (int c = 0; c < kClasses; ++c) {
+    if (M->class_cells[c] == 0) continue;
+    p.entries = M->bucket_lists + (int64_t)c * N;
+    p.entry_count = M->bucket_counts + c;
+    vofpc_status st = launch_class(ctx, p, M->class_cells[c], c, M->tune[c]);
+    if (st) return st;
+  }
+  return VOFPC_OK;
 }
 
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+struct TuneBuffers {
+  int32_t *mixed = nullptr, *band = nullptr, *counts = nullptr, *status = nullptr, *iters = nullptr;
+  double *s = nullptr, *n = nullptr, *A = nullptr, *d = nullptr, *ag = nullptr;
+  ~TuneBuffers() {
+    (void)hipFree(mixed); (void)hipFree(band); (void)hipFree(counts); (void)hipFree(status); (void)hipFree(iters);
+    (void)hipFree(s); (void)hipFree(n); (void)hipFree(A); (void)hipFree(d); (void)hipFree(ag);
+  }
+};
+
+std::string tune_key(vofpc_ctx ctx, vofpc_mesh M) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+  for (char &ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s cu%d n%lld f%lld v%lld c%lld,%lld,%lld,%lld", arch.c_str(), ctx->n_cu,
+           (long long)M->d.n_cells, (long long)M->d.n_faces, (long long)M->d.n_verts, (long long)M->class_cells[0],
+           (long long)M->class_cells[1], (long long)M->class_cells[2], (long long)M->class_cells[3]);
+  return buf;
+}
+}  // namespace
+
 }  // namespace vofpc
+
+extern "C" vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, const vofpc_recon_opts *opts,
+                                       const char *cache_path, int32_t *choice, int32_t *from_cache) {
+  using namespace vofpc;
+  clear_error();
+  VOFPC_REQUIRE(ctx && M && alpha, VOFPC_E_INVALID_ARG, "autotune: null argument");
+  VOFPC_REQUIRE(M->ctx && M->ctx->device == ctx->device, VOFPC_E_STATE, "autotune: mesh on another device");
+  VOFPC_HIP(hipSetDevice(ctx->device));
+  vofpc_recon_opts o;
+  if (opts) o = *opts; else vofpc_recon_opts_default(&o);
+  if (from_cache) *from_cache = 0;
+  const std::string key = tune_key(ctx, M);
+  const std::string tag = "vofpc-tune " + key + " :";
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "r")) {
+      char line[512];
+      bool hit = false;
+      while (fgets(line, sizeof line, f)) {
+        if (strncmp(line, tag.c_str(), tag.size()) != 0) continue;
+        int t[kClasses];
+        if (sscanf(line + tag.size(), "%d %d %d %d", &t[0], &t[1], &t[2], &t[3]) == kClasses) {
+          for (int c = 0; c < kClasses; ++c) M->tune[c] = (t[c] == 4) ? 4 : 3;
+          hit = true;
+        }
+      }
+      fclose(f);
+      if (hit) {
+        if (from_cache) *from_cache = 1;
+        if (choice)
+          for (int c = 0; c < kClasses; ++c) choice[c] = M->tune[c];
+        return VOFPC_OK;
+      }
+    }
+  }
+  // time the flavours on this field (greedy per class, all classes launched)
+  const int64_t N = M->d.n_cells;
+  TuneBuffers b;
+  if (hipMalloc(&b.mixed, 4 * N) || hipMalloc(&b.band, 4 * N) || hipMalloc(&b.counts, 8) ||
+      hipMalloc(&b.status, 4 * N) || hipMalloc(&b.iters, 4 * N) || hipMalloc(&b.s, 8 * N) ||
+      hipMalloc(&b.n, 24 * N) || hipMalloc(&b.A, 8 * N) || hipMalloc(&b.d, 8 * N) || hipMalloc(&b.ag, 8 * N)) {
+    set_error("autotune: hipMalloc of the trial buffers failed");
+    return VOFPC_E_OOM;
+  }
+  vofpc_interface itf;
+  itf.s = b.s; itf.n = b.n; itf.A = b.A; itf.d = b.d; itf.alpha_got = b.ag; itf.status = b.status;
+  itf.iters = b.iters; itf.cap = N;
+  vofpc_status st = launch_compact(ctx, M, alpha, o.eps_mixed, b.mixed, b.band, b.counts);
+  if (st) return st;
+  hipEvent_t e0, e1;
+  VOFPC_HIP(hipEventCreate(&e0));
+  VOFPC_HIP(hipEventCreate(&e1));
+  for (int c = 0; c < 2; ++c) {
+    if (M->class_cells[c] == 0 || (!M->bucketed && c != M->max_class)) continue;
+    float best = 0.f;
+    int best_f = 3;
+    for (int f = 3; f <= 4; ++f) {
+      M->tune[c] = f;
+      st = launch_reconstruct(ctx, M, alpha, b.mixed, b.counts, &o, nullptr, nullptr, &itf);
+      if (st) break;
+      (void)hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < 3 && !st; ++r) st = launch_reconstruct(ctx, M, alpha, b.mixed, b.counts, &o, nullptr, nullptr, &itf);
+      (void)hipEventRecord(e1, ctx->stream);
+      if (st) break;
+      if (hipEventSynchronize(e1) != hipSuccess) { st = VOFPC_E_HIP; set_error("autotune: event wait failed"); break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (f == 3 || ms < best) { best = ms; best_f = f; }
+    }
+    if (st) break;
+    M->tune[c] = best_f;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  VOFPC_HIP(hipStreamSynchronize(ctx->stream));
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "a")) {
+      fprintf(f, "%s %d %d %d %d\n", tag.c_str(), M->tune[0], M->tune[1], M->tune[2], M->tune[3]);
+      fclose(f);
+    }
+  }
+  if (choice)
+    for (int c = 0; c < kClasses; ++c) choice[c] = M->tune[c];
+  return VOFPC_OK;
+}
+

@@ -72,10 +72,20 @@ struct DevMesh {
   const double *ginv;  // [6][n_cells] xx yy zz xy xz yz of the inverse
 };
 
-}  // namespace vofpc
-
 // cells per block of the compaction kernels (sizes a mesh's block arrays)
 constexpr int kCompactBlockCells = 256;
+
+// Reconstruction kernel classes: the template variants by the largest cell
+// they hold (vertices, faces, loop positions, edges).
+constexpr int kClasses = 4;
+__host__ __device__ inline int class_of(int64_t nv, int64_t nf, int64_t nl, int64_t ne) {
+  if (nv <= 16 && nf <= 8 && nl <= 48 && ne <= 24) return 0;
+  if (nv <= 48 && nf <= 32 && nl <= 128 && ne <= 64) return 1;
+  if (nv <= 64 && nf <= 64 && nl <= 256 && ne <= 128) return 2;
+  return 3;
+}
+
+}  // namespace vofpc
 
 struct vofpc_ctx_s {
   int device;
@@ -100,6 +110,16 @@ struct vofpc_mesh_s {
   int32_t *blk_cnt;   // [2][n_blocks]
   int32_t *blk_off;   // [2][n_blocks]
   int64_t n_blk;
+  // cells per kernel class; the class of the largest cell; bucketed meshes
+  // (cells spread over several classes) launch one variant per class over
+  // per-class entry lists [kClasses][n_cells] with device counts
+  int64_t class_cells[vofpc::kClasses];
+  int max_class;
+  bool bucketed;
+  int32_t *bucket_lists;
+  int32_t *bucket_counts;
+  // occupancy flavour chosen per class (3 or 4 waves per SIMD; autotuned)
+  int tune[vofpc::kClasses];
   void *alloc[40];
   int n_alloc;
 };

@@ -94,6 +94,8 @@ def _load():
         "vofpc_mlp_bracket": ([P, P, P, P, P, I64, D, P, P], ctypes.c_int),
         "vofpc_reconstruct_learned": ([P, P, P, P, P, P, P, D, P, P, P], ctypes.c_int),
         "vofpc_mesh_concat": ([P, P, ctypes.c_int32, P], ctypes.c_int),
+        "vofpc_mesh_classes": ([P, P, P, P], ctypes.c_int),
+        "vofpc_autotune": ([P, P, P, P, ctypes.c_char_p, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -193,6 +195,13 @@ class Mesh:
         _check(lib.vofpc_mesh_concat(ctx.h, arr, len(meshes), ctypes.byref(h)), "vofpc_mesh_concat")
         return cls(ctx, None, _handle=h)
 
+    def classes(self) -> dict:
+        cells = (ctypes.c_int64 * 4)()
+        tune = (ctypes.c_int32 * 4)()
+        b = ctypes.c_int32()
+        _check(lib.vofpc_mesh_classes(self.h, cells, tune, ctypes.byref(b)), "vofpc_mesh_classes")
+        return {"cells": list(cells), "tune": list(tune), "bucketed": bool(b.value)}
+
     def info(self) -> dict:
         a = (ctypes.c_int64 * 8)()
         _check(lib.vofpc_mesh_info(self.h, a), "vofpc_mesh_info")
@@ -277,6 +286,17 @@ def reconstruct_learned(ctx: Context, mesh: Mesh, alpha, mixed_idx, counts, itf:
     _check(lib.vofpc_reconstruct_learned(ctx.h, mesh.h, _ptr(alpha), _ptr(mixed_idx), _ptr(counts), ctypes.byref(opts),
                                          mlp.h, float(delta_scale), _ptr(hint_lo), _ptr(hint_hi), ctypes.byref(ci)),
            "vofpc_reconstruct_learned")
+
+
+def autotune(ctx: Context, mesh: Mesh, alpha, opts: ReconOpts | None = None, cache_path: str | None = None):
+    """Pick the reconstruction kernel flavour per class by timing (see
+    vofpc_autotune); returns (flavours per class, taken from the cache)."""
+    choice = (ctypes.c_int32 * 4)()
+    hit = ctypes.c_int32()
+    _check(lib.vofpc_autotune(ctx.h, mesh.h, _ptr(alpha), ctypes.byref(opts) if opts is not None else None,
+                              cache_path.encode() if cache_path else None, choice, ctypes.byref(hit)),
+           "vofpc_autotune")
+    return list(choice), bool(hit.value)
 
 
 def grad_T(ctx: Context, mesh: Mesh, T, T_bface, T_sat: float, alpha, band_idx, counts, grad, status=None,

@@ -99,3 +99,34 @@ def test_multi_instance_time_steps_in_one_graph(R):
         rep = _check_step(wl, g)
         _say(f"step {t}: {g['n_mixed']} mixed ok {rep}")
     run.close()
+
+
+def test_buckets_and_autotune(R, tmp_path):
+    """A hex + Voronoi union is bucketed by kernel class; every flavour the
+    autotuner may pick gives the oracle's results; the choice is cached."""
+    import torch
+    from paper_2604_14938_amd import vofpc as V
+    wls = workloads.batched(hex_n=24, vor_n=12, seed=8, n_max=200, K=12, r_hi_h=3.0)
+    wl = workloads.concat_workloads(wls)
+    _say(f"buckets + autotune: {[w.mesh.n_cells for w in wls]} cells, {wl.n_mixed} mixed")
+    run = R.PathRun(wl, parts=[w.mesh for w in wls])
+    cls = run.mesh.classes()
+    assert cls["bucketed"] and cls["cells"][0] >= wls[0].mesh.n_cells and cls["cells"][1] > 0
+    ref = parity.oracle_path(wl)
+    for flavour in (3, 4):
+        # force a flavour through the cache file, then check the results
+        path = tmp_path / f"tune{flavour}.txt"
+        choice, hit = V.autotune(run.ctx, run.mesh, run.alpha, cache_path=str(path))
+        assert not hit and set(choice[:2]) <= {3, 4}
+        line = path.read_text().strip().rsplit(":", 1)[0] + f": {flavour} {flavour} 3 3\n"
+        path.write_text(line)
+        choice, hit = V.autotune(run.ctx, run.mesh, run.alpha, cache_path=str(path))
+        assert hit and choice[:2] == [flavour, flavour]
+        assert run.mesh.classes()["tune"][:2] == [flavour, flavour]
+        run.step()
+        g = run.results()
+        parity.check_lists(wl, g)
+        parity.check_interface(wl, g, ref["rec"])
+        _say(f"flavour {flavour} ok")
+    run.close()
+    torch.cuda.synchronize()
