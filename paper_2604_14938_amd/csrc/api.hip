@@ -149,25 +149,27 @@ extern "C" vofpc_status vofpc_mass_transfer(vofpc_ctx ctx, vofpc_mesh mesh, cons
 
 static vofpc_status issue_step(vofpc_ctx ctx, vofpc_mesh mesh, const vofpc_step_args *a) {
   VOFPC_REQUIRE(a, VOFPC_E_INVALID_ARG, "step: null arguments");
+  VOFPC_REQUIRE(a->mdot && a->Qdot && a->gradT, VOFPC_E_INVALID_ARG, "step: null gradient or mass-transfer output");
+  VOFPC_REQUIRE(a->h_lv != 0.0, VOFPC_E_INVALID_ARG, "step: h_lv must be nonzero");
   vofpc_status s = launch_compact(ctx, mesh, a->alpha, a->opts.eps_mixed, a->mixed_idx, a->band_idx, a->counts);
   if (s) return s;
+  // the band gradient first (it needs only the lists), so the reconstruction
+  // can finish every mixed cell with its mass transfer (Eq. mass_transfer)
+  s = launch_grad(ctx, mesh, a->T, a->T_bface, a->T_sat, a->alpha, a->band_idx, a->counts, VOFPC_SCOPE_BAND,
+                  VOFPC_GRAD_MODIFIED, a->gradT, a->grad_status);
+  if (s) return s;
+  MdotFuse mf{a->gradT, a->k_l, a->k_v, a->h_lv, a->mdot, a->Qdot};
   if (a->mlp) {
     // learned form: the network runs inside the reconstruction kernel
     VOFPC_REQUIRE(a->opts.bracket == VOFPC_BRACKET_PLAIN, VOFPC_E_INVALID_ARG,
                   "step: the learned form takes opts.bracket = VOFPC_BRACKET_PLAIN");
     VOFPC_REQUIRE((a->hint_lo == nullptr) == (a->hint_hi == nullptr), VOFPC_E_INVALID_ARG,
                   "step: give both hint_lo and hint_hi or neither");
-    s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, nullptr, nullptr, &a->itf, a->mlp,
-                           a->delta_scale, a->hint_lo, a->hint_hi);
-  } else {
-    s = launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, a->hint_lo, a->hint_hi, &a->itf);
+    return launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, nullptr, nullptr, &a->itf,
+                              a->mlp, a->delta_scale, a->hint_lo, a->hint_hi, &mf);
   }
-  if (s) return s;
-  s = launch_grad(ctx, mesh, a->T, a->T_bface, a->T_sat, a->alpha, a->band_idx, a->counts, VOFPC_SCOPE_BAND,
-                  VOFPC_GRAD_MODIFIED, a->gradT, a->grad_status);
-  if (s) return s;
-  return launch_mass_transfer(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->itf, a->gradT, nullptr, nullptr,
-                              a->k_l, a->k_v, a->h_lv, a->mdot, a->Qdot, nullptr, nullptr);
+  return launch_reconstruct(ctx, mesh, a->alpha, a->mixed_idx, a->counts, &a->opts, a->hint_lo, a->hint_hi, &a->itf,
+                            nullptr, 0.0, nullptr, nullptr, &mf);
 }
 
 extern "C" vofpc_status vofpc_step(vofpc_ctx ctx, vofpc_mesh mesh, const vofpc_step_args *args) {

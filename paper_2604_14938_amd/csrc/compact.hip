@@ -1,6 +1,7 @@
-// Mixed-cell and gradient-band compaction: wavefront ballots, a block scan and
-// a scan of the block totals, giving stable (ascending) index lists and their
-// lengths in device memory.
+// Mixed-cell and gradient-band compaction: a face pass for the band test,
+// a cell pass with wavefront ballots and block totals, and a scatter whose
+// blocks sum the totals before them, giving stable (ascending) index lists
+// and their lengths in device memory.
 #include <hip/hip_runtime.h>
 
 #include "vofpc_internal.h"
@@ -12,25 +13,35 @@ constexpr int kWaves = kCompactBlock / 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Faces whose two cells lie on opposite sides of alpha = 1/2 put both cells
+// in the band (interior faces only).  `cross` is a per-cell byte array that
+// the cell pass reads and clears again, so the next step starts from zeros.
+__global__ __launch_bounds__(kCompactBlock) void compact_faces_kernel(DevMesh m, const double *alpha, uint8_t *cross) {
+  const int64_t f = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
+  if (f >= m.n_faces) return;
+  const int q = m.face_neigh[f];
+  if (q < 0) return;
+  const int o = m.face_owner[f];
+  if ((alpha[o] - 0.5) * (alpha[q] - 0.5) < 0.0) {
+    cross[o] = 1;
+    cross[q] = 1;
+  }
+}
+
 // Per cell: bit 0 mixed (eps < alpha < 1-eps), bit 1 band (mixed, or a face
 // neighbour on the other side of alpha = 1/2).  Block totals of both.
 __global__ __launch_bounds__(kCompactBlock) void compact_flags_kernel(DevMesh m, const double *alpha, double eps,
-                                                                      uint8_t *flags, int32_t *blk_cnt,
-                                                                      int64_t n_blk) {
+                                                                      uint8_t *cross, uint8_t *flags,
+                                                                      int32_t *blk_cnt, int64_t n_blk) {
   __shared__ int32_t wsum[2][kWaves];
   const int64_t P = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
   bool mixed = false, band = false;
   if (P < m.n_cells) {
-    double a = alpha[P];
+    const double a = alpha[P];
     mixed = (a > eps) && (a < 1.0 - eps);
-    band = mixed;
-    if (!band) {
-      double ha = a - 0.5;
-      for (int64_t i = m.cell_face_off[P]; i < m.cell_face_off[P + 1]; ++i) {
-        int q = m.cf_nbr[i];
-        if (q >= 0 && ha * (alpha[q] - 0.5) < 0.0) { band = true; break; }
-      }
-    }
+    const uint8_t cr = cross[P];
+    band = mixed || cr;
+    if (cr) cross[P] = 0;
     flags[P] = (uint8_t)((mixed ? 1 : 0) | (band ? 2 : 0));
   }
   uint64_t bm = __ballot(mixed), bb = __ballot(band);
@@ -47,47 +58,35 @@ __global__ __launch_bounds__(kCompactBlock) void compact_flags_kernel(DevMesh m,
   }
 }
 
-// Exclusive scan of the block totals of both lists (one block) and the list
-// lengths.
-__global__ __launch_bounds__(1024) void compact_scan_kernel(const int32_t *blk_cnt, int32_t *blk_off, int64_t n_blk,
-                                                            int32_t *counts) {
-  __shared__ int32_t part[1024];
-  for (int list = 0; list < 2; ++list) {
-    const int32_t *c = blk_cnt + list * n_blk;
-    int32_t *o = blk_off + list * n_blk;
-    const int64_t per = (n_blk + 1023) / 1024;
-    const int64_t b = threadIdx.x * per, e = (b + per < n_blk) ? b + per : n_blk;
-    int32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += c[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (int d = 1; d < 1024; d <<= 1) {
-      int32_t t = (threadIdx.x >= (unsigned)d) ? part[threadIdx.x - d] : 0;
-      __syncthreads();
-      part[threadIdx.x] += t;
-      __syncthreads();
-    }
-    int32_t run = part[threadIdx.x] - s;
-    for (int64_t i = b; i < e; ++i) {
-      o[i] = run;
-      run += c[i];
-    }
-    if (threadIdx.x == 1023) counts[list] = part[1023];
-    __syncthreads();
-  }
-}
-
-// Scatter the cell ids into both lists in ascending order.
+// Scatter the cell ids into both lists in ascending order.  Each block sums
+// the totals of the blocks before it (a few hundred words from L2); the last
+// block also writes the list lengths.
 __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t n_cells, const uint8_t *flags,
-                                                                        const int32_t *blk_off, int64_t n_blk,
-                                                                        int32_t *mixed_idx, int32_t *band_idx) {
+                                                                        const int32_t *blk_cnt, int64_t n_blk,
+                                                                        int32_t *mixed_idx, int32_t *band_idx,
+                                                                        int32_t *counts) {
   __shared__ int32_t wbase[2][kWaves];
-  const int64_t P = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
+  __shared__ int32_t part[2][kWaves];
+  const int64_t b = blockIdx.x;
+  // exclusive prefix of the block totals
+  int32_t s0 = 0, s1 = 0;
+  for (int64_t i = threadIdx.x; i < b; i += kCompactBlock) {
+    s0 += blk_cnt[i];
+    s1 += blk_cnt[n_blk + i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o);
+    s1 += __shfl_xor(s1, o);
+  }
+  const int w = threadIdx.x >> 6, l = lane_id();
+  if (l == 0) {
+    part[0][w] = s0;
+    part[1][w] = s1;
+  }
+  const int64_t P = b * kCompactBlock + threadIdx.x;
   uint8_t f = (P < n_cells) ? flags[P] : 0;
   bool mixed = f & 1, band = f & 2;
   uint64_t bm = __ballot(mixed), bb = __ballot(band);
-  const int w = threadIdx.x >> 6, l = lane_id();
   const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
   if (l == 0) {
     wbase[0][w] = __popcll(bm);
@@ -95,12 +94,14 @@ __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t 
   }
   __syncthreads();
   if (threadIdx.x < 2) {
-    int32_t run = blk_off[threadIdx.x * n_blk + blockIdx.x];
+    int32_t run = 0;
+    for (int i = 0; i < kWaves; ++i) run += part[threadIdx.x][i];
     for (int i = 0; i < kWaves; ++i) {
       int32_t t = wbase[threadIdx.x][i];
       wbase[threadIdx.x][i] = run;
       run += t;
     }
+    if (b == n_blk - 1) counts[threadIdx.x] = run;
   }
   __syncthreads();
   if (mixed) mixed_idx[wbase[0][w] + __popcll(bm & below)] = (int32_t)P;
@@ -113,10 +114,11 @@ vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, do
   VOFPC_REQUIRE(eps >= 0 && eps < 0.5, VOFPC_E_INVALID_ARG, "compact: eps_mixed must be in [0, 0.5)");
   const int64_t nb = M->n_blk;
   hipStream_t s = ctx->stream;
-  compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->flags, M->blk_cnt, nb);
-  compact_scan_kernel<<<1, 1024, 0, s>>>(M->blk_cnt, M->blk_off, nb, counts);
-  compact_scatter_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, M->flags, M->blk_off, nb, mixed,
-                                                                  band);
+  const int64_t nfb = (M->d.n_faces + kCompactBlock - 1) / kCompactBlock;
+  compact_faces_kernel<<<(unsigned)nfb, kCompactBlock, 0, s>>>(M->d, alpha, M->cross);
+  compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->cross, M->flags, M->blk_cnt, nb);
+  compact_scatter_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, M->flags, M->blk_cnt, nb, mixed, band,
+                                                                  counts);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;
 }

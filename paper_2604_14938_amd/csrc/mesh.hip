@@ -369,13 +369,19 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   M->n_blk = (N + kCompactBlockCells - 1) / kCompactBlockCells;
   {
     uint8_t *fl = nullptr;
-    int32_t *bc = nullptr, *bo = nullptr;
-    if ((st = dev_copy<uint8_t>(M, nullptr, N, &fl)) || (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bc)) ||
-        (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bo))) {
+    int32_t *bc = nullptr;
+    if ((st = dev_copy<uint8_t>(M, nullptr, N, &fl)) || (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bc))) {
       vofpc_mesh_free(M);
       return st;
     }
-    M->flags = fl; M->blk_cnt = bc; M->blk_off = bo;
+    M->flags = fl; M->blk_cnt = bc;
+    uint8_t *cr = nullptr;
+    if ((st = dev_copy<uint8_t>(M, nullptr, N, &cr))) {
+      vofpc_mesh_free(M);
+      return st;
+    }
+    M->cross = cr;
+    VOFPC_HIP(hipMemset(cr, 0, (size_t)std::max<int64_t>(N, 1)));
   }
   int32_t *bad = nullptr;
   if ((st = dev_copy<int32_t>(M, nullptr, 1, &bad))) {
@@ -493,13 +499,19 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
   M->n_blk = (N + kCompactBlockCells - 1) / kCompactBlockCells;
   {
     uint8_t *fl = nullptr;
-    int32_t *bc = nullptr, *bo = nullptr;
-    if ((st = dev_copy<uint8_t>(M, nullptr, N, &fl)) || (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bc)) ||
-        (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bo))) {
+    int32_t *bc = nullptr;
+    if ((st = dev_copy<uint8_t>(M, nullptr, N, &fl)) || (st = dev_copy<int32_t>(M, nullptr, 2 * M->n_blk, &bc))) {
       vofpc_mesh_free(M);
       return st;
     }
-    M->flags = fl; M->blk_cnt = bc; M->blk_off = bo;
+    M->flags = fl; M->blk_cnt = bc;
+    uint8_t *cr = nullptr;
+    if ((st = dev_copy<uint8_t>(M, nullptr, N, &cr))) {
+      vofpc_mesh_free(M);
+      return st;
+    }
+    M->cross = cr;
+    VOFPC_HIP(hipMemset(cr, 0, (size_t)std::max<int64_t>(N, 1)));
   }
   M->max_nf = mx[0]; M->max_nv = mx[1]; M->max_fv = mx[2]; M->max_ne = mx[3]; M->max_loop = mx[4];
   M->ncf = ncf; M->nfv = nfv; M->ncv = ncv; M->ncl = ncl; M->nvc = nvc;

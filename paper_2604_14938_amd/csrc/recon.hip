@@ -150,6 +150,8 @@ struct ReconParams {
   const float *net_master;
   double net_delta;
   double *net_lo, *net_hi;
+  // mass transfer written with the interface (null gradT: not fused)
+  MdotFuse mf;
   vofpc_interface out;
 };
 
@@ -1113,6 +1115,19 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
       }
     }
     int nk = 0;
+    if (lane == 0 && p.mf.gradT) {
+      // mass transfer of the entry (one-sided form, as vofpc_mass_transfer)
+      double md = 0.0;
+      if (A_out > 0.0) {
+        const double gn = p.mf.gradT[P] * n0 + p.mf.gradT[N + P] * n1 + p.mf.gradT[2 * N + P] * n2;
+        const double gl = (a >= 0.5) ? gn : 0.0, gv = (a >= 0.5) ? 0.0 : gn;
+        const double ql = p.mf.k_l * gl * A_out;
+        const double qv = -p.mf.k_v * gv * A_out;
+        md = (ql + qv) / (p.mf.h_lv * m.V[P]);
+      }
+      p.mf.mdot[k] = md;
+      p.mf.Qdot[k] = -md * p.mf.h_lv;
+    }
     if (lane == 0) {
       p.out.s[k] = s_out;
       p.out.n[k] = n0; p.out.n[cap + k] = n1; p.out.n[2 * cap + k] = n2;
@@ -1200,7 +1215,7 @@ vofpc_status launch_class(vofpc_ctx ctx, const ReconParams &p, int64_t n_cells, 
 vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, const int32_t *mixed,
                                 const int32_t *counts, const vofpc_recon_opts *o, const double *hlo,
                                 const double *hhi, const vofpc_interface *out, vofpc_mlp net, double delta,
-                                double *net_lo, double *net_hi) {
+                                double *net_lo, double *net_hi, const MdotFuse *mf) {
   VOFPC_REQUIRE(alpha && mixed && counts && o && out, VOFPC_E_INVALID_ARG, "reconstruct: null argument");
   VOFPC_REQUIRE(out->s && out->n && out->A && out->d && out->alpha_got && out->status && out->iters,
                 VOFPC_E_INVALID_ARG, "reconstruct: null output array");
@@ -1230,6 +1245,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   p.fixed_iso = o->fixed_iso ? 1 : 0;
   p.use_hint = (o->bracket == VOFPC_BRACKET_HINT) ? 1 : 0;
   p.queue = ctx->queue;
+  p.mf = mf ? *mf : MdotFuse{nullptr, 0.0, 0.0, 0.0, nullptr, nullptr};
   p.net_wb = net ? mlp_weights_bf16(net) : nullptr;
   p.net_master = net ? mlp_params_f32(net) : nullptr;
   p.net_delta = delta;

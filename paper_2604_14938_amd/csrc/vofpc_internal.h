@@ -107,8 +107,8 @@ struct vofpc_mesh_s {
   // scratch for compaction (owned by the mesh; calls on one mesh must not
   // overlap in time)
   uint8_t *flags;
+  uint8_t *cross;     // band marks of the face pass (zero between calls)
   int32_t *blk_cnt;   // [2][n_blocks]
-  int32_t *blk_off;   // [2][n_blocks]
   int64_t n_blk;
   // cells per kernel class; the class of the largest cell; bucketed meshes
   // (cells spread over several classes) launch one variant per class over
@@ -134,12 +134,21 @@ namespace vofpc {
 // launchers (return VOFPC_OK or an error code with the message set)
 vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, double eps, int32_t *mixed,
                             int32_t *band, int32_t *counts);
+// mass transfer finished by the reconstruction (the whole step): the
+// one-sided form of vofpc_mass_transfer over the mixed list
+struct MdotFuse {
+  const double *gradT;
+  double k_l, k_v, h_lv;
+  double *mdot, *Qdot;
+};
 // net (optional): bracket network run inside the reconstruction, with
-// half-width factor delta; net_lo/net_hi (optional) receive its brackets
+// half-width factor delta; net_lo/net_hi (optional) receive its brackets;
+// mf (optional): mass transfer of every entry from the finished gradient
 vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh m, const double *alpha, const int32_t *mixed,
                                 const int32_t *counts, const vofpc_recon_opts *o, const double *hlo,
                                 const double *hhi, const vofpc_interface *out, vofpc_mlp net = nullptr,
-                                double delta = 0.0, double *net_lo = nullptr, double *net_hi = nullptr);
+                                double delta = 0.0, double *net_lo = nullptr, double *net_hi = nullptr,
+                                const MdotFuse *mf = nullptr);
 // device parameters of a network: BF16 weights and FP32 master copy
 const uint16_t *mlp_weights_bf16(vofpc_mlp M);
 const float *mlp_params_f32(vofpc_mlp M);
