@@ -163,6 +163,11 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--form", choices=("both", "plain", "learned"), default="both",
                     help="which forms to time (profiling runs time one)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the reconstruction kernel flavours on the workload before timing")
+    ap.add_argument("--workload", choices=("voronoi_bubble", "batched"), default="voronoi_bubble",
+                    help="batched: a 128^3 hexahedral and a 986,078-cell Voronoi mesh with random bubbles, "
+                         "stepped as one (a throughput-regime check; the default is the metric's workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -186,7 +191,24 @@ def main() -> int:
 
     log("generating workload")
     t0 = time.time()
-    wl = workloads.voronoi_bubble()
+    parts = None
+    if args.workload == "batched":
+        from synth import meshes as synth_meshes
+        wls = []
+        for i, build in enumerate((lambda: synth_meshes.hex_mesh(128), lambda: synth_meshes.voronoi_box_mesh(79, 3))):
+            m = build()
+            log(f"mesh {i}: {m.n_cells} cells")
+            wls.append(workloads.random_bubbles(m, seed=3 + 17 * i, n_max=1000, K=16, r_hi_h=12.0))
+            log(f"fields {i}: {wls[-1].meta['n_bubbles']} bubbles, {wls[-1].n_mixed} mixed")
+        wl = workloads.concat_workloads(wls)
+        parts = [w.mesh for w in wls]
+        wl_desc = (f"batched: 128^3 hexahedra ({wls[0].meta['n_bubbles']} bubbles) + jittered-BCC Voronoi mesh "
+                   f"of {wls[1].mesh.n_cells:,} cells ({wls[1].meta['n_bubbles']} bubbles), r ~ U[2h, 12h], "
+                   f"per-bubble linear T, one disjoint union")
+    else:
+        wl = workloads.voronoi_bubble()
+        wl_desc = ("voronoi_bubble: 194,672-cell box-clipped jittered-BCC Voronoi mesh of the unit cube "
+                   "(seed 2), vapour bubble r=0.25 at the centre, T_sat + 1.25 K erf((rho-0.25)/0.05) outside")
     log(f"workload ready in {time.time() - t0:.1f} s: {wl.mesh.n_cells} cells, {wl.n_mixed} mixed")
     from paper_2604_14938_amd import vofpc as V
     from paper_2604_14938_amd import train
@@ -196,8 +218,11 @@ def main() -> int:
         replays (HIP events on the context stream), then time the
         reconstruction launch alone the same way."""
         run = runner.PathRun(wl, device=0, ctx=V.Context(0, stream=torch.cuda.Stream()), mlp=mlp,
-                             delta_scale=dscale)
+                             delta_scale=dscale, parts=parts)
         stream = run.ctx.stream
+        if args.autotune:
+            choice, _ = V.autotune(run.ctx, run.mesh, run.alpha)
+            log(f"autotuned flavours per class: {choice}")
         run.step()
         res = run.results()
         g = run.capture()
@@ -271,8 +296,7 @@ def main() -> int:
     log(f"{form} reconstruction kernel: {recon_ms * 1e3:.1f} us, {rf / 1e6:.1f} MFLOP and {rb / 1e6:.2f} MB "
         f"algorithmic -> {tflops:.3f} TFLOP/s, {achieved:.1f} GB/s")
     cfg = {
-        "workload": "voronoi_bubble: 194,672-cell box-clipped jittered-BCC Voronoi mesh of the unit cube "
-                    "(seed 2), vapour bubble r=0.25 at the centre, T_sat + 1.25 K erf((rho-0.25)/0.05) outside",
+        "workload": wl_desc,
         "n_cells": int(wl.mesh.n_cells),
         "n_mixed": int(M),
         "n_band": int(head["n_band"]),
@@ -327,7 +351,7 @@ def main() -> int:
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": tflops / FP64_PEAK_TFLOPS,
-            "traffic": measured_traffic(form),
+            "traffic": measured_traffic(form) if args.workload == "voronoi_bubble" else None,
             "kernel_us": recon_ms * 1e3,
             "algorithmic_flops": rf,
             "algorithmic_bytes": rb,
