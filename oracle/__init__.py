@@ -67,8 +67,10 @@ def _lib():
     lib.orc_reconstruct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_mass_transfer.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, P, P]
+    D, I = ctypes.c_double, ctypes.c_int
+    lib.orc_extrapolate.argtypes = [P, P, P, P, P, P, P, P, D, I, I, D, P, P, P, P]
     for f in ("orc_face_geometry", "orc_cell_geometry", "orc_vertex_field", "orc_cut_cell",
-              "orc_grad", "orc_reconstruct", "orc_mass_transfer"):
+              "orc_grad", "orc_reconstruct", "orc_mass_transfer", "orc_extrapolate"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -196,6 +198,24 @@ def mass_transfer(geom: Geometry, alpha, n, A, gradT, k_l, k_v, h_lv, gl=None, g
     if e:
         raise RuntimeError("orc_mass_transfer failed")
     return mdot, Qdot
+
+
+def extrapolate(mesh, geom: Geometry, alpha, grad, n_int, A, eps_mixed=1e-8, layers=2, max_iter=120, tol=1e-3):
+    """Phase gradients by pseudo-time extrapolation (Eq. extrapolation):
+    returns (G_l [3,N], G_v [3,N], sweeps, domain mask [N] bool)."""
+    om = _om(mesh)
+    N = om.n_cells
+    gl = np.empty((3, N))
+    gv = np.empty((3, N))
+    it = np.zeros(1, np.int32)
+    dom = np.zeros(N, np.int8)
+    e = _lib().orc_extrapolate(om.ref, _p(geom.V), _p(geom.xc), _p(geom.Sf), _p(np.ascontiguousarray(alpha, float)),
+                               _p(np.ascontiguousarray(grad, float)), _p(np.ascontiguousarray(n_int, float)),
+                               _p(np.ascontiguousarray(A, float)), float(eps_mixed), int(layers), int(max_iter),
+                               float(tol), _p(gl), _p(gv), _p(it), _p(dom))
+    if e:
+        raise RuntimeError("orc_extrapolate failed")
+    return gl, gv, int(it[0]), dom.astype(bool)
 
 
 def band_mask(mesh, alpha, eps_mixed=1e-8) -> np.ndarray:

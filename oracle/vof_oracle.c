@@ -695,3 +695,138 @@ int orc_mass_transfer(int64_t N, const double *V, const double *alpha, const dou
   }
   return 0;
 }
+
+/* ------------------------------------------------- gradient extrapolation */
+/* Plain least-squares gradient of a cell field over the interior face
+ * neighbours of P only (App. B without boundary faces). */
+static void lsq_interior(const orc_mesh *m, const double *xc, const double *val, int64_t P, double *g) {
+  int64_t N = m->n_cells;
+  double G[6] = {0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};
+  for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+    int32_t f = m->cell_face[i];
+    int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+    if (Q < 0) continue;
+    double r[3] = {xc[Q] - xc[P], xc[N + Q] - xc[N + P], xc[2 * N + Q] - xc[2 * N + P]};
+    double dv = val[Q] - val[P];
+    G[0] += r[0] * r[0]; G[1] += r[1] * r[1]; G[2] += r[2] * r[2];
+    G[3] += r[0] * r[1]; G[4] += r[0] * r[2]; G[5] += r[1] * r[2];
+    b[0] += r[0] * dv; b[1] += r[1] * dv; b[2] += r[2] * dv;
+  }
+  solve_sym3(G, b, g);
+}
+
+/* Phase gradients at the interface by pseudo-time extrapolation
+ * (Eq. extrapolation, Sec. 2.4.4), applied to each gradient component:
+ *   G_l = G_v = grad (the interface-modified gradient) on the domain D, the
+ *   cells within `layers` interior-face hops of a mixed cell;
+ *   a liquid cell (alpha >= 1/2) keeps G_l and advances G_v, a vapour cell
+ *   keeps G_v and advances G_l, with velocity c = sgn(alpha - 1/2) n, where n
+ *   is the interface normal of a cell with A > 0 and otherwise the unit plain
+ *   least-squares gradient of alpha (no change where that vanishes);
+ *   first-order upwind: with w_f = -c.S_f over the faces of P whose
+ *   neighbour Q is in D and c.S_f < 0 (S_f outward from P), w = sum w_f,
+ *   F_P <- F_P + theta (sum w_f F_Q / w - F_P), theta = min(dtau w / V_P, 1);
+ *   Jacobi sweeps, dtau = min |x_Q - x_P| over interior faces;
+ *   stop at the first sweep whose largest change is below tol, or after
+ *   max_iter sweeps.
+ * gl, gv: [3][N] outputs (equal to grad outside D); iters: sweeps done;
+ * domain (optional, int8 [N]): 1 on D. */
+int orc_extrapolate(const orc_mesh *m, const double *V, const double *xc, const double *Sf, const double *alpha,
+                    const double *grad, const double *n_int, const double *A, double eps, int layers, int max_iter,
+                    double tol, double *gl, double *gv, int32_t *iters, int8_t *domain) {
+  int64_t N = m->n_cells, NF = m->n_faces;
+  int *mark = (int *)malloc(sizeof(int) * (size_t)N);
+  int *next = (int *)malloc(sizeof(int) * (size_t)N);
+  double *nrm = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  double *cur = (double *)malloc(sizeof(double) * 6 * (size_t)N);   /* [field l/v][3][N] */
+  double *nxt = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+  if (!mark || !next || !nrm || !cur || !nxt) {
+    free(mark); free(next); free(nrm); free(cur); free(nxt);
+    return 1;
+  }
+  /* domain: layers of interior face neighbours around the mixed cells */
+  for (int64_t P = 0; P < N; ++P) mark[P] = (alpha[P] > eps && alpha[P] < 1.0 - eps) ? 0 : -1;
+  for (int l = 1; l <= layers; ++l) {
+    memcpy(next, mark, sizeof(int) * (size_t)N);
+    for (int64_t f = 0; f < NF; ++f) {
+      int32_t o = m->face_owner[f], q = m->face_neigh[f];
+      if (q < 0) continue;
+      if (mark[o] == l - 1 && mark[q] < 0) next[q] = l;
+      if (mark[q] == l - 1 && mark[o] < 0) next[o] = l;
+    }
+    memcpy(mark, next, sizeof(int) * (size_t)N);
+  }
+  /* advection direction per domain cell */
+  for (int64_t P = 0; P < N; ++P) {
+    nrm[P] = nrm[N + P] = nrm[2 * N + P] = 0.0;
+    if (mark[P] < 0) continue;
+    if (mark[P] == 0 && A[P] > 0) {
+      for (int d = 0; d < 3; ++d) nrm[d * N + P] = n_int[d * N + P];
+    } else {
+      double g[3];
+      lsq_interior(m, xc, alpha, P, g);
+      double len = sqrt(v_dot(g, g));
+      if (len > 0)
+        for (int d = 0; d < 3; ++d) nrm[d * N + P] = g[d] / len;
+    }
+  }
+  double dtau = DBL_MAX;
+  for (int64_t f = 0; f < NF; ++f) {
+    int32_t o = m->face_owner[f], q = m->face_neigh[f];
+    if (q < 0) continue;
+    double r[3] = {xc[q] - xc[o], xc[N + q] - xc[N + o], xc[2 * N + q] - xc[2 * N + o]};
+    double d = sqrt(v_dot(r, r));
+    if (d < dtau) dtau = d;
+  }
+  for (int k = 0; k < 2; ++k)
+    for (int d = 0; d < 3; ++d)
+      for (int64_t P = 0; P < N; ++P) cur[(k * 3 + d) * N + P] = grad[d * N + P];
+  int it = 0;
+  while (it < max_iter) {
+    memcpy(nxt, cur, sizeof(double) * 6 * (size_t)N);
+    double change = 0.0;
+    for (int64_t P = 0; P < N; ++P) {
+      if (mark[P] < 0) continue;
+      int liquid = alpha[P] >= 0.5;
+      double s = liquid ? 1.0 : -1.0;
+      double c[3] = {s * nrm[P], s * nrm[N + P], s * nrm[2 * N + P]};
+      int fld = liquid ? 1 : 0; /* advanced field: G_v in liquid, G_l in vapour */
+      double w = 0.0, acc[3] = {0, 0, 0};
+      for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+        int32_t f = m->cell_face[i];
+        int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+        if (Q < 0 || mark[Q] < 0) continue;
+        double sg = (m->face_owner[f] == P) ? 1.0 : -1.0;
+        double S[3] = {sg * Sf[f], sg * Sf[NF + f], sg * Sf[2 * NF + f]};
+        double cs = v_dot(c, S);
+        if (!(cs < 0.0)) continue;
+        double wf = -cs;
+        w += wf;
+        for (int d = 0; d < 3; ++d) acc[d] += wf * cur[(fld * 3 + d) * N + Q];
+      }
+      if (!(w > 0.0)) continue;
+      double theta = dtau * w / V[P];
+      if (theta > 1.0) theta = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        double old = cur[(fld * 3 + d) * N + P];
+        double val = old + theta * (acc[d] / w - old);
+        nxt[(fld * 3 + d) * N + P] = val;
+        double ch = fabs(val - old);
+        if (ch > change) change = ch;
+      }
+    }
+    double *t = cur; cur = nxt; nxt = t;
+    ++it;
+    if (change < tol) break;
+  }
+  for (int d = 0; d < 3; ++d)
+    for (int64_t P = 0; P < N; ++P) {
+      gl[d * N + P] = cur[d * N + P];
+      gv[d * N + P] = cur[(3 + d) * N + P];
+    }
+  if (iters) *iters = it;
+  if (domain)
+    for (int64_t P = 0; P < N; ++P) domain[P] = mark[P] >= 0 ? 1 : 0;
+  free(mark); free(next); free(nrm); free(cur); free(nxt);
+  return 0;
+}

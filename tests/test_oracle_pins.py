@@ -406,3 +406,88 @@ def test_two_sided_gradients_are_used_when_given(hex_sphere_wl):
     ql = 0.5 * rec["n"][0] * rec["A"]
     qv = -0.25 * (-2.0 * rec["n"][2]) * rec["A"]
     np.testing.assert_allclose(mdot[has], ((ql + qv) / (10.0 * geom.V))[has], rtol=1e-13)
+
+
+# ---------------------------------------------------------------- extrapolation
+def _sym_boundary(mesh):
+    """A copy of the mesh whose boundary faces are symmetry faces (skipped by
+    the gradient stencil)."""
+    import copy
+    m = copy.copy(mesh)
+    m.face_bc = np.where(mesh.face_neigh < 0, 2, 0).astype(np.int8)
+    return m
+
+
+def test_extrapolation_carries_each_phase_slope_across_a_plane():
+    """Plane interface, alpha linear in the distance (so the alpha-interpolated
+    crossings lie on the plane), T rising with slope G_l in the liquid and G_v
+    in the vapour: the interface-modified gradient is G_l n in liquid cells and
+    G_v n in vapour cells, and the pseudo-time extrapolation (Eq.
+    extrapolation) fills the other phase's field with the other slope, so
+    every domain cell ends with G_l n and G_v n."""
+    mesh = _sym_boundary(meshes.hex_mesh(8))
+    geom = oracle.geometry(mesh)
+    nrm = np.array([0.8, 0.5, 0.2])
+    nrm /= np.linalg.norm(nrm)
+    dist = nrm @ (geom.xc - 0.5)
+    alpha = 0.5 + 0.6 * dist
+    T_sat, Gl, Gv = 373.15, 40.0, -15.0
+    T = T_sat + np.where(dist >= 0, Gl, Gv) * dist
+    grad, _ = oracle.grad(mesh, geom, T, np.zeros(mesh.n_faces), T_sat, alpha, modified=True)
+    liq = alpha >= 0.5
+    np.testing.assert_allclose(grad[:, liq], np.broadcast_to((Gl * nrm)[:, None], grad[:, liq].shape), atol=1e-9)
+    np.testing.assert_allclose(grad[:, ~liq], np.broadcast_to((Gv * nrm)[:, None], grad[:, ~liq].shape), atol=1e-9)
+    N = mesh.n_cells
+    n_int = np.broadcast_to(nrm[:, None], (3, N)).copy()
+    gl, gv, sweeps, dom = oracle.extrapolate(mesh, geom, alpha, grad, n_int, np.ones(N), max_iter=2000, tol=1e-13)
+    assert dom.all() and sweeps < 2000
+    np.testing.assert_allclose(gl, np.broadcast_to((Gl * nrm)[:, None], gl.shape), atol=1e-9)
+    np.testing.assert_allclose(gv, np.broadcast_to((Gv * nrm)[:, None], gv.shape), atol=1e-9)
+
+
+def _rough_extrapolation_case(seed=3):
+    wl = workloads.random_bubbles(meshes.voronoi_box_mesh(8, seed=seed), seed=seed, n_max=12, K=8, r_hi_h=3.0)
+    geom = oracle.geometry(wl.mesh)
+    rec = oracle.reconstruct(wl.mesh, wl.alpha, geom)
+    grad, _ = oracle.grad(wl.mesh, geom, wl.T, wl.T_bface, wl.T_sat, wl.alpha)
+    rng = np.random.default_rng(seed)
+    grad = grad + rng.normal(size=grad.shape) * 5.0      # rough fields: nothing special about them
+    return wl, geom, rec, grad
+
+
+def test_extrapolation_keeps_own_phase_and_obeys_a_maximum_principle():
+    """Each cell keeps its own phase's field (G_l in liquid, G_v in vapour)
+    and cells outside the domain keep the gradient; the upwind update is a
+    convex combination, so every extrapolated value lies within the range of
+    the initial field on the domain."""
+    wl, geom, rec, grad = _rough_extrapolation_case()
+    gl, gv, sweeps, dom = oracle.extrapolate(wl.mesh, geom, wl.alpha, grad, rec["n"], rec["A"])
+    liq = wl.alpha >= 0.5
+    np.testing.assert_array_equal(gl[:, liq], grad[:, liq])
+    np.testing.assert_array_equal(gv[:, ~liq], grad[:, ~liq])
+    np.testing.assert_array_equal(gl[:, ~dom], grad[:, ~dom])
+    np.testing.assert_array_equal(gv[:, ~dom], grad[:, ~dom])
+    for d in range(3):
+        lo, hi = grad[d, dom].min(), grad[d, dom].max()
+        for g in (gl, gv):
+            assert g[d, dom].min() >= lo - 1e-12 and g[d, dom].max() <= hi + 1e-12
+    assert 1 <= sweeps <= 120
+    # the domain holds the mixed cells and two layers of face neighbours
+    mixed = (wl.alpha > 1e-8) & (wl.alpha < 1 - 1e-8)
+    assert dom[mixed].all() and dom.sum() > mixed.sum()
+
+
+def test_extrapolation_phase_swap():
+    """alpha -> 1 - alpha flips every normal and swaps the phases, leaving
+    the advection velocity sgn(alpha - 1/2) n unchanged: the liquid and vapour
+    fields trade places (cells at alpha = 1/2 exactly are excluded by the
+    tie rule)."""
+    wl, geom, rec, grad = _rough_extrapolation_case(seed=5)
+    wl.alpha[wl.alpha == 0.5] += 1e-6          # keep every cell off the tie
+    rec = oracle.reconstruct(wl.mesh, wl.alpha, geom)
+    gl, gv, s1, dom = oracle.extrapolate(wl.mesh, geom, wl.alpha, grad, rec["n"], rec["A"], tol=1e-9)
+    gl2, gv2, s2, dom2 = oracle.extrapolate(wl.mesh, geom, 1.0 - wl.alpha, grad, -rec["n"], rec["A"], tol=1e-9)
+    np.testing.assert_array_equal(dom, dom2)
+    scale = np.abs(grad).max()
+    np.testing.assert_allclose(gl2, gv, atol=1e-9 * scale)
+    np.testing.assert_allclose(gv2, gl, atol=1e-9 * scale)
