@@ -266,6 +266,43 @@ vofpc_status vofpc_mass_transfer(vofpc_ctx ctx, vofpc_mesh mesh, const double *a
                                  double h_lv, double *mdot, double *Qdot, double *mdot_cells,
                                  double *Qdot_cells);
 
+/* ---------------------------------------------------- phase gradients */
+typedef struct {
+  double eps_mixed;  /* mixed cells seed the domain (1e-8) */
+  int32_t layers;    /* rings of interior face neighbours around them (2) */
+  int32_t max_iter;  /* pseudo-time sweeps at most (120) */
+  double tol;        /* stop when the largest change of a sweep is below this (1e-3, units of grad T) */
+} vofpc_extrap_opts;
+
+/* Fill *opts with the defaults above. */
+vofpc_status vofpc_extrap_opts_default(vofpc_extrap_opts *opts);
+
+/* Liquid- and vapour-side temperature gradients at the interface by
+ * pseudo-time extrapolation (Eq. extrapolation, Sec. 2.4.4), for the
+ * two-sided mass transfer of Eq. mass_transfer (pass them to
+ * vofpc_mass_transfer as gradT_l, gradT_v).  On the domain D (mixed cells and
+ * opts->layers rings of interior face neighbours) both fields start from the
+ * interface-modified gradient of T (computed here); a liquid cell (alpha >=
+ * 1/2) keeps gradT_l and advances gradT_v, a vapour cell the reverse, with
+ * velocity sgn(alpha - 1/2) n (the interface normal of itf where A > 0, else
+ * the unit plain least-squares gradient of alpha over interior neighbours),
+ * first-order upwind over the faces to D neighbours, pseudo-time step the
+ * smallest centre distance of two face neighbours with the local Courant
+ * number clipped at 1, Jacobi sweeps until the largest change falls below
+ * opts->tol or opts->max_iter sweeps.
+ * alpha, T: DEVICE [n_cells]; T_bface: DEVICE [n_faces]; mixed_idx, counts,
+ * itf: the compaction and reconstruction of this alpha; opts may be NULL.
+ * gradT_l, gradT_v: DEVICE [3][n_cells], written on D only.  report:
+ * optional DEVICE int32[2] = (sweeps done, 1 if a sweep barrier gave up
+ * waiting, which leaves the outputs invalid).  The sweeps run in one
+ * persistent kernel with one block per compute unit.  The first call on a
+ * mesh allocates its scratch (mesh-owned) and must not be captured; later
+ * calls are graph-capturable.  Calls on one mesh must not overlap. */
+vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const double *T,
+                               const double *T_bface, double T_sat, const int32_t *mixed_idx,
+                               const int32_t *counts, const vofpc_interface *itf, const vofpc_extrap_opts *opts,
+                               double *gradT_l, double *gradT_v, int32_t *report);
+
 /* ---------------------------------------------------------- bracket network */
 /* A small network predicts the isovalue of every mixed cell; the
  * reconstruction takes it as the first guess of its bracketed search, whose

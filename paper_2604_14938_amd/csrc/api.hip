@@ -131,6 +131,7 @@ extern "C" vofpc_status vofpc_grad_T(vofpc_ctx ctx, vofpc_mesh mesh, const doubl
   clear_error();
   vofpc_status s = check_pair(ctx, mesh);
   if (s) return s;
+  VOFPC_REQUIRE(T_bface, VOFPC_E_INVALID_ARG, "grad_T: null T_bface");
   return launch_grad(ctx, mesh, T, T_bface, T_sat, alpha, band_idx, counts, scope, variant, grad, status);
 }
 

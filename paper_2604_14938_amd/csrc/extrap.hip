@@ -1,0 +1,339 @@
+// Phase gradients at the interface by pseudo-time extrapolation
+// (Eq. extrapolation, Sec. 2.4.4), each gradient component separately:
+//   the domain D is the mixed cells and `layers` rings of interior face
+//   neighbours around them; on D, G_l = G_v = the interface-modified gradient;
+//   a liquid cell (alpha >= 1/2) keeps G_l and advances G_v, a vapour cell
+//   keeps G_v and advances G_l, with velocity c = sgn(alpha - 1/2) n (n: the
+//   interface normal where the cell has an interface, else the unit plain
+//   least-squares gradient of alpha over interior neighbours);
+//   first-order upwind, Jacobi: with w_f = -c.S_f over the faces whose
+//   neighbour is in D and c.S_f < 0, F_P <- F_P + theta (sum w_f F_Q / w - F_P),
+//   theta = min(dtau w / V_P, 1), dtau = the smallest centre distance of two
+//   face neighbours; stop at the first sweep whose largest change is below
+//   tol, or after max_iter sweeps.
+//
+// The sweeps run in one persistent kernel (one block per compute unit, all
+// resident at once) with a grid barrier between sweeps; its waits are
+// bounded, so a barrier that cannot complete ends the kernel with an error
+// flag instead of hanging.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "vofpc_internal.h"
+
+namespace vofpc {
+
+constexpr int kExBlock = 256;
+constexpr long long kBarrierSpins = 1ll << 24;   // ~1 s of polling, far beyond any sweep
+
+__device__ __forceinline__ bool is_mixed(double a, double eps) { return a > eps && a < 1.0 - eps; }
+
+// layer 0: the mixed cells; everything else outside; the list length is reset
+__global__ __launch_bounds__(kExBlock) void ex_init_kernel(int64_t n, const double *alpha, double eps, int8_t *mark,
+                                                           int32_t *info, uint64_t *mx, unsigned int *bar) {
+  const int64_t P = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
+  if (P < n) mark[P] = is_mixed(alpha[P], eps) ? 0 : -1;
+  if (P == 0) {
+    info[1] = 0;
+    info[2] = 0;
+    info[3] = 0;
+    mx[0] = mx[1] = mx[2] = 0ull;
+    bar[0] = 0u;
+  }
+}
+
+// grow the domain by one ring: neighbours of layer l-1 cells enter at layer l
+__global__ __launch_bounds__(kExBlock) void ex_grow_kernel(DevMesh m, int8_t *mark, int l) {
+  const int64_t f = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
+  if (f >= m.n_faces) return;
+  const int q = m.face_neigh[f];
+  if (q < 0) return;
+  const int o = m.face_owner[f];
+  const int mo = mark[o], mq = mark[q];
+  if (mo == l - 1 && mq < 0) mark[q] = (int8_t)l;
+  if (mq == l - 1 && mo < 0) mark[o] = (int8_t)l;
+}
+
+// domain list (order of the atomic claims; the sweeps do not depend on it)
+__global__ __launch_bounds__(kExBlock) void ex_list_kernel(int64_t n, const int8_t *mark, int32_t *list,
+                                                           int32_t *info) {
+  const int64_t P = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
+  const bool in = P < n && mark[P] >= 0;
+  const uint64_t bm = __ballot(in);
+  if (!bm) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)bm) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(&info[1], __popcll(bm));
+  base = __shfl(base, leader);
+  if (in) list[base + __popcll(bm & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))))] = (int32_t)P;
+}
+
+// advection direction: unit plain gradient of alpha (computed into nrm by
+// the gradient kernel) ...
+__global__ __launch_bounds__(kExBlock) void ex_normalise_kernel(int64_t N, const int32_t *list, const int32_t *info,
+                                                                double *nrm) {
+  const int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
+  if (j >= info[1]) return;
+  const int P = list[j];
+  const double g0 = nrm[P], g1 = nrm[N + P], g2 = nrm[2 * N + P];
+  const double len = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+  nrm[P] = len > 0 ? g0 / len : 0.0;
+  nrm[N + P] = len > 0 ? g1 / len : 0.0;
+  nrm[2 * N + P] = len > 0 ? g2 / len : 0.0;
+}
+
+// ... replaced by the interface normal where the cell has an interface
+__global__ __launch_bounds__(kExBlock) void ex_interface_normal_kernel(int64_t N, const int32_t *mixed,
+                                                                       const int32_t *counts, vofpc_interface itf,
+                                                                       double *nrm) {
+  int64_t n = counts[0];
+  if (n > itf.cap) n = itf.cap;
+  const int64_t k = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
+  if (k >= n) return;
+  if (!(itf.A[k] > 0)) return;
+  const int P = mixed[k];
+  nrm[P] = itf.n[k];
+  nrm[N + P] = itf.n[itf.cap + k];
+  nrm[2 * N + P] = itf.n[2 * itf.cap + k];
+}
+
+// both fields start from the gradient
+__global__ __launch_bounds__(kExBlock) void ex_fields_kernel(int64_t N, const int32_t *list, const int32_t *info,
+                                                             const double *grad, double *buf) {
+  const int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
+  if (j >= info[1]) return;
+  const int P = list[j];
+  for (int d = 0; d < 3; ++d) {
+    const double g = grad[d * N + P];
+    buf[d * N + P] = g;
+    buf[(3 + d) * N + P] = g;
+    buf[(6 + d) * N + P] = g;
+    buf[(9 + d) * N + P] = g;
+  }
+}
+
+struct ExParams {
+  DevMesh m;
+  const double *alpha;
+  const int32_t *list;
+  int32_t *info;
+  uint64_t *mx;
+  unsigned int *bar;
+  const int8_t *mark;
+  const double *nrm;
+  double *buf;   // [2][6][N]
+  double dtau, tol;
+  int max_iter;
+  double *gl, *gv;
+};
+
+// Grid-wide barrier over all blocks of the launch (all resident).  Returns
+// false when the wait ran out (then the error flag is set for every block).
+__device__ bool ex_barrier(const ExParams &p, unsigned int &gen) {
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __threadfence();
+    const unsigned int arrived = __hip_atomic_fetch_add(&p.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&p.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&p.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > kBarrierSpins) {
+          __hip_atomic_store(&p.info[3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (__hip_atomic_load(&p.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    __threadfence();
+  }
+  __syncthreads();
+  ++gen;
+  return ok != 0;
+}
+
+__global__ __launch_bounds__(kExBlock) void ex_sweeps_kernel(ExParams p) {
+  const DevMesh &m = p.m;
+  const int64_t N = m.n_cells, NF = m.n_faces;
+  const int64_t nd = p.info[1];
+  unsigned int gen = 0;
+  if (threadIdx.x == 0) gen = __hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  __shared__ unsigned int gen0;
+  __shared__ double red[kExBlock / 64];
+  if (threadIdx.x == 0) gen0 = gen;
+  __syncthreads();
+  gen = gen0;
+  int it = 0, last = 0;   // last: the buffer holding the newest iterate
+  while (it < p.max_iter) {
+    const double *cur = p.buf + (int64_t)(it & 1) * 6 * N;
+    double *nxt = p.buf + (int64_t)((it + 1) & 1) * 6 * N;
+    double change = 0.0;
+    for (int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x; j < nd; j += (int64_t)gridDim.x * kExBlock) {
+      const int P = p.list[j];
+      const bool liquid = p.alpha[P] >= 0.5;
+      const double sgn = liquid ? 1.0 : -1.0;
+      const double c0 = sgn * p.nrm[P], c1 = sgn * p.nrm[N + P], c2 = sgn * p.nrm[2 * N + P];
+      const int adv = liquid ? 3 : 0, keep = liquid ? 0 : 3;   // G_v advances in liquid, G_l in vapour
+      double w = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      for (int64_t i = m.cell_face_off[P]; i < m.cell_face_off[P + 1]; ++i) {
+        const int f = m.cell_face[i];
+        const int Q = m.cf_nbr[i];
+        if (Q < 0 || p.mark[Q] < 0) continue;
+        const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
+        const double cs = c0 * (sg * m.Sf[f]) + c1 * (sg * m.Sf[NF + f]) + c2 * (sg * m.Sf[2 * NF + f]);
+        if (!(cs < 0.0)) continue;
+        const double wf = -cs;
+        w += wf;
+        a0 += wf * cur[(adv + 0) * N + Q];
+        a1 += wf * cur[(adv + 1) * N + Q];
+        a2 += wf * cur[(adv + 2) * N + Q];
+      }
+      for (int d = 0; d < 3; ++d) nxt[(keep + d) * N + P] = cur[(keep + d) * N + P];
+      const double o0 = cur[(adv + 0) * N + P], o1 = cur[(adv + 1) * N + P], o2 = cur[(adv + 2) * N + P];
+      double n0 = o0, n1 = o1, n2 = o2;
+      if (w > 0.0) {
+        double theta = p.dtau * w / m.V[P];
+        if (theta > 1.0) theta = 1.0;
+        n0 = o0 + theta * (a0 / w - o0);
+        n1 = o1 + theta * (a1 / w - o1);
+        n2 = o2 + theta * (a2 / w - o2);
+      }
+      nxt[(adv + 0) * N + P] = n0;
+      nxt[(adv + 1) * N + P] = n1;
+      nxt[(adv + 2) * N + P] = n2;
+      change = fmax(change, fmax(fabs(n0 - o0), fmax(fabs(n1 - o1), fabs(n2 - o2))));
+    }
+    // largest change of the sweep: wave, block, then one atomic per block
+    for (int o = 32; o > 0; o >>= 1) change = fmax(change, __shfl_xor(change, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = change;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b = red[0];
+      for (int i = 1; i < kExBlock / 64; ++i) b = fmax(b, red[i]);
+      atomicMax((unsigned long long *)&p.mx[it % 3], (unsigned long long)__double_as_longlong(b));
+    }
+    if (!ex_barrier(p, gen)) return;
+    ++it;
+    last = it & 1;
+    const double total =
+        __longlong_as_double((long long)__hip_atomic_load(&p.mx[(it - 1) % 3], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT));
+    // the slot of the sweep after next was read by every block before this barrier
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.mx[(it + 1) % 3] = 0ull;
+    if (total < p.tol) break;
+  }
+  // outputs on the domain
+  const double *fin = p.buf + (int64_t)last * 6 * N;
+  for (int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x; j < nd; j += (int64_t)gridDim.x * kExBlock) {
+    const int P = p.list[j];
+    for (int d = 0; d < 3; ++d) {
+      p.gl[d * N + P] = fin[d * N + P];
+      p.gv[d * N + P] = fin[(3 + d) * N + P];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) p.info[2] = it;
+}
+
+__global__ void ex_report_kernel(const int32_t *info, int32_t *out) {
+  if (threadIdx.x == 0) {
+    out[0] = info[2];
+    out[1] = info[3];
+  }
+}
+
+}  // namespace vofpc
+
+using namespace vofpc;
+
+extern "C" vofpc_status vofpc_extrap_opts_default(vofpc_extrap_opts *o) {
+  clear_error();
+  VOFPC_REQUIRE(o, VOFPC_E_INVALID_ARG, "extrap_opts_default: null argument");
+  o->eps_mixed = 1e-8;
+  o->layers = 2;
+  o->max_iter = 120;
+  o->tol = 1e-3;
+  return VOFPC_OK;
+}
+
+extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, const double *T,
+                                          const double *T_bface, double T_sat, const int32_t *mixed_idx,
+                                          const int32_t *counts, const vofpc_interface *itf,
+                                          const vofpc_extrap_opts *opts, double *gradT_l, double *gradT_v,
+                                          int32_t *report) {
+  clear_error();
+  VOFPC_REQUIRE(ctx && M && alpha && T && T_bface && mixed_idx && counts && itf && gradT_l && gradT_v,
+                VOFPC_E_INVALID_ARG, "extrapolate: null argument");
+  VOFPC_REQUIRE(M->ctx && M->ctx->device == ctx->device, VOFPC_E_STATE, "extrapolate: mesh on another device");
+  VOFPC_REQUIRE(itf->n && itf->A && itf->cap > 0, VOFPC_E_INVALID_ARG, "extrapolate: interface record incomplete");
+  vofpc_extrap_opts o;
+  if (opts) o = *opts; else vofpc_extrap_opts_default(&o);
+  VOFPC_REQUIRE(o.layers >= 0 && o.layers <= 100 && o.max_iter >= 0 && o.max_iter <= 100000 && o.tol >= 0 &&
+                    o.eps_mixed >= 0 && o.eps_mixed < 0.5,
+                VOFPC_E_INVALID_ARG, "extrapolate: options out of range");
+  VOFPC_HIP(hipSetDevice(ctx->device));
+  const int64_t N = M->d.n_cells, NF = M->d.n_faces;
+  hipStream_t s = ctx->stream;
+  if (!M->ex_buf) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    VOFPC_HIP(hipStreamIsCapturing(s, &cs));
+    VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
+                  "extrapolate: the first call on a mesh sets up its buffers and must not be captured");
+    void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr, *e = nullptr, *f = nullptr, *g = nullptr;
+    vofpc_status st;
+    if ((st = mesh_scratch_alloc(M, (size_t)N, &a)) || (st = mesh_scratch_alloc(M, 4 * (size_t)N, &b)) ||
+        (st = mesh_scratch_alloc(M, 16, &c)) || (st = mesh_scratch_alloc(M, 32, &d)) ||
+        (st = mesh_scratch_alloc(M, 24 * (size_t)N, &e)) || (st = mesh_scratch_alloc(M, 96 * (size_t)N, &f)) ||
+        (st = mesh_scratch_alloc(M, 16, &g)))
+      return st;
+    VOFPC_HIP(hipMemset(g, 0, 16));
+    M->ex_mark = (int8_t *)a; M->ex_list = (int32_t *)b; M->ex_info = (int32_t *)c; M->ex_max = (uint64_t *)d;
+    M->ex_nrm = (double *)e; M->ex_buf = (double *)f; M->ex_bar = (unsigned int *)g;
+  }
+  const unsigned gN = (unsigned)((N + kExBlock - 1) / kExBlock), gF = (unsigned)((NF + kExBlock - 1) / kExBlock);
+  ex_init_kernel<<<gN, kExBlock, 0, s>>>(N, alpha, o.eps_mixed, M->ex_mark, M->ex_info, M->ex_max, M->ex_bar);
+  for (int l = 1; l <= o.layers; ++l) ex_grow_kernel<<<gF, kExBlock, 0, s>>>(M->d, M->ex_mark, l);
+  ex_list_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_mark, M->ex_list, M->ex_info);
+  VOFPC_HIP(hipGetLastError());
+  // gradient of T (interface-modified) and of alpha (plain, interior
+  // neighbours only) on the domain; the domain length sits in ex_info[1],
+  // where the gradient kernel reads its band count
+  const int32_t *dom_counts = M->ex_info;
+  vofpc_status st = launch_grad(ctx, M, T, T_bface, T_sat, alpha, M->ex_list, dom_counts, VOFPC_SCOPE_BAND,
+                                VOFPC_GRAD_MODIFIED, gradT_l, nullptr);
+  if (st) return st;
+  st = launch_grad(ctx, M, alpha, nullptr, 0.0, alpha, M->ex_list, dom_counts, VOFPC_SCOPE_BAND, VOFPC_GRAD_STANDARD,
+                   M->ex_nrm, nullptr);
+  if (st) return st;
+  ex_normalise_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_list, M->ex_info, M->ex_nrm);
+  const unsigned gM = (unsigned)((std::min<int64_t>(itf->cap, N) + kExBlock - 1) / kExBlock);
+  ex_interface_normal_kernel<<<gM, kExBlock, 0, s>>>(N, mixed_idx, counts, *itf, M->ex_nrm);
+  ex_fields_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_list, M->ex_info, gradT_l, M->ex_buf);
+  ExParams p;
+  p.m = M->d;
+  p.alpha = alpha;
+  p.list = M->ex_list;
+  p.info = M->ex_info;
+  p.mx = M->ex_max;
+  p.bar = M->ex_bar;
+  p.mark = M->ex_mark;
+  p.nrm = M->ex_nrm;
+  p.buf = M->ex_buf;
+  p.dtau = M->min_centre_dist;
+  p.tol = o.tol;
+  p.max_iter = o.max_iter;
+  p.gl = gradT_l;
+  p.gv = gradT_v;
+  // one block per compute unit: small blocks, so all are resident together
+  ex_sweeps_kernel<<<(unsigned)ctx->n_cu, kExBlock, 0, s>>>(p);
+  if (report) ex_report_kernel<<<1, 64, 0, s>>>(M->ex_info, report);
+  VOFPC_HIP(hipGetLastError());
+  return VOFPC_OK;
+}

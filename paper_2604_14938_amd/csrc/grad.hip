@@ -52,7 +52,7 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P, int j) {
         val = p.T_sat;
         crossed = 1;
       }
-    } else if (q == -1) {
+    } else if (q == -1 && p.Tb) {   // no boundary values given: interior neighbours only
       const int f = m.cell_face[i];
       r0 = m.xf[f] - xP0; r1 = m.xf[NF + f] - xP1; r2 = m.xf[2 * NF + f] - xP2;
       val = p.Tb[f];
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void grad_kernel(GradParams p) {
 vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh M, const double *T, const double *Tb, double T_sat,
                          const double *alpha, const int32_t *band, const int32_t *counts, int32_t scope,
                          int32_t variant, double *grad, int32_t *status) {
-  VOFPC_REQUIRE(T && Tb && alpha && grad, VOFPC_E_INVALID_ARG, "grad_T: null argument");
+  VOFPC_REQUIRE(T && alpha && grad, VOFPC_E_INVALID_ARG, "grad_T: null argument");
   VOFPC_REQUIRE(scope == VOFPC_SCOPE_BAND || scope == VOFPC_SCOPE_ALL, VOFPC_E_INVALID_ARG, "grad_T: unknown scope");
   VOFPC_REQUIRE(scope == VOFPC_SCOPE_ALL || (band && counts), VOFPC_E_INVALID_ARG,
                 "grad_T: band scope needs band_idx and counts");

@@ -140,6 +140,20 @@ __global__ void vertex_weight_kernel(DevMesh m, const double *xc, double *w, dou
   }
 }
 
+// Smallest |x_Q - x_P| over interior faces: non-negative doubles order like
+// their bit patterns, so an unsigned atomic min reduces them.
+__global__ void centre_distance_kernel(DevMesh m, const double *xc, uint64_t *dmin) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= m.n_faces) return;
+  const int q = m.face_neigh[f];
+  if (q < 0) return;
+  const int o = m.face_owner[f];
+  const int64_t N = m.n_cells;
+  const double r0 = xc[q] - xc[o], r1 = xc[N + q] - xc[N + o], r2 = xc[2 * N + q] - xc[2 * N + o];
+  const double d = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+  atomicMin((unsigned long long *)dmin, (unsigned long long)__double_as_longlong(d));
+}
+
 // -------------------------------------------------------------- host packing
 namespace {
 
@@ -147,6 +161,10 @@ template <class T>
 vofpc_status dev_copy(vofpc_mesh M, const T *host, size_t n, T **out) {
   void *p = nullptr;
   size_t bytes = std::max<size_t>(n * sizeof(T), 16);
+  if (M->n_alloc >= (int)(sizeof(M->alloc) / sizeof(M->alloc[0]))) {
+    set_error("mesh: too many device allocations");
+    return VOFPC_E_STATE;
+  }
   if (hipMalloc(&p, bytes) != hipSuccess) {
     set_error("hipMalloc failed during mesh upload");
     return VOFPC_E_OOM;
@@ -159,6 +177,13 @@ vofpc_status dev_copy(vofpc_mesh M, const T *host, size_t n, T **out) {
 }
 
 }  // namespace
+
+vofpc_status mesh_scratch_alloc(vofpc_mesh M, size_t bytes, void **out) {
+  uint8_t *p = nullptr;
+  vofpc_status st = dev_copy<uint8_t>(M, nullptr, bytes, &p);
+  *out = p;
+  return st;
+}
 
 // Kernel classes of a mesh: the class of its largest cell, and whether its
 // cells spread over several classes (each holding at least 1 % of the cells),
@@ -404,14 +429,31 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   cell_geom_kernel<<<(unsigned)((N + B - 1) / B), B, 0, s>>>(m, m.Sf, m.xf, (double *)m.V, (double *)m.xc, bad);
   ginv_kernel<<<(unsigned)((N + B - 1) / B), B, 0, s>>>(m, m.xc, m.xf, (double *)m.ginv);
   vertex_weight_kernel<<<(unsigned)((NV + B - 1) / B), B, 0, s>>>(m, m.xc, (double *)m.vc_w, (double *)m.vc_wmean);
+  // smallest distance between the centres of two face neighbours (the
+  // pseudo-time step of the gradient extrapolation); as ordered bits of a
+  // non-negative double, reduced by atomic min
+  uint64_t *dmin = nullptr;
+  if ((st = dev_copy<uint64_t>(M, nullptr, 1, &dmin))) {
+    vofpc_mesh_free(M);
+    return st;
+  }
+  VOFPC_HIP(hipMemsetAsync(dmin, 0x7f, sizeof(uint64_t), s));
+  centre_distance_kernel<<<(unsigned)((NF + B - 1) / B), B, 0, s>>>(m, m.xc, dmin);
   VOFPC_HIP(hipGetLastError());
   int32_t hbad = 0;
+  uint64_t hmin = 0;
   VOFPC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  VOFPC_HIP(hipMemcpyAsync(&hmin, dmin, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   VOFPC_HIP(hipStreamSynchronize(s));
   if (hbad) {
     vofpc_mesh_free(M);
     set_error("mesh_upload: a cell has non-positive volume (inverted or open)");
     return VOFPC_E_MESH;
+  }
+  {
+    double d;
+    memcpy(&d, &hmin, sizeof d);
+    M->min_centre_dist = d;   // huge (0x7f7f...) when the mesh has no interior face
   }
   *out = M;
   return VOFPC_OK;
@@ -517,8 +559,11 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
   M->ncf = ncf; M->nfv = nfv; M->ncv = ncv; M->ncl = ncl; M->nvc = nvc;
   {
     int64_t cc[kClasses] = {0, 0, 0, 0};
-    for (int i = 0; i < n; ++i)
+    M->min_centre_dist = ms[0]->min_centre_dist;
+    for (int i = 0; i < n; ++i) {
       for (int c = 0; c < kClasses; ++c) cc[c] += ms[i]->class_cells[c];
+      M->min_centre_dist = std::min(M->min_centre_dist, ms[i]->min_centre_dist);
+    }
     if ((st = setup_classes(M, cc))) {
       vofpc_mesh_free(M);
       return st;

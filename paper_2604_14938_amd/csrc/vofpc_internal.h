@@ -120,7 +120,17 @@ struct vofpc_mesh_s {
   int32_t *bucket_counts;
   // occupancy flavour chosen per class (3 or 4 waves per SIMD; autotuned)
   int tune[vofpc::kClasses];
-  void *alloc[40];
+  // smallest centre distance of two face neighbours (extrapolation step)
+  double min_centre_dist;
+  // gradient-extrapolation scratch, allocated by its first call (outside capture)
+  int8_t *ex_mark = nullptr;       // layer of each cell in the domain (-1 outside)
+  int32_t *ex_list = nullptr;      // domain cells (any order)
+  int32_t *ex_info = nullptr;      // [1] domain size, [2] sweeps done, [3] barrier wait ran out
+  uint64_t *ex_max = nullptr;      // three rotating slots of the largest change (ordered bits)
+  double *ex_nrm = nullptr;        // [3][n_cells] advection direction
+  double *ex_buf = nullptr;        // [2][6][n_cells]: G_l and G_v, two iterates
+  unsigned int *ex_bar = nullptr;  // grid barrier: [0] arrivals, [1] generation
+  void *alloc[64];
   int n_alloc;
 };
 
@@ -149,6 +159,8 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh m, const double *alpha
                                 const double *hhi, const vofpc_interface *out, vofpc_mlp net = nullptr,
                                 double delta = 0.0, double *net_lo = nullptr, double *net_hi = nullptr,
                                 const MdotFuse *mf = nullptr);
+// device scratch owned by a mesh (freed with it)
+vofpc_status mesh_scratch_alloc(vofpc_mesh M, size_t bytes, void **out);
 // device parameters of a network: BF16 weights and FP32 master copy
 const uint16_t *mlp_weights_bf16(vofpc_mlp M);
 const float *mlp_params_f32(vofpc_mlp M);

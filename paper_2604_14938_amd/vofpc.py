@@ -52,6 +52,11 @@ class CInterface(ctypes.Structure):
                 ("cap", I64)]
 
 
+class ExtrapOpts(ctypes.Structure):
+    _fields_ = [("eps_mixed", ctypes.c_double), ("layers", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
+
+
 class StepArgs(ctypes.Structure):
     _fields_ = [("alpha", P), ("T", P), ("T_bface", P), ("T_sat", D), ("k_l", D), ("k_v", D), ("h_lv", D),
                 ("opts", ReconOpts), ("hint_lo", P), ("hint_hi", P), ("mixed_idx", P), ("band_idx", P),
@@ -95,6 +100,8 @@ def _load():
         "vofpc_reconstruct_learned": ([P, P, P, P, P, P, P, D, P, P, P], ctypes.c_int),
         "vofpc_mesh_concat": ([P, P, ctypes.c_int32, P], ctypes.c_int),
         "vofpc_mesh_classes": ([P, P, P, P], ctypes.c_int),
+        "vofpc_extrap_opts_default": ([P], ctypes.c_int),
+        "vofpc_extrapolate": ([P, P, P, P, P, D, P, P, P, P, P, P, P], ctypes.c_int),
         "vofpc_autotune": ([P, P, P, P, ctypes.c_char_p, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -297,6 +304,23 @@ def autotune(ctx: Context, mesh: Mesh, alpha, opts: ReconOpts | None = None, cac
                               cache_path.encode() if cache_path else None, choice, ctypes.byref(hit)),
            "vofpc_autotune")
     return list(choice), bool(hit.value)
+
+
+def extrap_opts(**kw) -> ExtrapOpts:
+    o = ExtrapOpts()
+    _check(lib.vofpc_extrap_opts_default(ctypes.byref(o)), "vofpc_extrap_opts_default")
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def extrapolate(ctx: Context, mesh: Mesh, alpha, T, T_bface, T_sat: float, mixed_idx, counts, itf: Interface,
+                gradT_l, gradT_v, report=None, opts: ExtrapOpts | None = None) -> None:
+    """Phase gradients by pseudo-time extrapolation (see vofpc_extrapolate)."""
+    ci = itf.c()
+    _check(lib.vofpc_extrapolate(ctx.h, mesh.h, _ptr(alpha), _ptr(T), _ptr(T_bface), float(T_sat), _ptr(mixed_idx),
+                                 _ptr(counts), ctypes.byref(ci), ctypes.byref(opts) if opts is not None else None,
+                                 _ptr(gradT_l), _ptr(gradT_v), _ptr(report)), "vofpc_extrapolate")
 
 
 def grad_T(ctx: Context, mesh: Mesh, T, T_bface, T_sat: float, alpha, band_idx, counts, grad, status=None,
