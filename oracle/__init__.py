@@ -69,6 +69,7 @@ def _lib():
                                       ctypes.c_double, ctypes.c_double, P, P]
     D, I = ctypes.c_double, ctypes.c_int
     lib.orc_extrapolate.argtypes = [P, P, P, P, P, P, P, P, D, I, I, D, P, P, P, P]
+    lib.orc_robin.argtypes = [P, P, P, P, P, P, D, D, P, P, P, P, P]
     for f in ("orc_face_geometry", "orc_cell_geometry", "orc_vertex_field", "orc_cut_cell",
               "orc_grad", "orc_reconstruct", "orc_mass_transfer", "orc_extrapolate"):
         getattr(lib, f).restype = ctypes.c_int
@@ -240,3 +241,22 @@ def run_path(wl, **kw) -> dict:
     g, gst = grad(om, geom, wl.T, wl.T_bface, wl.T_sat, wl.alpha)
     mdot, Qdot = mass_transfer(geom, wl.alpha, rec["n"], rec["A"], g, wl.k_l, wl.k_v, wl.h_lv)
     return dict(geom=geom, rec=rec, grad=g, grad_status=gst, mdot=mdot, Qdot=Qdot, omesh=om)
+
+
+def robin(mesh, geom: Geometry, alpha, n_int, A, k_l, k_v):
+    """Interface heat-transfer coefficients of the detached faces
+    (Eq. interface_htc): returns dict with a_cell [N], a_face [2,NF] (owner,
+    neighbour side), d_face [2,NF], area_face [NF], crossing [NF] bool."""
+    om = _om(mesh)
+    N, NF = om.n_cells, om.n_faces
+    a_cell = np.empty(N)
+    a_face = np.empty((2, NF))
+    d_face = np.empty((2, NF))
+    area = np.empty(NF)
+    cross = np.zeros(NF, np.int8)
+    e = _lib().orc_robin(om.ref, _p(geom.xc), _p(geom.Sf), _p(np.ascontiguousarray(alpha, float)),
+                         _p(np.ascontiguousarray(n_int, float)), _p(np.ascontiguousarray(A, float)),
+                         float(k_l), float(k_v), _p(a_cell), _p(a_face), _p(d_face), _p(area), _p(cross))
+    if e:
+        raise RuntimeError("orc_robin failed")
+    return dict(a_cell=a_cell, a_face=a_face, d_face=d_face, area_face=area, crossing=cross.astype(bool))

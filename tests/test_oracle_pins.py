@@ -491,3 +491,124 @@ def test_extrapolation_phase_swap():
     scale = np.abs(grad).max()
     np.testing.assert_allclose(gl2, gv, atol=1e-9 * scale)
     np.testing.assert_allclose(gv2, gl, atol=1e-9 * scale)
+
+
+# ------------------------------------------- interface heat transfer (Robin)
+def _column_case(axis, frac, liquid_high, shear=0.0):
+    """Hex 8^3 with a plane normal to `axis` inside the cells of index 4
+    along it, at fraction `frac` of the cell from its low side; liquid above
+    the plane when liquid_high.  shear != 0 (axis 1 only) moves every vertex
+    by shear*y along x: the cells become parallelepipeds whose y-faces keep
+    the normal e_y while the centre connections across them tilt.  Returns
+    mesh, geometry, alpha, the cell index along the axis, the exact interface
+    arrays (A = h^2, n = +-e_axis in the cut cells) and h."""
+    mesh = meshes.hex_mesh(8)
+    if shear:
+        assert axis == 1
+        xyz = mesh.vert_xyz.copy()
+        xyz[0] += shear * xyz[1]
+        mesh = meshes.Mesh(**{**mesh.__dict__, "vert_xyz": xyz})
+    geom = oracle.geometry(mesh)
+    h = 1.0 / 8
+    idx = np.floor(geom.xc[axis] / h).astype(int)
+    a_cut = 1.0 - frac if liquid_high else frac
+    alpha = np.where(idx < 4, 0.0 if liquid_high else 1.0, 1.0 if liquid_high else 0.0)
+    alpha[idx == 4] = a_cut
+    N = mesh.n_cells
+    n_int = np.zeros((3, N))
+    n_int[axis, idx == 4] = 1.0 if liquid_high else -1.0
+    A = np.where(idx == 4, h * h, 0.0)
+    return mesh, geom, alpha, idx, n_int, A, h
+
+
+@pytest.mark.parametrize("axis,frac,liquid_high,shear",
+                         [(0, 0.3, True, 0.0), (1, 0.65, False, 0.0), (2, 0.45, True, 0.0), (1, 0.3, True, 0.4)])
+def test_robin_coefficients_for_a_plane_parallel_to_the_faces(axis, frac, liquid_high, shear):
+    """A plane parallel to the faces through the cells of index 4: the only
+    detached faces are the h^2 faces between index 3 and 4 (when the cut
+    cell holds more than half of the phase of index 5) or between 4 and 5
+    (otherwise); their projected interface area is h^2, and the alpha-
+    interpolated crossing lies at 1/(2|alpha_cut - alpha_far|) of the centre
+    distance from the far-phase cell, so its normal distance from each centre
+    is that fraction of h (on the sheared mesh too, where the centre
+    connection is longer than h).  Checked against these closed forms, face
+    by face, with the conductivities of each side's phase, for exact
+    interface arrays and (unsheared) for the oracle's own reconstruction."""
+    mesh, geom, alpha, idx, n_int, A, h = _column_case(axis, frac, liquid_high, shear)
+    k_l, k_v = 0.68, 0.025
+    a_cut = alpha[idx == 4][0]
+    lo_alpha = alpha[idx == 3][0]
+    # the detached interface sits between index 3 and 4 when the cut cell is
+    # on the other side of 1/2 from index 3, else between 4 and 5
+    pair = (3, 4) if (lo_alpha - 0.5) * (a_cut - 0.5) < 0 else (4, 5)
+    far = pair[0] if pair[0] != 4 else pair[1]
+    a_far = alpha[idx == far][0]
+    t_far = 0.5 / abs(a_cut - a_far)          # from the far cell's centre, in units of h
+    cases = [(n_int, A, 1e-13)]
+    if not shear:
+        rec = oracle.reconstruct(mesh, alpha, geom)
+        np.testing.assert_allclose(rec["A"][idx == 4], h * h, rtol=1e-12)
+        cases.append((rec["n"], rec["A"], 1e-11))
+    else:
+        # the connection across a y-face is longer than h: a plain distance
+        # would differ from the normal distance by this factor
+        assert np.sqrt(1 + shear ** 2) > 1.05
+    Smag = np.sqrt((geom.Sf ** 2).sum(0))
+    along = np.abs(geom.Sf[axis]) > (1 - 1e-12) * Smag      # faces normal to the axis
+    for nn, AA, tol in cases:
+        r = oracle.robin(mesh, geom, alpha, nn, AA, k_l, k_v)
+        o, q = mesh.face_owner, mesh.face_neigh
+        io, iq = idx[o], np.where(q >= 0, idx[np.maximum(q, 0)], -1)
+        expect = (q >= 0) & along & (np.minimum(io, iq) == pair[0]) & (np.maximum(io, iq) == pair[1])
+        np.testing.assert_array_equal(r["crossing"], expect)
+        f = np.nonzero(expect)[0]
+        assert len(f) == 64
+        np.testing.assert_allclose(r["area_face"][f], h * h, rtol=tol)
+        for side, cells in ((0, o[f]), (1, q[f])):
+            is_far = idx[cells] == far
+            d_exp = np.where(is_far, t_far, 1.0 - t_far) * h
+            k = np.where(alpha[cells] >= 0.5, k_l, k_v)
+            np.testing.assert_allclose(r["d_face"][side, f], d_exp, rtol=1e-12)
+            np.testing.assert_allclose(r["a_face"][side, f], k * h * h / d_exp, rtol=tol)
+        assert not r["a_face"][:, ~expect].any() and not r["area_face"][~expect].any()
+        # per cell: the sum over its detached faces (one each here)
+        a_exp = np.zeros(mesh.n_cells)
+        np.add.at(a_exp, o[f], r["a_face"][0, f])
+        np.add.at(a_exp, q[f], r["a_face"][1, f])
+        np.testing.assert_allclose(r["a_cell"], a_exp, rtol=1e-14)
+
+
+def test_robin_no_face_is_detached_at_alpha_one_half():
+    """A cut cell at alpha = 1/2 exactly is on neither side: the crossing
+    test is strict, so no face is detached and every coefficient is 0."""
+    mesh, geom, alpha, idx, n_int, A, h = _column_case(2, 0.5, True)
+    r = oracle.robin(mesh, geom, alpha, n_int, A, 0.68, 0.025)
+    assert not r["crossing"].any() and not r["a_cell"].any() and not r["a_face"].any()
+
+
+def test_robin_coefficients_phase_swap_and_rigid_motion():
+    """alpha -> 1-alpha with n -> -n and k_l <-> k_v leaves every
+    coefficient unchanged; so does a rotation plus translation of the mesh
+    with the normals rotated."""
+    wl = workloads.random_bubbles(meshes.voronoi_box_mesh(8, seed=9), seed=9, n_max=12, K=8, r_hi_h=3.0)
+    wl.alpha[wl.alpha == 0.5] += 1e-6
+    geom = oracle.geometry(wl.mesh)
+    rec = oracle.reconstruct(wl.mesh, wl.alpha, geom)
+    r0 = oracle.robin(wl.mesh, geom, wl.alpha, rec["n"], rec["A"], 0.68, 0.025)
+    assert r0["crossing"].sum() > 50 and (r0["a_face"][:, r0["crossing"]] > 0).mean() > 0.9
+    r1 = oracle.robin(wl.mesh, geom, 1.0 - wl.alpha, -rec["n"], rec["A"], 0.025, 0.68)
+    np.testing.assert_array_equal(r1["crossing"], r0["crossing"])
+    for k in ("a_cell", "a_face", "d_face", "area_face"):
+        np.testing.assert_allclose(r1[k], r0[k], rtol=1e-9, atol=0)
+    rng = np.random.default_rng(10)
+    Qm, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(Qm) < 0:
+        Qm[:, 0] *= -1
+    t = rng.normal(size=3)
+    m2 = meshes.Mesh(**{**wl.mesh.__dict__, "vert_xyz": Qm @ wl.mesh.vert_xyz + t[:, None]})
+    g2 = oracle.geometry(m2)
+    r2 = oracle.robin(m2, g2, wl.alpha, Qm @ rec["n"], rec["A"], 0.68, 0.025)
+    np.testing.assert_array_equal(r2["crossing"], r0["crossing"])
+    scale = {k: np.abs(r0[k]).max() for k in ("a_cell", "a_face", "d_face", "area_face")}
+    for k in scale:
+        np.testing.assert_allclose(r2[k], r0[k], atol=1e-9 * scale[k])
