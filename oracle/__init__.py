@@ -63,7 +63,8 @@ def _lib():
     lib.orc_cell_geometry.argtypes = [P, P, P]
     lib.orc_vertex_field.argtypes = [P, P, P, ctypes.c_int, P]
     lib.orc_cut_cell.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_double, P]
-    lib.orc_grad.argtypes = [P, P, P, P, P, ctypes.c_double, P, ctypes.c_int, ctypes.c_int, P, P]
+    lib.orc_grad.argtypes = [P, P, P, P, P, ctypes.c_double, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, P, P]
     lib.orc_reconstruct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_mass_transfer.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, P, P]
@@ -173,14 +174,17 @@ def reconstruct(mesh, alpha, geom: Geometry | None = None, *, eps_mixed=1e-8, to
     return out
 
 
-def grad(mesh, geom: Geometry, T, Tb, T_sat, alpha, modified=True, printed=False):
+def grad(mesh, geom: Geometry, T, Tb, T_sat, alpha, modified=True, printed=False, weight=0, extended=False):
+    """Least-squares gradient (App. B): weight 0 uniform, 1 inverse distance,
+    2 inverse distance squared; extended: vertex neighbours instead of face
+    neighbours."""
     om = _om(mesh)
     N = om.n_cells
     g = np.empty((3, N))
     st = np.empty(N, np.int32)
     e = _lib().orc_grad(om.ref, _p(geom.xc), _p(geom.xf), _p(np.ascontiguousarray(T, float)),
                         _p(np.ascontiguousarray(Tb, float)), float(T_sat), _p(np.ascontiguousarray(alpha, float)),
-                        int(modified), int(printed), _p(g), _p(st))
+                        int(modified), int(printed), int(weight), int(extended), _p(g), _p(st))
     if e:
         raise RuntimeError("orc_grad failed")
     return g, st

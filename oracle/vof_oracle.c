@@ -471,49 +471,150 @@ static int solve_sym3(const double G[6] /* xx yy zz xy xz yz */, const double *b
   return 0;
 }
 
+/* Cells sharing at least one vertex with each cell (the extended stencil of
+ * App. B "Neighbour stencil"), as CSR over cells, P itself excluded, in the
+ * order first met walking P's faces and their vertices.  Caller frees. */
+static int vertex_neighbours(const orc_mesh *m, int64_t **off_out, int32_t **nb_out) {
+  int64_t N = m->n_cells, NV = m->n_verts;
+  /* vertex -> cells: each cell once per vertex */
+  int64_t *vo = (int64_t *)calloc((size_t)NV + 1, sizeof(int64_t));
+  int32_t *last = (int32_t *)malloc(sizeof(int32_t) * (size_t)NV);
+  if (!vo || !last) { free(vo); free(last); return 1; }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t v = 0; v < NV; ++v) last[v] = -1;
+    int64_t *fill = NULL;
+    int32_t *vc = NULL;
+    if (pass == 1) {
+      for (int64_t v = 0; v < NV; ++v) vo[v + 1] += vo[v];
+      fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)NV);
+      vc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(vo[NV] ? vo[NV] : 1));
+      if (!fill || !vc) { free(fill); free(vc); free(vo); free(last); return 1; }
+      for (int64_t v = 0; v < NV; ++v) fill[v] = vo[v];
+    }
+    for (int64_t P = 0; P < N; ++P)
+      for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+        int32_t f = m->cell_face[i];
+        for (int64_t k = m->face_vert_off[f]; k < m->face_vert_off[f + 1]; ++k) {
+          int32_t v = m->face_vert[k];
+          if (last[v] == P) continue;
+          last[v] = (int32_t)P;
+          if (pass == 0) vo[v + 1]++;
+          else vc[fill[v]++] = (int32_t)P;
+        }
+      }
+    if (pass == 1) {
+      /* cell -> vertex neighbours */
+      int32_t *stamp = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+      int64_t *off = (int64_t *)calloc((size_t)N + 1, sizeof(int64_t));
+      int64_t cap = 0;
+      if (!stamp || !off) { free(stamp); free(off); free(fill); free(vc); free(vo); free(last); return 1; }
+      for (int64_t P = 0; P < N; ++P) stamp[P] = -1;
+      /* count */
+      for (int64_t P = 0; P < N; ++P) {
+        stamp[P] = (int32_t)P;
+        for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+          int32_t f = m->cell_face[i];
+          for (int64_t k = m->face_vert_off[f]; k < m->face_vert_off[f + 1]; ++k) {
+            int32_t v = m->face_vert[k];
+            for (int64_t j = vo[v]; j < vo[v + 1]; ++j)
+              if (stamp[vc[j]] != (int32_t)P) { stamp[vc[j]] = (int32_t)P; off[P + 1]++; }
+          }
+        }
+      }
+      for (int64_t P = 0; P < N; ++P) off[P + 1] += off[P];
+      cap = off[N];
+      int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cap ? cap : 1));
+      if (!nb) { free(stamp); free(off); free(fill); free(vc); free(vo); free(last); return 1; }
+      for (int64_t P = 0; P < N; ++P) stamp[P] = -1;
+      for (int64_t P = 0; P < N; ++P) {
+        int64_t w = off[P];
+        stamp[P] = (int32_t)P;
+        for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+          int32_t f = m->cell_face[i];
+          for (int64_t k = m->face_vert_off[f]; k < m->face_vert_off[f + 1]; ++k) {
+            int32_t v = m->face_vert[k];
+            for (int64_t j = vo[v]; j < vo[v + 1]; ++j)
+              if (stamp[vc[j]] != (int32_t)P) { stamp[vc[j]] = (int32_t)P; nb[w++] = vc[j]; }
+          }
+        }
+      }
+      free(stamp); free(fill); free(vc);
+      *off_out = off;
+      *nb_out = nb;
+    }
+  }
+  free(vo); free(last);
+  return 0;
+}
+
 /* Least-squares gradient of a cell field (App. B; interface modification of
  * Sec. 2.4.4).  modified: replace a crossing neighbour by (x_f, value_sat);
  * printed: use the printed Eq. front_interpolation weight |a_Q-1/2|/|a_P-a_Q|
  * instead of the linear-interpolation weight (a_P-1/2)/(a_P-a_Q).
+ * weight (App. B "Weighting"): 0 uniform, 1 inverse distance 1/|r|, 2 inverse
+ * distance squared 1/|r|^2, with r the (possibly shortened) displacement;
+ * the fit minimises sum w (dphi - g.r)^2, so G = sum w r r^T, b = sum w r dphi.
+ * extended (App. B "Neighbour stencil"): the interior neighbours are all
+ * cells sharing a vertex with P instead of the face neighbours; the crossing
+ * test and shortening apply to each centre connection alike.
  * Boundary faces with bc==1 act as neighbours at the face centroid with the
  * value Tb[f]; bc==2 (symmetry) faces are skipped.  grad is SoA [3][N]. */
+static void lsq_add(double *G, double *b, const double *r, double dv, int weight) {
+  double w = 1.0;
+  if (weight == 1) w = 1.0 / sqrt(v_dot(r, r));
+  else if (weight == 2) w = 1.0 / v_dot(r, r);
+  G[0] += w * r[0] * r[0]; G[1] += w * r[1] * r[1]; G[2] += w * r[2] * r[2];
+  G[3] += w * r[0] * r[1]; G[4] += w * r[0] * r[2]; G[5] += w * r[1] * r[2];
+  b[0] += w * r[0] * dv; b[1] += w * r[1] * dv; b[2] += w * r[2] * dv;
+}
+
 int orc_grad(const orc_mesh *m, const double *xc, const double *xf, const double *T, const double *Tb,
-             double T_sat, const double *alpha, int modified, int printed, double *grad, int32_t *status) {
+             double T_sat, const double *alpha, int modified, int printed, int weight, int extended,
+             double *grad, int32_t *status) {
   int64_t N = m->n_cells;
+  int64_t *xoff = NULL;
+  int32_t *xnb = NULL;
+  if (extended && vertex_neighbours(m, &xoff, &xnb)) return 1;
   for (int64_t P = 0; P < N; ++P) {
     double G[6] = {0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};
     double xP[3] = {xc[P], xc[N + P], xc[2 * N + P]};
+    /* interior neighbours: the face neighbours, or every vertex neighbour */
+    int64_t n_in = extended ? xoff[P + 1] - xoff[P] : m->cell_face_off[P + 1] - m->cell_face_off[P];
+    for (int64_t j = 0; j < n_in; ++j) {
+      int32_t Q;
+      if (extended) {
+        Q = xnb[xoff[P] + j];
+      } else {
+        int32_t f = m->cell_face[m->cell_face_off[P] + j];
+        Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+        if (Q < 0) continue;
+      }
+      double xQ[3] = {xc[Q], xc[N + Q], xc[2 * N + Q]};
+      double r[3], val = T[Q];
+      v_sub(xQ, xP, r);
+      if (modified && (alpha[P] - 0.5) * (alpha[Q] - 0.5) < 0.0) {
+        double t = printed ? fabs(alpha[Q] - 0.5) / fabs(alpha[P] - alpha[Q])
+                           : (alpha[P] - 0.5) / (alpha[P] - alpha[Q]);
+        r[0] *= t; r[1] *= t; r[2] *= t;
+        val = T_sat;
+      }
+      lsq_add(G, b, r, val - T[P], weight);
+    }
+    /* boundary faces with a value: virtual neighbours at the face centroid */
     for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
       int32_t f = m->cell_face[i];
-      double r[3], val;
-      int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
-      if (Q >= 0) {
-        double xQ[3] = {xc[Q], xc[N + Q], xc[2 * N + Q]};
-        v_sub(xQ, xP, r);
-        val = T[Q];
-        if (modified && (alpha[P] - 0.5) * (alpha[Q] - 0.5) < 0.0) {
-          double t = printed ? fabs(alpha[Q] - 0.5) / fabs(alpha[P] - alpha[Q])
-                             : (alpha[P] - 0.5) / (alpha[P] - alpha[Q]);
-          r[0] *= t; r[1] *= t; r[2] *= t;
-          val = T_sat;
-        }
-      } else if (m->face_bc[f] == 1) {
-        double x[3] = {xf[f], xf[m->n_faces + f], xf[2 * m->n_faces + f]};
-        v_sub(x, xP, r);
-        val = Tb[f];
-      } else {
-        continue;
-      }
-      double dv = val - T[P];
-      G[0] += r[0] * r[0]; G[1] += r[1] * r[1]; G[2] += r[2] * r[2];
-      G[3] += r[0] * r[1]; G[4] += r[0] * r[2]; G[5] += r[1] * r[2];
-      b[0] += r[0] * dv; b[1] += r[1] * dv; b[2] += r[2] * dv;
+      if (m->face_neigh[f] >= 0 || m->face_bc[f] != 1) continue;
+      double x[3] = {xf[f], xf[m->n_faces + f], xf[2 * m->n_faces + f]}, r[3];
+      v_sub(x, xP, r);
+      lsq_add(G, b, r, Tb[f] - T[P], weight);
     }
     double g[3];
     int sing = solve_sym3(G, b, g);
     if (status) status[P] = sing ? ORC_G_SINGULAR : ORC_OK;
     for (int d = 0; d < 3; ++d) grad[d * N + P] = g[d];
   }
+  free(xoff);
+  free(xnb);
   return 0;
 }
 

@@ -304,10 +304,12 @@ def test_least_squares_exact_for_linear_field(small_voronoi_wl):
     np.testing.assert_allclose(grad, np.broadcast_to(g[:, None], grad.shape), rtol=0, atol=1e-11)
 
 
-def test_modified_stencil_exact_for_planar_interface():
+@pytest.mark.parametrize("weight,extended", [(0, False), (1, False), (2, True), (0, True)])
+def test_modified_stencil_exact_for_planar_interface(weight, extended):
     """alpha = 1/2 + kappa dist(x), T = T_sat + G dist(x) for a plane: the
     alpha-interpolated crossing points lie on the plane where T = T_sat, so the
-    interface-modified gradient is exactly G n.  The printed mirror weight of
+    interface-modified gradient is exactly G n, for any weights and for the
+    vertex-neighbour stencil alike.  The printed mirror weight of
     Eq. front_interpolation does not have this property."""
     wl = workloads.voronoi_bubble(n=8, seed=5, r=0.3)
     mesh = wl.mesh
@@ -320,15 +322,16 @@ def test_modified_stencil_exact_for_planar_interface():
     T_sat, G = 373.15, 40.0
     T = T_sat + G * dist
     Tb = T_sat + G * (nrm @ (geom.xf - 0.5))
-    grad, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True)
+    grad, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True, weight=weight, extended=extended)
     np.testing.assert_allclose(grad, np.broadcast_to((G * nrm)[:, None], grad.shape), atol=1e-9)
     band = oracle.band_mask(mesh, alpha)
-    printed, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True, printed=True)
+    printed, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True, printed=True, weight=weight,
+                             extended=extended)
     err = np.linalg.norm(printed - (G * nrm)[:, None], axis=0)
     assert err[band & (np.abs(alpha - 0.5) > 0.05)].max() > 1.0
 
 
-def _one_d_setup(theta_frac, d_over_h, n=8):
+def _one_d_setup(theta_frac, d_over_h, n=8, weight=0, extended=False, full=False):
     """Hex mesh, interface normal to x between two cell columns; returns
     (gradient from the oracle, closed form Eq. g_fm, std ratio)."""
     mesh = meshes.hex_mesh(n)
@@ -349,12 +352,14 @@ def _one_d_setup(theta_frac, d_over_h, n=8):
     T = np.where(np.isclose(x, xP), T_sat + theta, T)
     T = np.where(np.isclose(x, xP + h), T_far, T)
     Tb = np.full(mesh.n_faces, T_sat)
-    grad, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True)
+    grad, _ = oracle.grad(mesh, geom, T, Tb, T_sat, alpha, modified=True, weight=weight, extended=extended)
     P = np.nonzero(np.isclose(x, xP) & np.isclose(geom.xc[1], (n // 2 + 0.5) * h) &
                    np.isclose(geom.xc[2], (n // 2 + 0.5) * h))[0][0]
     d = d_over_h * h
     g_fm = ((T[P] - T_sat) * d + (T_far - T[P]) * h) / (d * d + h * h)   # Eq. g_fm
     g_std = (T_far - T_sat) / (2 * h)                                     # Eq. g_std
+    if full:
+        return grad[:, P], dict(T_P=T[P], T_sat=T_sat, T_far=T_far, d=d, h=h, g_fm=g_fm)
     return grad[:, P], g_fm, g_std
 
 
@@ -364,6 +369,55 @@ def test_one_dimensional_modified_gradient_matches_app_c(d_over_h, theta_frac):
     g, g_fm, _ = _one_d_setup(theta_frac, d_over_h)
     assert g[0] == pytest.approx(g_fm, rel=1e-12)
     assert abs(g[1]) < 1e-9 and abs(g[2]) < 1e-9
+
+
+@pytest.mark.parametrize("d_over_h", [0.3, 0.7])
+@pytest.mark.parametrize("theta_frac", [0.0, 0.2])
+def test_one_dimensional_weighted_gradients(d_over_h, theta_frac):
+    """The same one-dimensional stencil (the interface point at distance d
+    with T_sat, the far neighbour at h) under the weights of App. B: with
+    w = 1/|r| the fit is the secant from the interface point to the far
+    neighbour, (T_far - T_sat)/(d + h); with w = 1/|r|^2 it is the mean of the
+    two one-sided slopes.  The vertex-neighbour stencil with uniform weights
+    shifts every column by the same y/z offsets and gives Eq. g_fm again."""
+    g1, c = _one_d_setup(theta_frac, d_over_h, weight=1, full=True)
+    assert g1[0] == pytest.approx((c["T_far"] - c["T_sat"]) / (c["d"] + c["h"]), rel=1e-12)
+    g2, c = _one_d_setup(theta_frac, d_over_h, weight=2, full=True)
+    mean = 0.5 * ((c["T_P"] - c["T_sat"]) / c["d"] + (c["T_far"] - c["T_P"]) / c["h"])
+    assert g2[0] == pytest.approx(mean, rel=1e-12)
+    ge, c = _one_d_setup(theta_frac, d_over_h, extended=True, full=True)
+    assert ge[0] == pytest.approx(c["g_fm"], rel=1e-12)
+    for g in (g1, g2, ge):
+        assert abs(g[1]) < 1e-9 and abs(g[2]) < 1e-9
+
+
+@pytest.mark.parametrize("weight", [0, 1, 2])
+def test_vertex_neighbour_stencil_on_a_cubic_field(weight):
+    """T = x^2 y on a uniform hex mesh, interior cells at (a, b, .): the face
+    stencil gives (2ab, a^2, 0) for any weights (all distances h); the
+    26-cell vertex stencil gives (2ab, a^2 + c h^2, 0), where c is the
+    w-weighted mean of the squared x offsets (in units of h) over the
+    (x, z) offsets of the y-neighbours: sum_w(sx^2) / sum_w(1) over
+    sx, sz in {-1, 0, 1} with w = (1 + sx^2 + sz^2)^(-k/2): 2/3 for k = 0,
+    (sqrt2 + 4/sqrt3)/(1 + 2 sqrt2 + 4/sqrt3) for k = 1 and 7/13 for k = 2."""
+    n = 8
+    mesh = meshes.hex_mesh(n)
+    geom = oracle.geometry(mesh)
+    h = mesh.h
+    T = geom.xc[0] ** 2 * geom.xc[1]
+    Tb = geom.xf[0] ** 2 * geom.xf[1]
+    one = np.ones(mesh.n_cells)
+    idx = np.floor(geom.xc / h).astype(int)
+    inner = np.all((idx >= 1) & (idx <= n - 2), axis=0)
+    a, b = geom.xc[0, inner], geom.xc[1, inner]
+    c = {0: 2.0 / 3.0, 1: (np.sqrt(2) + 4 / np.sqrt(3)) / (1 + 2 * np.sqrt(2) + 4 / np.sqrt(3)), 2: 7.0 / 13.0}[weight]
+    gf, _ = oracle.grad(mesh, geom, T, Tb, 0.0, one, weight=weight)
+    ge, _ = oracle.grad(mesh, geom, T, Tb, 0.0, one, weight=weight, extended=True)
+    np.testing.assert_allclose(gf[0, inner], 2 * a * b, atol=1e-12)
+    np.testing.assert_allclose(gf[1, inner], a * a, atol=1e-12)
+    np.testing.assert_allclose(ge[0, inner], 2 * a * b, atol=1e-12)
+    np.testing.assert_allclose(ge[1, inner], a * a + c * h * h, atol=1e-12)
+    assert np.abs(gf[2, inner]).max() < 1e-12 and np.abs(ge[2, inner]).max() < 1e-12
 
 
 def test_boost_ratio_reproduces_printed_values():
