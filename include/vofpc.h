@@ -241,12 +241,26 @@ vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha,
 #define VOFPC_GRAD_MODIFIED 0 /* interface-modified stencil (Sec. 2.4.4) */
 #define VOFPC_GRAD_STANDARD 1 /* plain least squares, no modification */
 #define VOFPC_GRAD_PRINTED 2  /* modified, with the printed mirror weight |a_Q-1/2|/|a_P-a_Q| */
+/* Flags or-ed into the variant (App. B, "Weighting" and "Neighbour stencil";
+ * the paper runs with neither): the fit minimises sum w (dT - g.r)^2 with
+ * w = 1/|r| or 1/|r|^2 of the (possibly shortened) displacement r, and the
+ * vertex stencil takes every cell sharing a vertex with P in place of the
+ * face neighbours (crossing test and shortening apply to each connection). */
+#define VOFPC_GRAD_W_INV_DIST 0x10
+#define VOFPC_GRAD_W_INV_DIST2 0x20
+#define VOFPC_GRAD_VERTEX_STENCIL 0x40
 
 /* Interface-modified least-squares gradient of T (App. B with Sec. 2.4.4).
  * T: DEVICE [n_cells]; T_bface: DEVICE [n_faces] (values used on faces with
  * face_bc == 1); alpha: DEVICE [n_cells]; band_idx/counts from
  * vofpc_compact (ignored for VOFPC_SCOPE_ALL).  Band cells build their
- * least-squares matrix on the fly; other cells use the stored inverse.
+ * least-squares matrix on the fly; other cells use the stored inverse (plain
+ * variants without flags only; with a flag every cell builds its own).
+ * variant: VOFPC_GRAD_MODIFIED/STANDARD/PRINTED, optionally or-ed with one
+ * weight flag and VOFPC_GRAD_VERTEX_STENCIL; anything else is
+ * VOFPC_E_INVALID_ARG.  The first call with the vertex stencil on a mesh
+ * builds its cell -> vertex-neighbour lists (mesh-owned, about 4 B per
+ * neighbour; host work plus a copy) and must not be captured.
  * grad: DEVICE [3][n_cells]; status: optional DEVICE int32 [n_cells]
  * (VOFPC_CELL_OK or VOFPC_CELL_G_SINGULAR, written where grad is written). */
 vofpc_status vofpc_grad_T(vofpc_ctx ctx, vofpc_mesh mesh, const double *T, const double *T_bface, double T_sat,
@@ -293,15 +307,51 @@ vofpc_status vofpc_extrap_opts_default(vofpc_extrap_opts *opts);
  * alpha, T: DEVICE [n_cells]; T_bface: DEVICE [n_faces]; mixed_idx, counts,
  * itf: the compaction and reconstruction of this alpha; opts may be NULL.
  * gradT_l, gradT_v: DEVICE [3][n_cells], written on D only.  report:
- * optional DEVICE int32[2] = (sweeps done, 1 if a sweep barrier gave up
- * waiting, which leaves the outputs invalid).  The sweeps run in one
- * persistent kernel with one block per compute unit.  The first call on a
- * mesh allocates its scratch (mesh-owned) and must not be captured; later
- * calls are graph-capturable.  Calls on one mesh must not overlap. */
+ * optional DEVICE int32[2] = (sweeps done, 0).  Each sweep is one kernel;
+ * after convergence the remaining sweep kernels return at once
+ * (opts->max_iter kernels are always issued, so a captured graph holds them
+ * all; an idle one costs a few microseconds).  The first
+ * call on a mesh allocates its scratch (mesh-owned) and must not be captured;
+ * later calls are graph-capturable.  Calls on one mesh must not overlap. */
 vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const double *T,
                                const double *T_bface, double T_sat, const int32_t *mixed_idx,
                                const int32_t *counts, const vofpc_interface *itf, const vofpc_extrap_opts *opts,
                                double *gradT_l, double *gradT_v, int32_t *report);
+
+/* ------------------------------------------ interface coupling coefficients */
+/* Coefficients of the implicit interface condition of the energy equation
+ * (Eq. interface_htc, Sec. 2.4.4 "Heat source/sink").  An interior face f
+ * whose cells P (owner) and Q satisfy (alpha_P - 1/2)(alpha_Q - 1/2) < 0 is
+ * detached: its diffusive coupling is dropped and each of its cells C is tied
+ * to T_sat with a_f,C = k_C A_int,f / d_f,C, added to C's diagonal with
+ * a_f,C T_sat on the right-hand side.  Readings: k_C = k_l when alpha_C >= 1/2,
+ * else k_v; x_f = x_P + t (x_Q - x_P), t = (alpha_P - 1/2)/(alpha_P - alpha_Q)
+ * (the crossing point of the gradient stencil, Eq. front_interpolation);
+ * d_f,C = |nf . (x_f - x_C)| with nf the unit face normal; A_int,f =
+ * |nf . (A_P n_P + A_Q n_Q)|, the face-normal projection of the interface area
+ * vectors of the two cells (zero for a cell that is not in the mixed list).
+ * A side with d = 0 (a centre connection parallel to the face) gets a = 0.
+ *
+ * mixed_idx, band_idx, counts: the lists of vofpc_compact (cells must be
+ * valid ids); itf: the reconstruction of the mixed list (entry k <-> cell
+ * mixed_idx[k]; A and n are read).  Outputs (DEVICE, caller-owned, each
+ * optional):
+ *   a_diag     [n_band] compact over the band list: entry k holds the sum of
+ *              a_f,C over the detached faces of C = band_idx[k] (0 if none);
+ *   face_idx   [face_cap] detached faces, in no particular order;
+ *   face_a     [2][face_cap] a_f on the owner side, then on the neighbour side;
+ *   face_d     [2][face_cap] d_f on the owner side, then the neighbour side;
+ *   face_area  [face_cap] A_int,f;
+ *   n_face     int32[1]: the number of detached faces (required when any face
+ *              output is given); records beyond face_cap are not written, so
+ *              n_face > face_cap means the capacity was too small.
+ * The first call on a mesh allocates a mesh-owned map (4 B per cell) and must
+ * not be captured; later calls are graph-capturable.  Calls on one mesh must
+ * not overlap. */
+vofpc_status vofpc_robin(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed_idx,
+                         const int32_t *band_idx, const int32_t *counts, const vofpc_interface *itf, double k_l,
+                         double k_v, double *a_diag, int64_t face_cap, int32_t *face_idx, double *face_a,
+                         double *face_d, double *face_area, int32_t *n_face);
 
 /* ---------------------------------------------------------- bracket network */
 /* A small network predicts the isovalue of every mixed cell; the

@@ -132,6 +132,14 @@ extern "C" vofpc_status vofpc_grad_T(vofpc_ctx ctx, vofpc_mesh mesh, const doubl
   vofpc_status s = check_pair(ctx, mesh);
   if (s) return s;
   VOFPC_REQUIRE(T_bface, VOFPC_E_INVALID_ARG, "grad_T: null T_bface");
+  if ((variant & VOFPC_GRAD_VERTEX_STENCIL) && !mesh->xn_off) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    VOFPC_HIP(hipStreamIsCapturing(ctx->stream, &cs));
+    VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
+                  "grad_T: the first vertex-stencil call on a mesh builds its lists and must not be captured");
+    s = mesh_vertex_stencil(mesh);
+    if (s) return s;
+  }
   return launch_grad(ctx, mesh, T, T_bface, T_sat, alpha, band_idx, counts, scope, variant, grad, status);
 }
 

@@ -12,34 +12,35 @@
 //   face neighbours; stop at the first sweep whose largest change is below
 //   tol, or after max_iter sweeps.
 //
-// The sweeps run in one persistent kernel (one block per compute unit, all
-// resident at once) with a grid barrier between sweeps; its waits are
-// bounded, so a barrier that cannot complete ends the kernel with an error
-// flag instead of hanging.
+// One kernel per sweep: the kernel boundary is the synchronisation.  A grid
+// barrier inside one persistent kernel was measured slower on this chip: with
+// one block per XCD it lacks memory parallelism, and with many blocks every
+// sweep pays device-scope fences that write back and invalidate the per-XCD
+// L2 caches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 #include "vofpc_internal.h"
+#include "wave_ops.h"
 
 namespace vofpc {
 
 constexpr int kExBlock = 256;
-constexpr long long kBarrierSpins = 1ll << 24;   // ~1 s of polling, far beyond any sweep
 
 __device__ __forceinline__ bool is_mixed(double a, double eps) { return a > eps && a < 1.0 - eps; }
 
 // layer 0: the mixed cells; everything else outside; the list length is reset
 __global__ __launch_bounds__(kExBlock) void ex_init_kernel(int64_t n, const double *alpha, double eps, int8_t *mark,
-                                                           int32_t *info, uint64_t *mx, unsigned int *bar) {
+                                                           int32_t *info, uint64_t *mx) {
   const int64_t P = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
   if (P < n) mark[P] = is_mixed(alpha[P], eps) ? 0 : -1;
   if (P == 0) {
     info[1] = 0;
     info[2] = 0;
     info[3] = 0;
+    info[4] = 0;
     mx[0] = mx[1] = mx[2] = 0ull;
-    bar[0] = 0u;
   }
 }
 
@@ -120,7 +121,6 @@ struct ExParams {
   const int32_t *list;
   int32_t *info;
   uint64_t *mx;
-  unsigned int *bar;
   const int8_t *mark;
   const double *nrm;
   double *buf;   // [2][6][N]
@@ -129,109 +129,105 @@ struct ExParams {
   double *gl, *gv;
 };
 
-// Grid-wide barrier over all blocks of the launch (all resident).  Returns
-// false when the wait ran out (then the error flag is set for every block).
-__device__ bool ex_barrier(const ExParams &p, unsigned int &gen) {
-  __syncthreads();
-  __shared__ int ok;
-  if (threadIdx.x == 0) {
-    ok = 1;
-    __threadfence();
-    const unsigned int arrived = __hip_atomic_fetch_add(&p.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == gridDim.x - 1) {
-      __hip_atomic_store(&p.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&p.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > kBarrierSpins) {
-          __hip_atomic_store(&p.info[3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-      }
-    }
-    if (__hip_atomic_load(&p.info[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-    __threadfence();
-  }
-  __syncthreads();
-  ++gen;
-  return ok != 0;
-}
+constexpr int kExLanes = 16;   // lanes per domain cell in the sweeps (one DPP row)
 
-__global__ __launch_bounds__(kExBlock) void ex_sweeps_kernel(ExParams p) {
+// Upwind update of domain entry j from iterate cur into nxt by the 16 lanes
+// of one row, one face per lane; returns (on lane 0) the largest change of
+// its three advanced components.
+__device__ __forceinline__ double ex_update(const ExParams &p, int64_t j, int lane, const double *cur,
+                                            double *nxt) {
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells, NF = m.n_faces;
-  const int64_t nd = p.info[1];
-  unsigned int gen = 0;
-  if (threadIdx.x == 0) gen = __hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-  __shared__ unsigned int gen0;
-  __shared__ double red[kExBlock / 64];
-  if (threadIdx.x == 0) gen0 = gen;
-  __syncthreads();
-  gen = gen0;
-  int it = 0, last = 0;   // last: the buffer holding the newest iterate
-  while (it < p.max_iter) {
-    const double *cur = p.buf + (int64_t)(it & 1) * 6 * N;
-    double *nxt = p.buf + (int64_t)((it + 1) & 1) * 6 * N;
-    double change = 0.0;
-    for (int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x; j < nd; j += (int64_t)gridDim.x * kExBlock) {
-      const int P = p.list[j];
-      const bool liquid = p.alpha[P] >= 0.5;
-      const double sgn = liquid ? 1.0 : -1.0;
-      const double c0 = sgn * p.nrm[P], c1 = sgn * p.nrm[N + P], c2 = sgn * p.nrm[2 * N + P];
-      const int adv = liquid ? 3 : 0, keep = liquid ? 0 : 3;   // G_v advances in liquid, G_l in vapour
-      double w = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
-      for (int64_t i = m.cell_face_off[P]; i < m.cell_face_off[P + 1]; ++i) {
-        const int f = m.cell_face[i];
-        const int Q = m.cf_nbr[i];
-        if (Q < 0 || p.mark[Q] < 0) continue;
-        const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
-        const double cs = c0 * (sg * m.Sf[f]) + c1 * (sg * m.Sf[NF + f]) + c2 * (sg * m.Sf[2 * NF + f]);
-        if (!(cs < 0.0)) continue;
-        const double wf = -cs;
-        w += wf;
-        a0 += wf * cur[(adv + 0) * N + Q];
-        a1 += wf * cur[(adv + 1) * N + Q];
-        a2 += wf * cur[(adv + 2) * N + Q];
-      }
-      for (int d = 0; d < 3; ++d) nxt[(keep + d) * N + P] = cur[(keep + d) * N + P];
-      const double o0 = cur[(adv + 0) * N + P], o1 = cur[(adv + 1) * N + P], o2 = cur[(adv + 2) * N + P];
-      double n0 = o0, n1 = o1, n2 = o2;
-      if (w > 0.0) {
-        double theta = p.dtau * w / m.V[P];
-        if (theta > 1.0) theta = 1.0;
-        n0 = o0 + theta * (a0 / w - o0);
-        n1 = o1 + theta * (a1 / w - o1);
-        n2 = o2 + theta * (a2 / w - o2);
-      }
-      nxt[(adv + 0) * N + P] = n0;
-      nxt[(adv + 1) * N + P] = n1;
-      nxt[(adv + 2) * N + P] = n2;
-      change = fmax(change, fmax(fabs(n0 - o0), fmax(fabs(n1 - o1), fabs(n2 - o2))));
-    }
-    // largest change of the sweep: wave, block, then one atomic per block
-    for (int o = 32; o > 0; o >>= 1) change = fmax(change, __shfl_xor(change, o));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = change;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double b = red[0];
-      for (int i = 1; i < kExBlock / 64; ++i) b = fmax(b, red[i]);
-      atomicMax((unsigned long long *)&p.mx[it % 3], (unsigned long long)__double_as_longlong(b));
-    }
-    if (!ex_barrier(p, gen)) return;
-    ++it;
-    last = it & 1;
-    const double total =
-        __longlong_as_double((long long)__hip_atomic_load(&p.mx[(it - 1) % 3], __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT));
-    // the slot of the sweep after next was read by every block before this barrier
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.mx[(it + 1) % 3] = 0ull;
-    if (total < p.tol) break;
+  const int P = p.list[j];
+  const bool liquid = p.alpha[P] >= 0.5;
+  const double sgn = liquid ? 1.0 : -1.0;
+  const double c0 = sgn * p.nrm[P], c1 = sgn * p.nrm[N + P], c2 = sgn * p.nrm[2 * N + P];
+  const int adv = liquid ? 3 : 0, keep = liquid ? 0 : 3;   // G_v advances in liquid, G_l in vapour
+  double w = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kExLanes) {
+    const int Q = m.cf_nbr[i];
+    if (Q < 0 || p.mark[Q] < 0) continue;
+    const int f = m.cell_face[i];
+    const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
+    const double cs = c0 * (sg * m.Sf[f]) + c1 * (sg * m.Sf[NF + f]) + c2 * (sg * m.Sf[2 * NF + f]);
+    if (!(cs < 0.0)) continue;
+    const double wf = -cs;
+    w += wf;
+    a0 += wf * cur[(adv + 0) * N + Q];
+    a1 += wf * cur[(adv + 1) * N + Q];
+    a2 += wf * cur[(adv + 2) * N + Q];
   }
-  // outputs on the domain
-  const double *fin = p.buf + (int64_t)last * 6 * N;
+  w = gsum<kExLanes>(w);
+  a0 = gsum<kExLanes>(a0);
+  a1 = gsum<kExLanes>(a1);
+  a2 = gsum<kExLanes>(a2);
+  if (lane < 3) nxt[(keep + lane) * N + P] = cur[(keep + lane) * N + P];
+  if (lane != 0) return 0.0;
+  const double o0 = cur[(adv + 0) * N + P], o1 = cur[(adv + 1) * N + P], o2 = cur[(adv + 2) * N + P];
+  double n0 = o0, n1 = o1, n2 = o2;
+  if (w > 0.0) {
+    double theta = p.dtau * w / m.V[P];
+    if (theta > 1.0) theta = 1.0;
+    n0 = o0 + theta * (a0 / w - o0);
+    n1 = o1 + theta * (a1 / w - o1);
+    n2 = o2 + theta * (a2 / w - o2);
+  }
+  nxt[(adv + 0) * N + P] = n0;
+  nxt[(adv + 1) * N + P] = n1;
+  nxt[(adv + 2) * N + P] = n2;
+  return fmax(fabs(n0 - o0), fmax(fabs(n1 - o1), fabs(n2 - o2)));
+}
+
+// Sweep `it` (0-based) of the Jacobi iteration.  From the second sweep on it
+// first reads the largest change of the previous sweep (complete: it ran in
+// the previous kernel): below tol, the iteration has converged after `it`
+// sweeps and this and every later sweep kernel return at once.
+__global__ __launch_bounds__(kExBlock) void ex_sweep_kernel(ExParams p, int it) {
+  __shared__ double red[kExBlock / 64];
+  if (p.info[4]) return;   // converged earlier
+  if (it > 0) {
+    const double prev = __longlong_as_double((long long)p.mx[(it - 1) % 3]);
+    if (prev < p.tol) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.info[4] = 1;
+        p.info[2] = it;
+      }
+      return;
+    }
+  }
+  // slot it+1 was last read by the kernel of sweep it-1, now complete
+  if (blockIdx.x == 0 && threadIdx.x == 0) p.mx[(it + 1) % 3] = 0ull;
+  const int64_t N = p.m.n_cells;
+  const int64_t nd = p.info[1];
+  const double *cur = p.buf + (int64_t)(it & 1) * 6 * N;
+  double *nxt = p.buf + (int64_t)((it + 1) & 1) * 6 * N;
+  double change = 0.0;
+  // rows of 16 lanes take the domain cells; every lane of a row sees the
+  // same cells, so the row reductions see all its lanes
+  constexpr int kCells = kExBlock / kExLanes;
+  const int lane = threadIdx.x % kExLanes;
+  for (int64_t j = blockIdx.x * (int64_t)kCells + threadIdx.x / kExLanes; j < nd; j += (int64_t)gridDim.x * kCells)
+    change = fmax(change, ex_update(p, j, lane, cur, nxt));
+  // largest change of the sweep: wave, block, then one atomic per block
+  for (int o = 32; o > 0; o >>= 1) change = fmax(change, __shfl_xor(change, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = change;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int i = 1; i < kExBlock / 64; ++i) b = fmax(b, red[i]);
+    atomicMax((unsigned long long *)&p.mx[it % 3], (unsigned long long)__double_as_longlong(b));
+  }
+}
+
+// After the last sweep kernel: the number of sweeps done, and the outputs on
+// the domain from the buffer of the newest iterate.
+__global__ __launch_bounds__(kExBlock) void ex_finish_kernel(ExParams p) {
+  const int64_t N = p.m.n_cells;
+  const int64_t nd = p.info[1];
+  // converged: the count the first idle sweep kernel recorded; otherwise
+  // every sweep ran (the last one counts whether or not it met the tolerance)
+  const int sweeps = p.info[4] ? p.info[2] : p.max_iter;
+  const double *fin = p.buf + (int64_t)(sweeps & 1) * 6 * N;
   for (int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x; j < nd; j += (int64_t)gridDim.x * kExBlock) {
     const int P = p.list[j];
     for (int d = 0; d < 3; ++d) {
@@ -239,7 +235,7 @@ __global__ __launch_bounds__(kExBlock) void ex_sweeps_kernel(ExParams p) {
       p.gv[d * N + P] = fin[(3 + d) * N + P];
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) p.info[2] = it;
+  if (blockIdx.x == 0 && threadIdx.x == 0) p.info[2] = sweeps;
 }
 
 __global__ void ex_report_kernel(const int32_t *info, int32_t *out) {
@@ -286,19 +282,17 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
     VOFPC_HIP(hipStreamIsCapturing(s, &cs));
     VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
                   "extrapolate: the first call on a mesh sets up its buffers and must not be captured");
-    void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr, *e = nullptr, *f = nullptr, *g = nullptr;
+    void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr, *e = nullptr, *f = nullptr;
     vofpc_status st;
     if ((st = mesh_scratch_alloc(M, (size_t)N, &a)) || (st = mesh_scratch_alloc(M, 4 * (size_t)N, &b)) ||
-        (st = mesh_scratch_alloc(M, 16, &c)) || (st = mesh_scratch_alloc(M, 32, &d)) ||
-        (st = mesh_scratch_alloc(M, 24 * (size_t)N, &e)) || (st = mesh_scratch_alloc(M, 96 * (size_t)N, &f)) ||
-        (st = mesh_scratch_alloc(M, 16, &g)))
+        (st = mesh_scratch_alloc(M, 32, &c)) || (st = mesh_scratch_alloc(M, 32, &d)) ||
+        (st = mesh_scratch_alloc(M, 24 * (size_t)N, &e)) || (st = mesh_scratch_alloc(M, 96 * (size_t)N, &f)))
       return st;
-    VOFPC_HIP(hipMemset(g, 0, 16));
     M->ex_mark = (int8_t *)a; M->ex_list = (int32_t *)b; M->ex_info = (int32_t *)c; M->ex_max = (uint64_t *)d;
-    M->ex_nrm = (double *)e; M->ex_buf = (double *)f; M->ex_bar = (unsigned int *)g;
+    M->ex_nrm = (double *)e; M->ex_buf = (double *)f;
   }
   const unsigned gN = (unsigned)((N + kExBlock - 1) / kExBlock), gF = (unsigned)((NF + kExBlock - 1) / kExBlock);
-  ex_init_kernel<<<gN, kExBlock, 0, s>>>(N, alpha, o.eps_mixed, M->ex_mark, M->ex_info, M->ex_max, M->ex_bar);
+  ex_init_kernel<<<gN, kExBlock, 0, s>>>(N, alpha, o.eps_mixed, M->ex_mark, M->ex_info, M->ex_max);
   for (int l = 1; l <= o.layers; ++l) ex_grow_kernel<<<gF, kExBlock, 0, s>>>(M->d, M->ex_mark, l);
   ex_list_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_mark, M->ex_list, M->ex_info);
   VOFPC_HIP(hipGetLastError());
@@ -322,7 +316,6 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   p.list = M->ex_list;
   p.info = M->ex_info;
   p.mx = M->ex_max;
-  p.bar = M->ex_bar;
   p.mark = M->ex_mark;
   p.nrm = M->ex_nrm;
   p.buf = M->ex_buf;
@@ -331,8 +324,14 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   p.max_iter = o.max_iter;
   p.gl = gradT_l;
   p.gv = gradT_v;
-  // one block per compute unit: small blocks, so all are resident together
-  ex_sweeps_kernel<<<(unsigned)ctx->n_cu, kExBlock, 0, s>>>(p);
+  // sweeps: 16 domain cells per block; the finish kernel one cell per thread
+  const unsigned gS = (unsigned)std::max<int64_t>(1, std::min<int64_t>(gN, (int64_t)ctx->n_cu * 2));
+  const unsigned gW = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>((N + kExBlock / kExLanes - 1) / (kExBlock / kExLanes), (int64_t)ctx->n_cu * 4));
+  // one kernel per sweep: the kernel boundary orders the sweeps; once the
+  // tolerance is met the remaining sweep kernels return at once
+  for (int it = 0; it < o.max_iter; ++it) ex_sweep_kernel<<<gW, kExBlock, 0, s>>>(p, it);
+  ex_finish_kernel<<<gS, kExBlock, 0, s>>>(p);
   if (report) ex_report_kernel<<<1, 64, 0, s>>>(M->ex_info, report);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;

@@ -19,9 +19,25 @@ struct GradParams {
   const double *T, *Tb, *alpha;
   double T_sat;
   const int32_t *band, *counts;
-  int scope, variant;
+  int scope, variant;   // base variant (VOFPC_GRAD_MODIFIED/STANDARD/PRINTED)
+  int weight;           // 0 uniform, 1 inverse distance, 2 inverse distance squared
+  const int64_t *xn_off;   // vertex-neighbour stencil (null: face neighbours)
+  const int32_t *xn_cell;
   double *grad;
   int32_t *status;
+};
+
+// least-squares sums of one cell: G (6 components) and b
+struct LsqSums {
+  double xx = 0, yy = 0, zz = 0, xy = 0, xz = 0, yz = 0, b0 = 0, b1 = 0, b2 = 0;
+  __device__ __forceinline__ void add(double r0, double r1, double r2, double dv, int weight) {
+    double w = 1.0;
+    if (weight == 1) w = 1.0 / sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    else if (weight == 2) w = 1.0 / (r0 * r0 + r1 * r1 + r2 * r2);
+    const double w0 = w * r0, w1 = w * r1, w2 = w * r2;
+    xx += w0 * r0; yy += w1 * r1; zz += w2 * r2; xy += w0 * r1; xz += w0 * r2; yz += w1 * r2;
+    b0 += w0 * dv; b1 += w1 * dv; b2 += w2 * dv;
+  }
 };
 
 constexpr int kGradLanes = 16;   // lanes per cell (one DPP row)
@@ -35,34 +51,36 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P, int j) {
   const double aP = p.alpha[P], TP = p.T[P];
   const bool modify = p.variant != VOFPC_GRAD_STANDARD;
   const bool printed = p.variant == VOFPC_GRAD_PRINTED;
-  double xx = 0, yy = 0, zz = 0, xy = 0, xz = 0, yz = 0, b0 = 0, b1 = 0, b2 = 0;
+  LsqSums L;
   int crossed = 0;
-  const int64_t i1 = m.cell_face_off[P + 1];
-  for (int64_t i = m.cell_face_off[P] + j; i < i1; i += kGradLanes) {
+  // an interior neighbour q: the centre connection, shortened to the
+  // alpha-interpolated crossing held at T_sat where the interface cuts it
+  auto interior = [&](int q) {
+    double r0 = m.xc[q] - xP0, r1 = m.xc[N + q] - xP1, r2 = m.xc[2 * N + q] - xP2;
+    const double aQ = p.alpha[q];
+    double val = p.T[q];
+    if (modify && (aP - 0.5) * (aQ - 0.5) < 0.0) {
+      const double t = printed ? fabs(aQ - 0.5) / fabs(aP - aQ) : (aP - 0.5) / (aP - aQ);
+      r0 *= t; r1 *= t; r2 *= t;
+      val = p.T_sat;
+      crossed = 1;
+    }
+    L.add(r0, r1, r2, val - TP, p.weight);
+  };
+  const int64_t i0 = m.cell_face_off[P], i1 = m.cell_face_off[P + 1];
+  if (p.xn_off) {
+    for (int64_t i = p.xn_off[P] + j; i < p.xn_off[P + 1]; i += kGradLanes) interior(p.xn_cell[i]);
+  }
+  for (int64_t i = i0 + j; i < i1; i += kGradLanes) {
     const int q = m.cf_nbr[i];
-    double r0, r1, r2, val;
     if (q >= 0) {
-      r0 = m.xc[q] - xP0; r1 = m.xc[N + q] - xP1; r2 = m.xc[2 * N + q] - xP2;
-      const double aQ = p.alpha[q];
-      val = p.T[q];
-      if (modify && (aP - 0.5) * (aQ - 0.5) < 0.0) {
-        // alpha-interpolated crossing of the centre connection, held at T_sat
-        const double t = printed ? fabs(aQ - 0.5) / fabs(aP - aQ) : (aP - 0.5) / (aP - aQ);
-        r0 *= t; r1 *= t; r2 *= t;
-        val = p.T_sat;
-        crossed = 1;
-      }
+      if (!p.xn_off) interior(q);
     } else if (q == -1 && p.Tb) {   // no boundary values given: interior neighbours only
       const int f = m.cell_face[i];
-      r0 = m.xf[f] - xP0; r1 = m.xf[NF + f] - xP1; r2 = m.xf[2 * NF + f] - xP2;
-      val = p.Tb[f];
-    } else {
-      continue;
+      L.add(m.xf[f] - xP0, m.xf[NF + f] - xP1, m.xf[2 * NF + f] - xP2, p.Tb[f] - TP, p.weight);
     }
-    const double dv = val - TP;
-    xx += r0 * r0; yy += r1 * r1; zz += r2 * r2; xy += r0 * r1; xz += r0 * r2; yz += r1 * r2;
-    b0 += r0 * dv; b1 += r1 * dv; b2 += r2 * dv;
   }
+  double xx = L.xx, yy = L.yy, zz = L.zz, xy = L.xy, xz = L.xz, yz = L.yz, b0 = L.b0, b1 = L.b1, b2 = L.b2;
   xx = gsum<kGradLanes>(xx); yy = gsum<kGradLanes>(yy); zz = gsum<kGradLanes>(zz);
   xy = gsum<kGradLanes>(xy); xz = gsum<kGradLanes>(xz); yz = gsum<kGradLanes>(yz);
   b0 = gsum<kGradLanes>(b0); b1 = gsum<kGradLanes>(b1); b2 = gsum<kGradLanes>(b2);
@@ -70,7 +88,7 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P, int j) {
   if (j != 0) return;
   double g0, g1, g2;
   int st = VOFPC_CELL_OK;
-  if (p.scope == VOFPC_SCOPE_ALL && !crossed) {
+  if (p.scope == VOFPC_SCOPE_ALL && !crossed && p.weight == 0 && !p.xn_off) {
     const double *gi = m.ginv;
     const double ixx = gi[P], iyy = gi[N + P], izz = gi[2 * N + P];
     const double ixy = gi[3 * N + P], ixz = gi[4 * N + P], iyz = gi[5 * N + P];
@@ -119,13 +137,22 @@ vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh M, const double *T, const dou
   VOFPC_REQUIRE(scope == VOFPC_SCOPE_BAND || scope == VOFPC_SCOPE_ALL, VOFPC_E_INVALID_ARG, "grad_T: unknown scope");
   VOFPC_REQUIRE(scope == VOFPC_SCOPE_ALL || (band && counts), VOFPC_E_INVALID_ARG,
                 "grad_T: band scope needs band_idx and counts");
-  VOFPC_REQUIRE(variant >= VOFPC_GRAD_MODIFIED && variant <= VOFPC_GRAD_PRINTED, VOFPC_E_INVALID_ARG,
-                "grad_T: unknown variant");
+  const int base = variant & 0xf, flags = variant & ~0xf;
+  VOFPC_REQUIRE(base >= VOFPC_GRAD_MODIFIED && base <= VOFPC_GRAD_PRINTED &&
+                    (flags & ~(VOFPC_GRAD_W_INV_DIST | VOFPC_GRAD_W_INV_DIST2 | VOFPC_GRAD_VERTEX_STENCIL)) == 0 &&
+                    (flags & (VOFPC_GRAD_W_INV_DIST | VOFPC_GRAD_W_INV_DIST2)) !=
+                        (VOFPC_GRAD_W_INV_DIST | VOFPC_GRAD_W_INV_DIST2),
+                VOFPC_E_INVALID_ARG, "grad_T: unknown variant");
+  VOFPC_REQUIRE(!(flags & VOFPC_GRAD_VERTEX_STENCIL) || M->xn_off, VOFPC_E_STATE,
+                "grad_T: the vertex stencil of this mesh is not built");
   GradParams p;
   p.m = M->d;
   p.T = T; p.Tb = Tb; p.alpha = alpha; p.T_sat = T_sat;
   p.band = band; p.counts = counts;
-  p.scope = scope; p.variant = variant;
+  p.scope = scope; p.variant = base;
+  p.weight = (flags & VOFPC_GRAD_W_INV_DIST) ? 1 : (flags & VOFPC_GRAD_W_INV_DIST2) ? 2 : 0;
+  p.xn_off = (flags & VOFPC_GRAD_VERTEX_STENCIL) ? M->xn_off : nullptr;
+  p.xn_cell = (flags & VOFPC_GRAD_VERTEX_STENCIL) ? M->xn_cell : nullptr;
   p.grad = grad; p.status = status;
   const int64_t N = M->d.n_cells;
   int64_t grid = (N + 15) / 16;

@@ -185,6 +185,46 @@ vofpc_status mesh_scratch_alloc(vofpc_mesh M, size_t bytes, void **out) {
   return st;
 }
 
+// Cell -> vertex-neighbour lists (every cell sharing a vertex with the cell,
+// itself excluded) for the extended gradient stencil, from the mesh's own
+// cell -> vertex and vertex -> cell arrays, built on the host once.
+vofpc_status mesh_vertex_stencil(vofpc_mesh M) {
+  if (M->xn_off) return VOFPC_OK;
+  const int64_t N = M->d.n_cells, NV = M->d.n_verts;
+  std::vector<int64_t> cv_off(N + 1), vc_off(NV + 1);
+  VOFPC_HIP(hipMemcpy(cv_off.data(), M->d.cv_off, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost));
+  VOFPC_HIP(hipMemcpy(vc_off.data(), M->d.vc_off, sizeof(int64_t) * (NV + 1), hipMemcpyDeviceToHost));
+  std::vector<int32_t> cv(cv_off[N]), vc(vc_off[NV]);
+  VOFPC_HIP(hipMemcpy(cv.data(), M->d.cv_gid, sizeof(int32_t) * cv.size(), hipMemcpyDeviceToHost));
+  VOFPC_HIP(hipMemcpy(vc.data(), M->d.vc_cell, sizeof(int32_t) * vc.size(), hipMemcpyDeviceToHost));
+  std::vector<int64_t> off(N + 1, 0);
+  std::vector<int32_t> nb;
+  nb.reserve((size_t)N * 32);
+  std::vector<int32_t> stamp(N, -1);
+  for (int64_t P = 0; P < N; ++P) {
+    stamp[P] = (int32_t)P;
+    for (int64_t a = cv_off[P]; a < cv_off[P + 1]; ++a) {
+      const int32_t v = cv[a];
+      for (int64_t j = vc_off[v]; j < vc_off[v + 1]; ++j) {
+        const int32_t c = vc[j];
+        if (stamp[c] != (int32_t)P) {
+          stamp[c] = (int32_t)P;
+          nb.push_back(c);
+        }
+      }
+    }
+    off[P + 1] = (int64_t)nb.size();
+  }
+  int64_t *d_off = nullptr;
+  int32_t *d_nb = nullptr;
+  vofpc_status st = dev_copy<int64_t>(M, off.data(), off.size(), &d_off);
+  if (!st) st = dev_copy<int32_t>(M, nb.data(), nb.size(), &d_nb);
+  if (st) return st;
+  M->xn_off = d_off;
+  M->xn_cell = d_nb;
+  return VOFPC_OK;
+}
+
 // Kernel classes of a mesh: the class of its largest cell, and whether its
 // cells spread over several classes (each holding at least 1 % of the cells),
 // in which case the reconstruction buckets its mixed entries by class.

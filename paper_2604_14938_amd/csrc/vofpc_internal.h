@@ -125,11 +125,15 @@ struct vofpc_mesh_s {
   // gradient-extrapolation scratch, allocated by its first call (outside capture)
   int8_t *ex_mark = nullptr;       // layer of each cell in the domain (-1 outside)
   int32_t *ex_list = nullptr;      // domain cells (any order)
-  int32_t *ex_info = nullptr;      // [1] domain size, [2] sweeps done, [3] barrier wait ran out
+  int32_t *ex_info = nullptr;      // [1] domain size, [2] sweeps done, [3] unused, [4] converged
   uint64_t *ex_max = nullptr;      // three rotating slots of the largest change (ordered bits)
   double *ex_nrm = nullptr;        // [3][n_cells] advection direction
   double *ex_buf = nullptr;        // [2][6][n_cells]: G_l and G_v, two iterates
-  unsigned int *ex_bar = nullptr;  // grid barrier: [0] arrivals, [1] generation
+  // interface coupling: mixed entry of each cell (-1 between calls)
+  int32_t *rb_entry = nullptr;
+  // vertex-neighbour gradient stencil (built by its first use): CSR over cells
+  int64_t *xn_off = nullptr;
+  int32_t *xn_cell = nullptr;
   void *alloc[64];
   int n_alloc;
 };
@@ -161,6 +165,8 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh m, const double *alpha
                                 const MdotFuse *mf = nullptr);
 // device scratch owned by a mesh (freed with it)
 vofpc_status mesh_scratch_alloc(vofpc_mesh M, size_t bytes, void **out);
+// build the cell -> vertex-neighbour lists of a mesh (synchronous; no-op once built)
+vofpc_status mesh_vertex_stencil(vofpc_mesh M);
 // device parameters of a network: BF16 weights and FP32 master copy
 const uint16_t *mlp_weights_bf16(vofpc_mlp M);
 const float *mlp_params_f32(vofpc_mlp M);

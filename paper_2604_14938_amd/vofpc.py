@@ -25,6 +25,7 @@ BRACKET_PLAIN, BRACKET_HINT = 0, 1
 VERTEX_IDW, VERTEX_MEAN = 0, 1
 SCOPE_BAND, SCOPE_ALL = 0, 1
 GRAD_MODIFIED, GRAD_STANDARD, GRAD_PRINTED = 0, 1, 2
+GRAD_W_INV_DIST, GRAD_W_INV_DIST2, GRAD_VERTEX_STENCIL = 0x10, 0x20, 0x40   # flags or-ed into the variant
 
 P = ctypes.c_void_p
 I32 = ctypes.c_int32
@@ -103,6 +104,7 @@ def _load():
         "vofpc_extrap_opts_default": ([P], ctypes.c_int),
         "vofpc_extrapolate": ([P, P, P, P, P, D, P, P, P, P, P, P, P], ctypes.c_int),
         "vofpc_autotune": ([P, P, P, P, ctypes.c_char_p, P, P], ctypes.c_int),
+        "vofpc_robin": ([P, P, P, P, P, P, P, D, D, P, I64, P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -321,6 +323,21 @@ def extrapolate(ctx: Context, mesh: Mesh, alpha, T, T_bface, T_sat: float, mixed
     _check(lib.vofpc_extrapolate(ctx.h, mesh.h, _ptr(alpha), _ptr(T), _ptr(T_bface), float(T_sat), _ptr(mixed_idx),
                                  _ptr(counts), ctypes.byref(ci), ctypes.byref(opts) if opts is not None else None,
                                  _ptr(gradT_l), _ptr(gradT_v), _ptr(report)), "vofpc_extrapolate")
+
+
+def robin(ctx: Context, mesh: Mesh, alpha, mixed_idx, band_idx, counts, itf: Interface, k_l: float, k_v: float,
+          a_diag=None, face_idx=None, face_a=None, face_d=None, face_area=None, n_face=None) -> None:
+    """Interface coupling coefficients of the detached faces (see vofpc_robin).
+    face_cap is the length of face_idx (or face_area, or face_a's rows)."""
+    cap = 0
+    for t, rows in ((face_idx, 1), (face_area, 1), (face_a, 2), (face_d, 2)):
+        if t is not None:
+            cap = t.numel() // rows
+            break
+    ci = itf.c()
+    _check(lib.vofpc_robin(ctx.h, mesh.h, _ptr(alpha), _ptr(mixed_idx), _ptr(band_idx), _ptr(counts),
+                           ctypes.byref(ci), float(k_l), float(k_v), _ptr(a_diag), int(cap), _ptr(face_idx),
+                           _ptr(face_a), _ptr(face_d), _ptr(face_area), _ptr(n_face)), "vofpc_robin")
 
 
 def grad_T(ctx: Context, mesh: Mesh, T, T_bface, T_sat: float, alpha, band_idx, counts, grad, status=None,

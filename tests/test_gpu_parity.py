@@ -179,6 +179,53 @@ def test_gradient_variants(V, runner, variant):
     run.close()
 
 
+@pytest.mark.parametrize("name", ["vor12", "hex_small_bubbles"])
+@pytest.mark.parametrize("weight,extended,scope", [(1, False, "band"), (2, False, "all"), (0, True, "band"),
+                                                   (1, True, "all"), (2, True, "band")])
+def test_gradient_weights_and_vertex_stencil(V, runner, name, weight, extended, scope):
+    """Least-squares weights 1/|r|, 1/|r|^2 and the vertex-neighbour stencil
+    (App. B) against the oracle, over the band and over every cell."""
+    import torch
+    wl = _wl(name)
+    _say(f"gradient weight={weight} extended={extended} scope={scope} on {name}")
+    run = runner.PathRun(wl)
+    run.step()
+    b = run.buf
+    N = wl.mesh.n_cells
+    out = torch.zeros(3, N, dtype=torch.float64, device=run.dev)
+    st = torch.zeros(N, dtype=torch.int32, device=run.dev)
+    var = V.GRAD_MODIFIED | {0: 0, 1: V.GRAD_W_INV_DIST, 2: V.GRAD_W_INV_DIST2}[weight]
+    if extended:
+        var |= V.GRAD_VERTEX_STENCIL
+    torch.cuda.synchronize()
+    if scope == "all":
+        V.grad_T(run.ctx, run.mesh, run.T, run.Tb, wl.T_sat, run.alpha, None, None, out, st, scope=V.SCOPE_ALL,
+                 variant=var)
+        cells = np.arange(N)
+    else:
+        V.grad_T(run.ctx, run.mesh, run.T, run.Tb, wl.T_sat, run.alpha, b.band_idx, b.counts, out, st, variant=var)
+        cells = run.results()["band_idx"]
+    torch.cuda.synchronize()
+    ref, rst = oracle.grad(wl.mesh, oracle.geometry(wl.mesh), wl.T, wl.T_bface, wl.T_sat, wl.alpha,
+                           weight=weight, extended=extended)
+    parity.check_grad(wl, out.cpu().numpy(), ref, cells)
+    np.testing.assert_array_equal(st.cpu().numpy()[cells], rst[cells])
+    run.close()
+
+
+def test_gradient_variant_flags_are_checked(V, runner):
+    import torch
+    wl = _wl("vor12")
+    run = runner.PathRun(wl)
+    N = wl.mesh.n_cells
+    out = torch.zeros(3, N, dtype=torch.float64, device=run.dev)
+    for bad in (V.GRAD_W_INV_DIST | V.GRAD_W_INV_DIST2, 0x80, 3):
+        with pytest.raises(V.VofpcError):
+            V.grad_T(run.ctx, run.mesh, run.T, run.Tb, wl.T_sat, run.alpha, None, None, out, scope=V.SCOPE_ALL,
+                     variant=bad)
+    run.close()
+
+
 def test_fixed_isovalue_and_vertex_override(V, runner):
     import torch
     wl = _wl("vor12")
