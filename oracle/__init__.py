@@ -71,6 +71,12 @@ def _lib():
     D, I = ctypes.c_double, ctypes.c_int
     lib.orc_extrapolate.argtypes = [P, P, P, P, P, P, P, P, D, I, I, D, P, P, P, P]
     lib.orc_robin.argtypes = [P, P, P, P, P, P, D, D, P, P, P, P, P]
+    lib.orc_csf_smooth.argtypes = [P, P, P, P, P, I, P]
+    lib.orc_lsq_interior.argtypes = [P, P, P, P]
+    lib.orc_csf_normal.argtypes = [P, P, P, P]
+    lib.orc_csf_raw_curvature.argtypes = [P, P, P, P, P, P, P]
+    lib.orc_csf_smooth_curvature.argtypes = [P, P, P, P, P, P, P]
+    lib.orc_csf.argtypes = [P, P, P, P, P, P, I, D, P, P, P, P, P, P]
     for f in ("orc_face_geometry", "orc_cell_geometry", "orc_vertex_field", "orc_cut_cell",
               "orc_grad", "orc_reconstruct", "orc_mass_transfer", "orc_extrapolate"):
         getattr(lib, f).restype = ctypes.c_int
@@ -264,3 +270,53 @@ def robin(mesh, geom: Geometry, alpha, n_int, A, k_l, k_v):
     if e:
         raise RuntimeError("orc_robin failed")
     return dict(a_cell=a_cell, a_face=a_face, d_face=d_face, area_face=area, crossing=cross.astype(bool))
+
+
+# ------------------------------------------------------------- CSF curvature
+def csf(mesh, geom: Geometry, alpha, n_smooth=2, sigma=1.0):
+    """The surface-tension curvature chain (Sec. 2.4, surface tension):
+    dict with alpha_hat [N], n [3,N], kappa_raw, kappa_star, kappa [N], F [3,N]."""
+    om = _om(mesh)
+    N = om.n_cells
+    out = dict(alpha_hat=np.empty(N), n=np.empty((3, N)), kappa_raw=np.empty(N), kappa_star=np.empty(N),
+               kappa=np.empty(N), F=np.empty((3, N)))
+    e = _lib().orc_csf(om.ref, _p(geom.V), _p(geom.xc), _p(geom.Sf), _p(geom.xf),
+                       _p(np.ascontiguousarray(alpha, float)), int(n_smooth), float(sigma), _p(out["alpha_hat"]),
+                       _p(out["n"]), _p(out["kappa_raw"]), _p(out["kappa_star"]), _p(out["kappa"]), _p(out["F"]))
+    if e:
+        raise RuntimeError("orc_csf failed")
+    return out
+
+
+def csf_smooth(mesh, geom: Geometry, alpha, n_smooth):
+    om = _om(mesh)
+    out = np.empty(om.n_cells)
+    if _lib().orc_csf_smooth(om.ref, _p(geom.xc), _p(geom.Sf), _p(geom.xf), _p(np.ascontiguousarray(alpha, float)),
+                             int(n_smooth), _p(out)):
+        raise RuntimeError("orc_csf_smooth failed")
+    return out
+
+
+def lsq_interior(mesh, geom: Geometry, val):
+    om = _om(mesh)
+    g = np.empty((3, om.n_cells))
+    _lib().orc_lsq_interior(om.ref, _p(geom.xc), _p(np.ascontiguousarray(val, float)), _p(g))
+    return g
+
+
+def csf_raw_curvature(mesh, geom: Geometry, n):
+    om = _om(mesh)
+    k = np.empty(om.n_cells)
+    _lib().orc_csf_raw_curvature(om.ref, _p(geom.V), _p(geom.xc), _p(geom.Sf), _p(geom.xf),
+                                 _p(np.ascontiguousarray(n, float)), _p(k))
+    return k
+
+
+def csf_smooth_curvature(mesh, geom: Geometry, alpha_hat, n, kraw):
+    om = _om(mesh)
+    ks = np.empty(om.n_cells)
+    k = np.empty(om.n_cells)
+    _lib().orc_csf_smooth_curvature(om.ref, _p(geom.xc), _p(np.ascontiguousarray(alpha_hat, float)),
+                                    _p(np.ascontiguousarray(n, float)), _p(np.ascontiguousarray(kraw, float)),
+                                    _p(ks), _p(k))
+    return ks, k

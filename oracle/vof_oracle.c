@@ -991,3 +991,171 @@ int orc_robin(const orc_mesh *m, const double *xc, const double *Sf, const doubl
   }
   return 0;
 }
+
+/* ------------------------------------------------- CSF curvature chain */
+/* Surface-tension curvature of the continuum-surface-force model (Sec. 2.4,
+ * momentum terms, surface tension), in the order the method states it:
+ *   smoothing  alpha_hat_P = sum_f alpha_hat_f A_f / sum_f A_f over all faces,
+ *              alpha_hat_f = alpha_P + w_f (alpha_Q - alpha_P) (the printed
+ *              (1 - w_f) alpha_P + w_f alpha_Q, written so that equal values
+ *              stay exact), w_f the geometric weight of Q: the fraction of the
+ *              centre connection P->Q at which it meets the face plane,
+ *              w_f = nf.(x_f - x_P) / nf.(x_Q - x_P); boundary faces take
+ *              alpha_hat_P; Jacobi sweeps, n_smooth of them;
+ *   normal     n_P = grad(alpha_hat)/(|grad(alpha_hat)| + 1e-15), the plain
+ *              least-squares gradient over interior face neighbours (App. B);
+ *   raw        kappa~_P = -div n = -(1/V_P) sum_f n_f . S_f (Gauss, S_f
+ *              outward), n_f = n_P + w_f (n_Q - n_P), n_P on boundary faces;
+ *   step 1     kappa*_P = (kappa~_P w_P + sum_Q kappa~_Q w_Q) /
+ *              (w_P + sum_Q w_Q + 1e-15), w_i = (1 - 2|1/2 - alpha_hat_i|)^8,
+ *              Q over the face neighbours;
+ *   step 2     kappa_P = (kappa*_P w_P + sum_Q kappa*_Q w_Q wn_Q) /
+ *              (w_P + sum_Q w_Q wn_Q + 1e-15), wn_Q = |n_P . s_Q|^8, s_Q the
+ *              unit centre connection (the 1e-15 of step 1 is added here too:
+ *              without it pure cells divide 0 by 0);
+ *   force      F_P = sigma kappa_P grad(alpha)_P, the plain least-squares
+ *              gradient of the sharp alpha over interior face neighbours.
+ * Each stage is its own function so that it can be checked alone.  Arrays are
+ * SoA, vectors [3][N]. */
+static double face_weight(const orc_mesh *m, const double *xc, const double *Sf, const double *xf, int32_t f,
+                          int64_t P, int64_t Q) {
+  int64_t N = m->n_cells, NF = m->n_faces;
+  double S[3] = {Sf[f], Sf[NF + f], Sf[2 * NF + f]};
+  double a = 0.0, b = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    a += S[d] * (xf[d * NF + f] - xc[d * N + P]);
+    b += S[d] * (xc[d * N + Q] - xc[d * N + P]);
+  }
+  return a / b;
+}
+
+int orc_csf_smooth(const orc_mesh *m, const double *xc, const double *Sf, const double *xf, const double *alpha,
+                   int n_smooth, double *alpha_hat) {
+  int64_t N = m->n_cells, NF = m->n_faces;
+  double *cur = (double *)malloc(sizeof(double) * (size_t)N);
+  if (!cur) return 1;
+  memcpy(alpha_hat, alpha, sizeof(double) * (size_t)N);
+  for (int it = 0; it < n_smooth; ++it) {
+    memcpy(cur, alpha_hat, sizeof(double) * (size_t)N);
+    for (int64_t P = 0; P < N; ++P) {
+      double num = 0.0, den = 0.0;
+      for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+        int32_t f = m->cell_face[i];
+        int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+        double A = sqrt(Sf[f] * Sf[f] + Sf[NF + f] * Sf[NF + f] + Sf[2 * NF + f] * Sf[2 * NF + f]);
+        double af = cur[P];
+        if (Q >= 0) af = cur[P] + face_weight(m, xc, Sf, xf, f, P, Q) * (cur[Q] - cur[P]);
+        num += af * A;
+        den += A;
+      }
+      alpha_hat[P] = num / den;
+    }
+  }
+  free(cur);
+  return 0;
+}
+
+/* plain least-squares gradient over interior face neighbours (App. B) */
+int orc_lsq_interior(const orc_mesh *m, const double *xc, const double *val, double *grad) {
+  int64_t N = m->n_cells;
+  for (int64_t P = 0; P < N; ++P) {
+    double g[3];
+    lsq_interior(m, xc, val, P, g);
+    for (int d = 0; d < 3; ++d) grad[d * N + P] = g[d];
+  }
+  return 0;
+}
+
+int orc_csf_normal(const orc_mesh *m, const double *xc, const double *alpha_hat, double *n) {
+  int64_t N = m->n_cells;
+  orc_lsq_interior(m, xc, alpha_hat, n);
+  for (int64_t P = 0; P < N; ++P) {
+    double g[3] = {n[P], n[N + P], n[2 * N + P]};
+    double den = sqrt(v_dot(g, g)) + 1e-15;
+    for (int d = 0; d < 3; ++d) n[d * N + P] = g[d] / den;
+  }
+  return 0;
+}
+
+int orc_csf_raw_curvature(const orc_mesh *m, const double *V, const double *xc, const double *Sf, const double *xf,
+                          const double *n, double *kraw) {
+  int64_t N = m->n_cells, NF = m->n_faces;
+  for (int64_t P = 0; P < N; ++P) {
+    double div = 0.0;
+    for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+      int32_t f = m->cell_face[i];
+      int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+      double sg = (m->face_owner[f] == P) ? 1.0 : -1.0;
+      double nf[3];
+      for (int d = 0; d < 3; ++d) nf[d] = n[d * N + P];
+      if (Q >= 0) {
+        double w = face_weight(m, xc, Sf, xf, f, P, Q);
+        for (int d = 0; d < 3; ++d) nf[d] = n[d * N + P] + w * (n[d * N + Q] - n[d * N + P]);
+      }
+      div += sg * (nf[0] * Sf[f] + nf[1] * Sf[NF + f] + nf[2] * Sf[2 * NF + f]);
+    }
+    kraw[P] = -div / V[P];
+  }
+  return 0;
+}
+
+static double colour_weight(double a) {
+  double w = 1.0 - 2.0 * fabs(0.5 - a);
+  double w2 = w * w, w4 = w2 * w2;
+  return w4 * w4;
+}
+
+int orc_csf_smooth_curvature(const orc_mesh *m, const double *xc, const double *alpha_hat, const double *n,
+                             const double *kraw, double *kstar, double *kappa) {
+  int64_t N = m->n_cells;
+  for (int64_t P = 0; P < N; ++P) {
+    double wP = colour_weight(alpha_hat[P]);
+    double num = kraw[P] * wP, den = wP;
+    for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+      int32_t f = m->cell_face[i];
+      int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+      if (Q < 0) continue;
+      double wQ = colour_weight(alpha_hat[Q]);
+      num += kraw[Q] * wQ;
+      den += wQ;
+    }
+    kstar[P] = num / (den + 1e-15);
+  }
+  for (int64_t P = 0; P < N; ++P) {
+    double wP = colour_weight(alpha_hat[P]);
+    double num = kstar[P] * wP, den = wP;
+    double nP[3] = {n[P], n[N + P], n[2 * N + P]};
+    for (int64_t i = m->cell_face_off[P]; i < m->cell_face_off[P + 1]; ++i) {
+      int32_t f = m->cell_face[i];
+      int32_t Q = (m->face_owner[f] == P) ? m->face_neigh[f] : m->face_owner[f];
+      if (Q < 0) continue;
+      double s[3] = {xc[Q] - xc[P], xc[N + Q] - xc[N + P], xc[2 * N + Q] - xc[2 * N + P]};
+      double len = sqrt(v_dot(s, s));
+      double c = fabs(v_dot(nP, s) / len);
+      double c2 = c * c, c4 = c2 * c2;
+      double wn = c4 * c4;
+      double wQ = colour_weight(alpha_hat[Q]);
+      num += kstar[Q] * wQ * wn;
+      den += wQ * wn;
+    }
+    kappa[P] = num / (den + 1e-15);
+  }
+  return 0;
+}
+
+/* the whole chain; F (optional) = sigma kappa grad(alpha) */
+int orc_csf(const orc_mesh *m, const double *V, const double *xc, const double *Sf, const double *xf,
+            const double *alpha, int n_smooth, double sigma, double *alpha_hat, double *n, double *kraw,
+            double *kstar, double *kappa, double *F) {
+  int64_t N = m->n_cells;
+  if (orc_csf_smooth(m, xc, Sf, xf, alpha, n_smooth, alpha_hat)) return 1;
+  orc_csf_normal(m, xc, alpha_hat, n);
+  orc_csf_raw_curvature(m, V, xc, Sf, xf, n, kraw);
+  orc_csf_smooth_curvature(m, xc, alpha_hat, n, kraw, kstar, kappa);
+  if (F) {
+    orc_lsq_interior(m, xc, alpha, F);
+    for (int64_t P = 0; P < N; ++P)
+      for (int d = 0; d < 3; ++d) F[d * N + P] = sigma * kappa[P] * F[d * N + P];
+  }
+  return 0;
+}
