@@ -14,6 +14,10 @@
 * ``pipe_film``      Voronoi cells of a pipe with a wavy liquid film on the wall.
 * ``batched``        several meshes with many bubbles each (a hexahedral and a
   Voronoi mesh by default), stepped as one disjoint union.
+* ``static_sphere``  one vapour sphere at rest with the Scriven-like erf
+  temperature profile on a hexahedral (n^3) or Voronoi (2 n^3) mesh: the
+  static analogue of the gradient-anisotropy study (Sec. 3.3, gradient
+  anisotropy on structured vs polyhedral meshes).
 * ``multi_instance`` many independent Voronoi meshes of log-uniform sizes, each
   with one bubble moving on a circle around the vertical axis through the box
   centre (rigid rotation, one revolution over the time steps).
@@ -72,6 +76,21 @@ def voronoi_bubble(n: int = 46, seed: int = 2, r: float = 0.25, width: float = 0
     Tb = fields.radial_erf_T(mesh.face_vertex_mean(), c, r, width, dT, T_SAT)
     return Workload(f"voronoi {mesh.n_cells} cells bubble r={r}", mesh, alpha, T, Tb,
                     meta={"spheres": np.array([[*c, r]])})
+
+
+def static_sphere(kind: str = "hex", n: int = 75, seed: int = 11, r: float = 0.25, width: float = 0.05,
+                  dT: float = 1.25, K: int = 16) -> Workload:
+    """A vapour sphere r at the centre of the unit cube, T = T_sat inside and
+    T_sat + dT erf((rho - r)/width) outside, on hex_mesh(n) or
+    voronoi_box_mesh(n, seed) (2 n^3 cells)."""
+    mesh = hex_mesh(n) if kind == "hex" else voronoi_box_mesh(n, seed)
+    c = (0.5, 0.5, 0.5)
+    alpha = fields.sphere_alpha(mesh, np.array([[*c, r]]), K=K)
+    T = fields.radial_erf_T(mesh.cell_vertex_mean(), c, r, width, dT, T_SAT)
+    Tb = fields.radial_erf_T(mesh.face_vertex_mean(), c, r, width, dT, T_SAT)
+    return Workload(f"static sphere on {kind} {mesh.n_cells} cells", mesh, alpha, T, Tb,
+                    meta={"spheres": np.array([[*c, r]]), "centre": np.array(c), "r": r, "width": width,
+                          "dT": dT, "kind": kind})
 
 
 def random_bubbles(mesh: Mesh, seed: int, n_max: int = 1000, K: int = 16,
