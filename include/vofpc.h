@@ -353,6 +353,39 @@ vofpc_status vofpc_robin(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, co
                          double k_v, double *a_diag, int64_t face_cap, int32_t *face_idx, double *face_a,
                          double *face_d, double *face_area, int32_t *n_face);
 
+/* ------------------------------------------------- surface-tension curvature */
+/* Curvature of the continuum-surface-force term (Sec. 2.4, momentum terms,
+ * surface tension), over every cell:
+ *   alpha_hat: n_smooth Jacobi sweeps of the face-area-weighted average of
+ *     face values alpha_P + w_f (alpha_Q - alpha_P), w_f the geometric weight
+ *     of Q (the fraction of the centre connection P->Q at the face plane),
+ *     alpha_P on boundary faces;
+ *   n = grad(alpha_hat) / (|grad(alpha_hat)| + 1e-15), the plain least-squares
+ *     gradient over interior face neighbours (App. B), vapour -> liquid;
+ *   kappa_raw = -div n by the Gauss sum with n_f = n_P + w_f (n_Q - n_P)
+ *     (n_P on boundary faces);
+ *   kappa* = (k~_P w_P + sum_Q k~_Q w_Q) / (w_P + sum_Q w_Q + 1e-15) over the
+ *     face neighbours, w = (1 - 2|1/2 - alpha_hat|)^8;
+ *   kappa = (k*_P w_P + sum_Q k*_Q w_Q wn_Q) / (w_P + sum_Q w_Q wn_Q + 1e-15),
+ *     wn_Q = |n_P . s_Q|^8, s_Q the unit centre connection (the 1e-15 is
+ *     added here too so that pure cells give 0);
+ *   force = sigma kappa grad(alpha), the plain gradient of the sharp alpha.
+ * A droplet (liquid inside) has positive curvature.
+ * alpha: DEVICE [n_cells].  Outputs (DEVICE, caller-owned): alpha_hat [n_cells],
+ * n [3][n_cells], kappa [n_cells] required; kappa_raw [n_cells] and force
+ * [3][n_cells] optional (NULL skips; without force the gradient of alpha is
+ * not computed).  opts NULL: defaults.  The first call on a mesh allocates
+ * its scratch (24 B per cell, mesh-owned) and must not be captured; later
+ * calls are graph-capturable.  Calls on one mesh must not overlap. */
+typedef struct {
+  int32_t n_smooth;  /* smoothing sweeps of alpha (2) */
+  double sigma;      /* surface tension coefficient for the force (1.0) */
+} vofpc_csf_opts;
+
+vofpc_status vofpc_csf_opts_default(vofpc_csf_opts *opts);
+vofpc_status vofpc_curvature(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const vofpc_csf_opts *opts,
+                             double *alpha_hat, double *n, double *kappa_raw, double *kappa, double *force);
+
 /* ---------------------------------------------------------- bracket network */
 /* A small network predicts the isovalue of every mixed cell; the
  * reconstruction takes it as the first guess of its bracketed search, whose

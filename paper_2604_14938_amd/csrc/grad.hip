@@ -88,7 +88,9 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P, int j) {
   if (j != 0) return;
   double g0, g1, g2;
   int st = VOFPC_CELL_OK;
-  if (p.scope == VOFPC_SCOPE_ALL && !crossed && p.weight == 0 && !p.xn_off) {
+  // the stored inverse holds the face stencil with boundary values: usable
+  // for the plain variant when boundary values are given
+  if (p.scope == VOFPC_SCOPE_ALL && !crossed && p.weight == 0 && !p.xn_off && p.Tb) {
     const double *gi = m.ginv;
     const double ixx = gi[P], iyy = gi[N + P], izz = gi[2 * N + P];
     const double ixy = gi[3 * N + P], ixz = gi[4 * N + P], iyz = gi[5 * N + P];

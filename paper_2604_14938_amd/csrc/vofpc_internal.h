@@ -131,6 +131,8 @@ struct vofpc_mesh_s {
   double *ex_buf = nullptr;        // [2][6][n_cells]: G_l and G_v, two iterates
   // interface coupling: mixed entry of each cell (-1 between calls)
   int32_t *rb_entry = nullptr;
+  // curvature scratch: [3][n_cells] (smoothing ping-pong, raw and step-1 curvature)
+  double *csf_buf = nullptr;
   // vertex-neighbour gradient stencil (built by its first use): CSR over cells
   int64_t *xn_off = nullptr;
   int32_t *xn_cell = nullptr;

@@ -105,6 +105,8 @@ def _load():
         "vofpc_extrapolate": ([P, P, P, P, P, D, P, P, P, P, P, P, P], ctypes.c_int),
         "vofpc_autotune": ([P, P, P, P, ctypes.c_char_p, P, P], ctypes.c_int),
         "vofpc_robin": ([P, P, P, P, P, P, P, D, D, P, I64, P, P, P, P, P], ctypes.c_int),
+        "vofpc_csf_opts_default": ([P], ctypes.c_int),
+        "vofpc_curvature": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -323,6 +325,26 @@ def extrapolate(ctx: Context, mesh: Mesh, alpha, T, T_bface, T_sat: float, mixed
     _check(lib.vofpc_extrapolate(ctx.h, mesh.h, _ptr(alpha), _ptr(T), _ptr(T_bface), float(T_sat), _ptr(mixed_idx),
                                  _ptr(counts), ctypes.byref(ci), ctypes.byref(opts) if opts is not None else None,
                                  _ptr(gradT_l), _ptr(gradT_v), _ptr(report)), "vofpc_extrapolate")
+
+
+class CsfOpts(ctypes.Structure):
+    _fields_ = [("n_smooth", ctypes.c_int32), ("sigma", ctypes.c_double)]
+
+
+def csf_opts(**kw) -> CsfOpts:
+    o = CsfOpts()
+    _check(lib.vofpc_csf_opts_default(ctypes.byref(o)), "vofpc_csf_opts_default")
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def curvature(ctx: Context, mesh: Mesh, alpha, alpha_hat, n, kappa, kappa_raw=None, force=None,
+              opts: CsfOpts | None = None) -> None:
+    """Surface-tension curvature chain (see vofpc_curvature)."""
+    _check(lib.vofpc_curvature(ctx.h, mesh.h, _ptr(alpha), ctypes.byref(opts) if opts is not None else None,
+                               _ptr(alpha_hat), _ptr(n), _ptr(kappa_raw), _ptr(kappa), _ptr(force)),
+           "vofpc_curvature")
 
 
 def robin(ctx: Context, mesh: Mesh, alpha, mixed_idx, band_idx, counts, itf: Interface, k_l: float, k_v: float,
