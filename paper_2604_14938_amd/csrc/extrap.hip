@@ -27,12 +27,13 @@
 namespace vofpc {
 
 constexpr int kExBlock = 256;
+constexpr int kExMaxGrid = 1024;   // blocks of the stencil and sweep kernels at most
 
 __device__ __forceinline__ bool is_mixed(double a, double eps) { return a > eps && a < 1.0 - eps; }
 
 // layer 0: the mixed cells; everything else outside; the list length is reset
 __global__ __launch_bounds__(kExBlock) void ex_init_kernel(int64_t n, const double *alpha, double eps, int8_t *mark,
-                                                           int32_t *info, uint64_t *mx) {
+                                                           int32_t *info) {
   const int64_t P = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
   if (P < n) mark[P] = is_mixed(alpha[P], eps) ? 0 : -1;
   if (P == 0) {
@@ -40,7 +41,6 @@ __global__ __launch_bounds__(kExBlock) void ex_init_kernel(int64_t n, const doub
     info[2] = 0;
     info[3] = 0;
     info[4] = 0;
-    mx[0] = mx[1] = mx[2] = 0ull;
   }
 }
 
@@ -119,8 +119,10 @@ struct ExParams {
   DevMesh m;
   const double *alpha;
   const int32_t *list;
+  double *wup;      // per cell-face slot: upwind weight w_f / sum w (0 off the upwind set)
+  double *theta;    // per domain entry: pseudo-time fraction min(dtau sum w / V, 1), 0 without upwind faces
   int32_t *info;
-  uint64_t *mx;
+  double *part;     // [2][grid] per-block largest change of the last two sweeps
   const int8_t *mark;
   const double *nrm;
   double *buf;   // [2][6][N]
@@ -129,52 +131,85 @@ struct ExParams {
   double *gl, *gv;
 };
 
-constexpr int kExLanes = 16;   // lanes per domain cell in the sweeps (one DPP row)
+constexpr int kExLanes = 16;   // lanes per domain cell in the stencil and sweeps (one DPP row)
 
-// Upwind update of domain entry j from iterate cur into nxt by the 16 lanes
-// of one row, one face per lane; returns (on lane 0) the largest change of
-// its three advanced components.
-__device__ __forceinline__ double ex_update(const ExParams &p, int64_t j, int lane, const double *cur,
-                                            double *nxt) {
+// The upwind stencil of domain entry j, fixed for the whole iteration: with
+// c = sgn(alpha - 1/2) n, the faces with c.S_f < 0 (S_f outward) whose
+// neighbour is in the domain get w_f = -c.S_f; each such cell-face slot keeps
+// w_f / sum w, every other slot 0, and the entry keeps
+// theta = min(dtau sum w / V_P, 1) (0 when no face is upwind: no update).
+__device__ __forceinline__ void ex_stencil(const ExParams &p, int64_t j, int lane) {
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells, NF = m.n_faces;
   const int P = p.list[j];
-  const bool liquid = p.alpha[P] >= 0.5;
-  const double sgn = liquid ? 1.0 : -1.0;
+  const double sgn = p.alpha[P] >= 0.5 ? 1.0 : -1.0;
   const double c0 = sgn * p.nrm[P], c1 = sgn * p.nrm[N + P], c2 = sgn * p.nrm[2 * N + P];
-  const int adv = liquid ? 3 : 0, keep = liquid ? 0 : 3;   // G_v advances in liquid, G_l in vapour
-  double w = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kExLanes) {
+  const int64_t i0 = m.cell_face_off[P], i1 = m.cell_face_off[P + 1];
+  double w = 0.0;
+  for (int64_t i = i0 + lane; i < i1; i += kExLanes) {
     const int Q = m.cf_nbr[i];
-    if (Q < 0 || p.mark[Q] < 0) continue;
-    const int f = m.cell_face[i];
-    const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
-    const double cs = c0 * (sg * m.Sf[f]) + c1 * (sg * m.Sf[NF + f]) + c2 * (sg * m.Sf[2 * NF + f]);
-    if (!(cs < 0.0)) continue;
-    const double wf = -cs;
+    double wf = 0.0;
+    if (Q >= 0 && p.mark[Q] >= 0) {
+      const int f = m.cell_face[i];
+      const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
+      const double cs = c0 * (sg * m.Sf[f]) + c1 * (sg * m.Sf[NF + f]) + c2 * (sg * m.Sf[2 * NF + f]);
+      if (cs < 0.0) wf = -cs;
+    }
+    p.wup[i] = wf;
     w += wf;
-    a0 += wf * cur[(adv + 0) * N + Q];
-    a1 += wf * cur[(adv + 1) * N + Q];
-    a2 += wf * cur[(adv + 2) * N + Q];
   }
   w = gsum<kExLanes>(w);
+  if (w > 0.0)
+    for (int64_t i = i0 + lane; i < i1; i += kExLanes) p.wup[i] = p.wup[i] / w;
+  if (lane == 0) {
+    double th = 0.0;
+    if (w > 0.0) {
+      th = p.dtau * w / m.V[P];
+      if (th > 1.0) th = 1.0;
+    }
+    p.theta[j] = th;
+  }
+}
+
+__global__ __launch_bounds__(kExBlock) void ex_stencil_kernel(ExParams p) {
+  constexpr int kCells = kExBlock / kExLanes;
+  const int64_t nd = p.info[1];
+  const int lane = threadIdx.x % kExLanes;
+  for (int64_t j = blockIdx.x * (int64_t)kCells + threadIdx.x / kExLanes; j < nd; j += (int64_t)gridDim.x * kCells)
+    ex_stencil(p, j, lane);
+}
+
+// Upwind update of domain entry j from iterate cur into nxt by the 16 lanes
+// of one row, one face slot per lane; returns (on lane 0) the largest change
+// of its three advanced components.  The kept field was written to both
+// iterates at the start and is not touched.
+__device__ __forceinline__ double ex_update(const ExParams &p, int64_t j, int lane, const double *cur,
+                                            double *nxt) {
+  const DevMesh &m = p.m;
+  const int64_t N = m.n_cells;
+  const int P = p.list[j];
+  const int adv = p.alpha[P] >= 0.5 ? 3 : 0;   // G_v advances in liquid, G_l in vapour
+  const double *ca = cur + (int64_t)adv * N;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kExLanes) {
+    const double wf = p.wup[i];
+    if (wf == 0.0) continue;
+    const int Q = m.cf_nbr[i];
+    a0 += wf * ca[Q];
+    a1 += wf * ca[N + Q];
+    a2 += wf * ca[2 * N + Q];
+  }
   a0 = gsum<kExLanes>(a0);
   a1 = gsum<kExLanes>(a1);
   a2 = gsum<kExLanes>(a2);
-  if (lane < 3) nxt[(keep + lane) * N + P] = cur[(keep + lane) * N + P];
   if (lane != 0) return 0.0;
-  const double o0 = cur[(adv + 0) * N + P], o1 = cur[(adv + 1) * N + P], o2 = cur[(adv + 2) * N + P];
-  double n0 = o0, n1 = o1, n2 = o2;
-  if (w > 0.0) {
-    double theta = p.dtau * w / m.V[P];
-    if (theta > 1.0) theta = 1.0;
-    n0 = o0 + theta * (a0 / w - o0);
-    n1 = o1 + theta * (a1 / w - o1);
-    n2 = o2 + theta * (a2 / w - o2);
-  }
-  nxt[(adv + 0) * N + P] = n0;
-  nxt[(adv + 1) * N + P] = n1;
-  nxt[(adv + 2) * N + P] = n2;
+  const double th = p.theta[j];
+  const double o0 = ca[P], o1 = ca[N + P], o2 = ca[2 * N + P];
+  const double n0 = o0 + th * (a0 - o0), n1 = o1 + th * (a1 - o1), n2 = o2 + th * (a2 - o2);
+  double *na = nxt + (int64_t)adv * N;
+  na[P] = n0;
+  na[N + P] = n1;
+  na[2 * N + P] = n2;
   return fmax(fabs(n0 - o0), fmax(fabs(n1 - o1), fabs(n2 - o2)));
 }
 
@@ -184,9 +219,21 @@ __device__ __forceinline__ double ex_update(const ExParams &p, int64_t j, int la
 // sweeps and this and every later sweep kernel return at once.
 __global__ __launch_bounds__(kExBlock) void ex_sweep_kernel(ExParams p, int it) {
   __shared__ double red[kExBlock / 64];
-  if (p.info[4]) return;   // converged earlier
+  const int converged = p.info[4];
+  const int64_t nd = p.info[1];
+  if (converged) return;
   if (it > 0) {
-    const double prev = __longlong_as_double((long long)p.mx[(it - 1) % 3]);
+    // largest change of the previous sweep: the maximum of its blocks'
+    // partial maxima (every block of that kernel wrote its slot)
+    const double *part = p.part + (int64_t)((it - 1) & 1) * gridDim.x;
+    double prev = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kExBlock) prev = fmax(prev, part[b]);
+    for (int o = 32; o > 0; o >>= 1) prev = fmax(prev, __shfl_xor(prev, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = prev;
+    __syncthreads();
+    prev = red[0];
+    for (int i = 1; i < kExBlock / 64; ++i) prev = fmax(prev, red[i]);
+    __syncthreads();
     if (prev < p.tol) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.info[4] = 1;
@@ -195,10 +242,7 @@ __global__ __launch_bounds__(kExBlock) void ex_sweep_kernel(ExParams p, int it) 
       return;
     }
   }
-  // slot it+1 was last read by the kernel of sweep it-1, now complete
-  if (blockIdx.x == 0 && threadIdx.x == 0) p.mx[(it + 1) % 3] = 0ull;
   const int64_t N = p.m.n_cells;
-  const int64_t nd = p.info[1];
   const double *cur = p.buf + (int64_t)(it & 1) * 6 * N;
   double *nxt = p.buf + (int64_t)((it + 1) & 1) * 6 * N;
   double change = 0.0;
@@ -208,14 +252,15 @@ __global__ __launch_bounds__(kExBlock) void ex_sweep_kernel(ExParams p, int it) 
   const int lane = threadIdx.x % kExLanes;
   for (int64_t j = blockIdx.x * (int64_t)kCells + threadIdx.x / kExLanes; j < nd; j += (int64_t)gridDim.x * kCells)
     change = fmax(change, ex_update(p, j, lane, cur, nxt));
-  // largest change of the sweep: wave, block, then one atomic per block
+  // this block's largest change into its slot of this sweep's partials
+  // (plain stores: the next sweep kernel reads them after the kernel boundary)
   for (int o = 32; o > 0; o >>= 1) change = fmax(change, __shfl_xor(change, o));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = change;
   __syncthreads();
   if (threadIdx.x == 0) {
     double b = red[0];
     for (int i = 1; i < kExBlock / 64; ++i) b = fmax(b, red[i]);
-    atomicMax((unsigned long long *)&p.mx[it % 3], (unsigned long long)__double_as_longlong(b));
+    p.part[(int64_t)(it & 1) * gridDim.x + blockIdx.x] = b;
   }
 }
 
@@ -282,17 +327,19 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
     VOFPC_HIP(hipStreamIsCapturing(s, &cs));
     VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
                   "extrapolate: the first call on a mesh sets up its buffers and must not be captured");
-    void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr, *e = nullptr, *f = nullptr;
+    void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr, *e = nullptr, *f = nullptr, *g = nullptr,
+         *h = nullptr;
     vofpc_status st;
     if ((st = mesh_scratch_alloc(M, (size_t)N, &a)) || (st = mesh_scratch_alloc(M, 4 * (size_t)N, &b)) ||
-        (st = mesh_scratch_alloc(M, 32, &c)) || (st = mesh_scratch_alloc(M, 32, &d)) ||
-        (st = mesh_scratch_alloc(M, 24 * (size_t)N, &e)) || (st = mesh_scratch_alloc(M, 96 * (size_t)N, &f)))
+        (st = mesh_scratch_alloc(M, 32, &c)) || (st = mesh_scratch_alloc(M, 16 * kExMaxGrid, &d)) ||
+        (st = mesh_scratch_alloc(M, 24 * (size_t)N, &e)) || (st = mesh_scratch_alloc(M, 96 * (size_t)N, &f)) ||
+        (st = mesh_scratch_alloc(M, 8 * (size_t)M->ncf, &g)) || (st = mesh_scratch_alloc(M, 8 * (size_t)N, &h)))
       return st;
-    M->ex_mark = (int8_t *)a; M->ex_list = (int32_t *)b; M->ex_info = (int32_t *)c; M->ex_max = (uint64_t *)d;
-    M->ex_nrm = (double *)e; M->ex_buf = (double *)f;
+    M->ex_mark = (int8_t *)a; M->ex_list = (int32_t *)b; M->ex_info = (int32_t *)c; M->ex_part = (double *)d;
+    M->ex_nrm = (double *)e; M->ex_buf = (double *)f; M->ex_wup = (double *)g; M->ex_theta = (double *)h;
   }
   const unsigned gN = (unsigned)((N + kExBlock - 1) / kExBlock), gF = (unsigned)((NF + kExBlock - 1) / kExBlock);
-  ex_init_kernel<<<gN, kExBlock, 0, s>>>(N, alpha, o.eps_mixed, M->ex_mark, M->ex_info, M->ex_max);
+  ex_init_kernel<<<gN, kExBlock, 0, s>>>(N, alpha, o.eps_mixed, M->ex_mark, M->ex_info);
   for (int l = 1; l <= o.layers; ++l) ex_grow_kernel<<<gF, kExBlock, 0, s>>>(M->d, M->ex_mark, l);
   ex_list_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_mark, M->ex_list, M->ex_info);
   VOFPC_HIP(hipGetLastError());
@@ -315,10 +362,12 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   p.alpha = alpha;
   p.list = M->ex_list;
   p.info = M->ex_info;
-  p.mx = M->ex_max;
+  p.part = M->ex_part;
   p.mark = M->ex_mark;
   p.nrm = M->ex_nrm;
   p.buf = M->ex_buf;
+  p.wup = M->ex_wup;
+  p.theta = M->ex_theta;
   p.dtau = M->min_centre_dist;
   p.tol = o.tol;
   p.max_iter = o.max_iter;
@@ -327,9 +376,12 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   // sweeps: 16 domain cells per block; the finish kernel one cell per thread
   const unsigned gS = (unsigned)std::max<int64_t>(1, std::min<int64_t>(gN, (int64_t)ctx->n_cu * 2));
   const unsigned gW = (unsigned)std::max<int64_t>(
-      1, std::min<int64_t>((N + kExBlock / kExLanes - 1) / (kExBlock / kExLanes), (int64_t)ctx->n_cu * 4));
-  // one kernel per sweep: the kernel boundary orders the sweeps; once the
-  // tolerance is met the remaining sweep kernels return at once
+      1, std::min<int64_t>((N + kExBlock / kExLanes - 1) / (kExBlock / kExLanes),
+                           std::min<int64_t>((int64_t)ctx->n_cu * 2, kExMaxGrid)));
+  // the upwind stencil once; then one kernel per sweep: the kernel boundary
+  // orders the sweeps, and once the tolerance is met the remaining sweep
+  // kernels return at once
+  ex_stencil_kernel<<<gW, kExBlock, 0, s>>>(p);
   for (int it = 0; it < o.max_iter; ++it) ex_sweep_kernel<<<gW, kExBlock, 0, s>>>(p, it);
   ex_finish_kernel<<<gS, kExBlock, 0, s>>>(p);
   if (report) ex_report_kernel<<<1, 64, 0, s>>>(M->ex_info, report);

@@ -126,9 +126,11 @@ struct vofpc_mesh_s {
   int8_t *ex_mark = nullptr;       // layer of each cell in the domain (-1 outside)
   int32_t *ex_list = nullptr;      // domain cells (any order)
   int32_t *ex_info = nullptr;      // [1] domain size, [2] sweeps done, [3] unused, [4] converged
-  uint64_t *ex_max = nullptr;      // three rotating slots of the largest change (ordered bits)
+  double *ex_part = nullptr;       // [2][grid] per-block largest change of the last two sweeps
   double *ex_nrm = nullptr;        // [3][n_cells] advection direction
   double *ex_buf = nullptr;        // [2][6][n_cells]: G_l and G_v, two iterates
+  double *ex_wup = nullptr;        // per cell-face slot: normalised upwind weight
+  double *ex_theta = nullptr;      // per domain entry: pseudo-time fraction
   // interface coupling: mixed entry of each cell (-1 between calls)
   int32_t *rb_entry = nullptr;
   // curvature scratch: [3][n_cells] (smoothing ping-pong, raw and step-1 curvature)
