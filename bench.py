@@ -309,23 +309,62 @@ def main() -> int:
         two_sided(120)
         torch.cuda.synchronize()
         dom = int((~torch.isnan(gl[0])).sum().item())
-        two = {"sweeps": int(repd[0].item()), "domain_cells": dom}
+        two = {"two_sided_mdot": {"sweeps": int(repd[0].item()), "domain_cells": dom}}
+        tsm = two["two_sided_mdot"]
         # the paper's cap of 120 sweeps, and a cap of 32 that still covers its
         # typical 10-30 sweeps: every sweep is a kernel, idle once converged
         for cap, name in ((120, "max_sweeps_120"), (32, "max_sweeps_32")):
             two_sided(cap)
             torch.cuda.synchronize()
-            ok = int(repd[1].item()) == 0 and int(repd[0].item()) == two["sweeps"]
+            ok = int(repd[1].item()) == 0 and int(repd[0].item()) == tsm["sweeps"]
             graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(graph, stream=run.ctx.stream):
                 two_sided(cap)
             graph.replay()
             torch.cuda.synchronize()
-            two[name] = {"us_eager": timed(lambda: two_sided(cap)), "us_graph_replay": timed(graph.replay),
+            tsm[name] = {"us_eager": timed(lambda: two_sided(cap)), "us_graph_replay": timed(graph.replay),
                          "report_ok": ok}
-            log(f"two-sided mass transfer, {name}: eager {two[name]['us_eager']:.1f} us, graph replay "
-                f"{two[name]['us_graph_replay']:.1f} us ({two['sweeps']} sweeps over {dom} cells)")
+            log(f"two-sided mass transfer, {name}: eager {tsm[name]['us_eager']:.1f} us, graph replay "
+                f"{tsm[name]['us_graph_replay']:.1f} us ({tsm['sweeps']} sweeps over {dom} cells)")
         del graph
+        # interface coupling coefficients (Eq. interface_htc) on the same
+        # interface, and the surface-tension curvature chain over every cell
+        nf_cap = wl.mesh.n_faces
+        ad = torch.zeros(N, dtype=torch.float64, device=run.dev)
+        fi = torch.zeros(nf_cap, dtype=torch.int32, device=run.dev)
+        fa = torch.zeros(2, nf_cap, dtype=torch.float64, device=run.dev)
+        fd = torch.zeros(2, nf_cap, dtype=torch.float64, device=run.dev)
+        fr = torch.zeros(nf_cap, dtype=torch.float64, device=run.dev)
+        nfo = torch.zeros(1, dtype=torch.int32, device=run.dev)
+
+        def robin():
+            V.robin(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.band_idx, b.counts, b.itf, wl.k_l, wl.k_v,
+                    a_diag=ad, face_idx=fi, face_a=fa, face_d=fd, face_area=fr, n_face=nfo)
+
+        ah = torch.zeros(N, dtype=torch.float64, device=run.dev)
+        cn = torch.zeros(3, N, dtype=torch.float64, device=run.dev)
+        kp = torch.zeros(N, dtype=torch.float64, device=run.dev)
+        fs = torch.zeros(3, N, dtype=torch.float64, device=run.dev)
+
+        def curvature():
+            V.curvature(run.ctx, run.mesh, run.alpha, ah, cn, kp, force=fs,
+                        opts=V.csf_opts(n_smooth=2, sigma=0.0589))
+
+        for name, fn in (("robin", robin), ("curvature", curvature)):
+            fn()
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=run.ctx.stream):
+                fn()
+            graph.replay()
+            torch.cuda.synchronize()
+            two[name] = {"us_graph_replay": timed(graph.replay)}
+            del graph
+        two["robin"]["detached_faces"] = int(nfo.item())
+        two["curvature"]["cells"] = int(N)
+        two["curvature"]["n_smooth"] = 2
+        log(f"interface coupling: {two['robin']['us_graph_replay']:.1f} us ({two['robin']['detached_faces']} "
+            f"detached faces); curvature chain: {two['curvature']['us_graph_replay']:.1f} us over {N} cells")
         run.close()
     if plain is None and learned is None:
         print(json.dumps({"error": "no trained weights for the learned form"}))
@@ -360,7 +399,7 @@ def main() -> int:
         "step_GBps": sb / (ms_per_step * 1e-3) / 1e9,
     }
     if two is not None:
-        cfg["two_sided_mdot"] = two
+        cfg["follow_on"] = two
     if plain is not None:
         cfg["plain"] = {"cells_per_s": M / (ms_p * 1e-3), "ms_per_step": ms_p, "recon_us": rms_p * 1e3,
                         "evals_per_cell_mean": float(plain["iters"].mean()),

@@ -13,12 +13,20 @@
 //              times |n_P . s_Q|^8 (s_Q the unit centre connection);
 //   force      F = sigma kappa grad(alpha), plain least squares of the sharp
 //              alpha.
-// Every stage is one pass over all cells with 16 lanes per cell (one face per
-// lane, DPP row sums), like the band gradient.
+// Every output is exact outside the cells within n_smooth + 3 rings of the
+// seed (cells with alpha other than 0 or 1, or with a face neighbour of another
+// alpha): a pure cell among equal neighbours keeps alpha_hat = alpha exactly
+// (sums of A_f over sums of A_f), so alpha_hat differs from alpha within
+// n_smooth - 1 rings, the normal is nonzero one ring further, the raw
+// curvature one more, and each smoothing step one more.  The chain therefore
+// fills alpha_hat = alpha and zeros everywhere (one streaming pass), lists
+// that domain, and runs every stage on the list only, with 16 lanes per cell
+// (one face per lane, DPP row sums) like the band gradient.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "ring_ops.h"
 #include "vofpc_internal.h"
 #include "wave_ops.h"
 
@@ -44,15 +52,19 @@ __device__ __forceinline__ double colour_weight(double a) {
   return w4 * w4;
 }
 
-#define CSF_CELL_LOOP(N)                                                                                       \
+// rows of 16 lanes over the domain list; every lane of a row sees the same
+// cell, so the row reductions see all its lanes
+#define CSF_CELL_LOOP                                                                                          \
   const int lane = threadIdx.x % kCsfLanes;                                                                    \
-  for (int64_t P_ = blockIdx.x * (int64_t)kCsfCells + threadIdx.x / kCsfLanes; P_ < (N);                       \
-       P_ += (int64_t)gridDim.x * kCsfCells)
+  const int64_t nd_ = *len;                                                                                    \
+  for (int64_t j_ = blockIdx.x * (int64_t)kCsfCells + threadIdx.x / kCsfLanes; j_ < nd_;                       \
+       j_ += (int64_t)gridDim.x * kCsfCells)
 
-__global__ __launch_bounds__(kCsfBlock) void csf_smooth_kernel(DevMesh m, const double *cur, double *nxt) {
-  const int64_t N = m.n_cells, NF = m.n_faces;
-  CSF_CELL_LOOP(N) {
-    const int P = (int)P_;
+__global__ __launch_bounds__(kCsfBlock) void csf_smooth_kernel(DevMesh m, const int32_t *list, const int32_t *len,
+                                                               const double *cur, double *nxt) {
+  const int64_t NF = m.n_faces;
+  CSF_CELL_LOOP {
+    const int P = list[j_];
     const double aP = cur[P];
     double num = 0.0, den = 0.0;
     for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kCsfLanes) {
@@ -70,14 +82,56 @@ __global__ __launch_bounds__(kCsfBlock) void csf_smooth_kernel(DevMesh m, const 
   }
 }
 
-__global__ __launch_bounds__(kCsfBlock) void csf_copy_kernel(int64_t n, const double *a, double *b) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = a[i];
+// seed of the domain: cells with alpha other than 0 or 1 (the face pass adds
+// the cells with a neighbour of another alpha); the list length is reset
+__global__ __launch_bounds__(kCsfBlock) void csf_seed_cells_kernel(int64_t n, const double *alpha, int8_t *mark,
+                                                                   int32_t *len) {
+  const int64_t P = blockIdx.x * (int64_t)kCsfBlock + threadIdx.x;
+  if (P < n) mark[P] = (alpha[P] == 0.0 || alpha[P] == 1.0) ? -1 : 0;
+  if (P == 0) *len = 0;
 }
 
-// n = g / (|g| + eps) in place
-__global__ __launch_bounds__(kCsfBlock) void csf_normalise_kernel(int64_t N, double *n) {
+__global__ __launch_bounds__(kCsfBlock) void csf_seed_faces_kernel(DevMesh m, const double *alpha, int8_t *mark) {
+  const int64_t f = blockIdx.x * (int64_t)kCsfBlock + threadIdx.x;
+  if (f >= m.n_faces) return;
+  const int q = m.face_neigh[f];
+  if (q < 0) return;
+  const int o = m.face_owner[f];
+  if (alpha[o] != alpha[q]) {
+    mark[o] = 0;
+    mark[q] = 0;
+  }
+}
+
+// every cell: alpha_hat = alpha (both smoothing buffers) and every other
+// output 0, their values outside the domain
+__global__ __launch_bounds__(kCsfBlock) void csf_fill_kernel(int64_t N, const double *alpha, double *ah, double *tmp,
+                                                             double *n, double *kr, double *ks, double *kappa,
+                                                             double *F) {
   for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < N; P += (int64_t)gridDim.x * blockDim.x) {
+    const double a = alpha[P];
+    ah[P] = a;
+    tmp[P] = a;
+    n[P] = 0.0;
+    n[N + P] = 0.0;
+    n[2 * N + P] = 0.0;
+    kr[P] = 0.0;
+    ks[P] = 0.0;
+    kappa[P] = 0.0;
+    if (F) {
+      F[P] = 0.0;
+      F[N + P] = 0.0;
+      F[2 * N + P] = 0.0;
+    }
+  }
+}
+
+// n = g / (|g| + eps) in place, on the domain
+__global__ __launch_bounds__(kCsfBlock) void csf_normalise_kernel(int64_t N, const int32_t *list, const int32_t *len,
+                                                                  double *n) {
+  const int64_t nd = *len;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nd; j += (int64_t)gridDim.x * blockDim.x) {
+    const int P = list[j];
     const double g0 = n[P], g1 = n[N + P], g2 = n[2 * N + P];
     const double den = sqrt(g0 * g0 + g1 * g1 + g2 * g2) + kCsfEps;
     n[P] = g0 / den;
@@ -86,10 +140,11 @@ __global__ __launch_bounds__(kCsfBlock) void csf_normalise_kernel(int64_t N, dou
   }
 }
 
-__global__ __launch_bounds__(kCsfBlock) void csf_divergence_kernel(DevMesh m, const double *n, double *kraw) {
+__global__ __launch_bounds__(kCsfBlock) void csf_divergence_kernel(DevMesh m, const int32_t *list,
+                                                                   const int32_t *len, const double *n, double *kraw) {
   const int64_t N = m.n_cells, NF = m.n_faces;
-  CSF_CELL_LOOP(N) {
-    const int P = (int)P_;
+  CSF_CELL_LOOP {
+    const int P = list[j_];
     const double p0 = n[P], p1 = n[N + P], p2 = n[2 * N + P];
     double div = 0.0;
     for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kCsfLanes) {
@@ -110,11 +165,10 @@ __global__ __launch_bounds__(kCsfBlock) void csf_divergence_kernel(DevMesh m, co
   }
 }
 
-__global__ __launch_bounds__(kCsfBlock) void csf_step1_kernel(DevMesh m, const double *ah, const double *kraw,
-                                                              double *kstar) {
-  const int64_t N = m.n_cells;
-  CSF_CELL_LOOP(N) {
-    const int P = (int)P_;
+__global__ __launch_bounds__(kCsfBlock) void csf_step1_kernel(DevMesh m, const int32_t *list, const int32_t *len,
+                                                              const double *ah, const double *kraw, double *kstar) {
+  CSF_CELL_LOOP {
+    const int P = list[j_];
     double num = 0.0, den = 0.0;
     for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kCsfLanes) {
       const int Q = m.cf_nbr[i];
@@ -133,12 +187,12 @@ __global__ __launch_bounds__(kCsfBlock) void csf_step1_kernel(DevMesh m, const d
 }
 
 // step 2, and the force where asked: F holds grad(alpha) on entry
-__global__ __launch_bounds__(kCsfBlock) void csf_step2_kernel(DevMesh m, const double *ah, const double *n,
-                                                              const double *kstar, double *kappa, double sigma,
-                                                              double *F) {
+__global__ __launch_bounds__(kCsfBlock) void csf_step2_kernel(DevMesh m, const int32_t *list, const int32_t *len,
+                                                              const double *ah, const double *n, const double *kstar,
+                                                              double *kappa, double sigma, double *F) {
   const int64_t N = m.n_cells;
-  CSF_CELL_LOOP(N) {
-    const int P = (int)P_;
+  CSF_CELL_LOOP {
+    const int P = list[j_];
     const double n0 = n[P], n1 = n[N + P], n2 = n[2 * N + P];
     const double x0 = m.xc[P], x1 = m.xc[N + P], x2 = m.xc[2 * N + P];
     double num = 0.0, den = 0.0;
@@ -189,53 +243,65 @@ extern "C" vofpc_status vofpc_curvature(vofpc_ctx ctx, vofpc_mesh M, const doubl
   VOFPC_REQUIRE(M->ctx && M->ctx->device == ctx->device, VOFPC_E_STATE, "curvature: mesh on another device");
   vofpc_csf_opts o;
   if (opts) o = *opts; else vofpc_csf_opts_default(&o);
-  VOFPC_REQUIRE(o.n_smooth >= 0 && o.n_smooth <= 1000, VOFPC_E_INVALID_ARG, "curvature: n_smooth out of range");
+  VOFPC_REQUIRE(o.n_smooth >= 0 && o.n_smooth <= 100, VOFPC_E_INVALID_ARG, "curvature: n_smooth out of range");
   VOFPC_HIP(hipSetDevice(ctx->device));
-  const int64_t N = M->d.n_cells;
+  const int64_t N = M->d.n_cells, NF = M->d.n_faces;
   hipStream_t s = ctx->stream;
   if (!M->csf_buf) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     VOFPC_HIP(hipStreamIsCapturing(s, &cs));
     VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
                   "curvature: the first call on a mesh sets up its buffers and must not be captured");
-    void *a = nullptr;
-    vofpc_status st = mesh_scratch_alloc(M, 24 * (size_t)N, &a);
-    if (st) return st;
+    void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
+    vofpc_status st;
+    if ((st = mesh_scratch_alloc(M, 24 * (size_t)N, &a)) || (st = mesh_scratch_alloc(M, (size_t)N, &b)) ||
+        (st = mesh_scratch_alloc(M, 4 * (size_t)N, &c)) || (st = mesh_scratch_alloc(M, 16, &d)))
+      return st;
     M->csf_buf = (double *)a;
+    M->csf_mark = (int8_t *)b;
+    M->csf_list = (int32_t *)c;
+    M->csf_len = (int32_t *)d;
   }
   double *tmp = M->csf_buf;                                  // smoothing ping-pong
   double *kr = kappa_raw ? kappa_raw : M->csf_buf + N;       // raw curvature
   double *ks = M->csf_buf + 2 * N;                           // step-1 curvature
+  int8_t *mark = M->csf_mark;
+  int32_t *list = M->csf_list;
+  int32_t *len = M->csf_len + 1;   // [1]: domain length (the gradient reads a band count there)
+  const unsigned gN = (unsigned)std::max<int64_t>(1, (N + kCsfBlock - 1) / kCsfBlock);
+  const unsigned gF = (unsigned)std::max<int64_t>(1, (NF + kCsfBlock - 1) / kCsfBlock);
   const unsigned gC = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kCsfCells - 1) / kCsfCells,
                                                                          (int64_t)ctx->n_cu * 16));
   const unsigned gE = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kCsfBlock - 1) / kCsfBlock,
                                                                          (int64_t)ctx->n_cu * 8));
+  // the domain: seed, then n_smooth + 3 rings
+  csf_seed_cells_kernel<<<gN, kCsfBlock, 0, s>>>(N, alpha, mark, len);
+  csf_seed_faces_kernel<<<gF, kCsfBlock, 0, s>>>(M->d, alpha, mark);
+  for (int l = 1; l <= o.n_smooth + 3; ++l) ring_grow_kernel<<<gF, kRingBlock, 0, s>>>(M->d, mark, l);
+  ring_list_kernel<<<gN, kRingBlock, 0, s>>>(N, mark, list, len);
+  csf_fill_kernel<<<gE, kCsfBlock, 0, s>>>(N, alpha, alpha_hat, tmp, n, kr, ks, kappa, force);
   // smoothing: sweep k writes alpha_hat when n_smooth - 1 - k is even, so the
   // last sweep lands there
-  if (o.n_smooth == 0) {
-    csf_copy_kernel<<<gE, kCsfBlock, 0, s>>>(N, alpha, alpha_hat);
-  } else {
-    const double *src = alpha;
-    for (int k = 0; k < o.n_smooth; ++k) {
-      double *dst = ((o.n_smooth - 1 - k) % 2 == 0) ? alpha_hat : tmp;
-      csf_smooth_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, src, dst);
-      src = dst;
-    }
+  const double *src = alpha;
+  for (int k = 0; k < o.n_smooth; ++k) {
+    double *dst = ((o.n_smooth - 1 - k) % 2 == 0) ? alpha_hat : tmp;
+    csf_smooth_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, list, len, src, dst);
+    src = dst;
   }
   VOFPC_HIP(hipGetLastError());
   // normal from the plain gradient of alpha_hat (interior neighbours only)
-  vofpc_status st = launch_grad(ctx, M, alpha_hat, nullptr, 0.0, alpha_hat, nullptr, nullptr, VOFPC_SCOPE_ALL,
+  vofpc_status st = launch_grad(ctx, M, alpha_hat, nullptr, 0.0, alpha_hat, list, M->csf_len, VOFPC_SCOPE_BAND,
                                 VOFPC_GRAD_STANDARD, n, nullptr);
   if (st) return st;
-  csf_normalise_kernel<<<gE, kCsfBlock, 0, s>>>(N, n);
-  csf_divergence_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, n, kr);
-  csf_step1_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, alpha_hat, kr, ks);
+  csf_normalise_kernel<<<gE, kCsfBlock, 0, s>>>(N, list, len, n);
+  csf_divergence_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, list, len, n, kr);
+  csf_step1_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, list, len, alpha_hat, kr, ks);
   if (force) {
-    st = launch_grad(ctx, M, alpha, nullptr, 0.0, alpha, nullptr, nullptr, VOFPC_SCOPE_ALL, VOFPC_GRAD_STANDARD,
+    st = launch_grad(ctx, M, alpha, nullptr, 0.0, alpha, list, M->csf_len, VOFPC_SCOPE_BAND, VOFPC_GRAD_STANDARD,
                      force, nullptr);
     if (st) return st;
   }
-  csf_step2_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, alpha_hat, n, ks, kappa, o.sigma, force);
+  csf_step2_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, list, len, alpha_hat, n, ks, kappa, o.sigma, force);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;
 }

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 
+#include "ring_ops.h"
 #include "vofpc_internal.h"
 #include "wave_ops.h"
 
@@ -42,33 +43,6 @@ __global__ __launch_bounds__(kExBlock) void ex_init_kernel(int64_t n, const doub
     info[3] = 0;
     info[4] = 0;
   }
-}
-
-// grow the domain by one ring: neighbours of layer l-1 cells enter at layer l
-__global__ __launch_bounds__(kExBlock) void ex_grow_kernel(DevMesh m, int8_t *mark, int l) {
-  const int64_t f = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
-  if (f >= m.n_faces) return;
-  const int q = m.face_neigh[f];
-  if (q < 0) return;
-  const int o = m.face_owner[f];
-  const int mo = mark[o], mq = mark[q];
-  if (mo == l - 1 && mq < 0) mark[q] = (int8_t)l;
-  if (mq == l - 1 && mo < 0) mark[o] = (int8_t)l;
-}
-
-// domain list (order of the atomic claims; the sweeps do not depend on it)
-__global__ __launch_bounds__(kExBlock) void ex_list_kernel(int64_t n, const int8_t *mark, int32_t *list,
-                                                           int32_t *info) {
-  const int64_t P = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
-  const bool in = P < n && mark[P] >= 0;
-  const uint64_t bm = __ballot(in);
-  if (!bm) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)bm) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(&info[1], __popcll(bm));
-  base = __shfl(base, leader);
-  if (in) list[base + __popcll(bm & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))))] = (int32_t)P;
 }
 
 // advection direction: unit plain gradient of alpha (computed into nrm by
@@ -340,8 +314,8 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   }
   const unsigned gN = (unsigned)((N + kExBlock - 1) / kExBlock), gF = (unsigned)((NF + kExBlock - 1) / kExBlock);
   ex_init_kernel<<<gN, kExBlock, 0, s>>>(N, alpha, o.eps_mixed, M->ex_mark, M->ex_info);
-  for (int l = 1; l <= o.layers; ++l) ex_grow_kernel<<<gF, kExBlock, 0, s>>>(M->d, M->ex_mark, l);
-  ex_list_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_mark, M->ex_list, M->ex_info);
+  for (int l = 1; l <= o.layers; ++l) ring_grow_kernel<<<gF, kRingBlock, 0, s>>>(M->d, M->ex_mark, l);
+  ring_list_kernel<<<gN, kRingBlock, 0, s>>>(N, M->ex_mark, M->ex_list, M->ex_info + 1);
   VOFPC_HIP(hipGetLastError());
   // gradient of T (interface-modified) and of alpha (plain, interior
   // neighbours only) on the domain; the domain length sits in ex_info[1],

@@ -10,18 +10,21 @@
 // face-normal projection of the two cells' interface area vectors A n.
 //
 // Three small kernels: the mixed list is scattered into a per-mesh map
-// cell -> entry (so a face can find both cells' interfaces), one thread per
-// band entry sums its side of every detached face and the owner side appends
-// the face record, and the map is cleared again (it stays -1 between calls).
+// cell -> entry (so a face can find both cells' interfaces), a row of 16
+// lanes per band entry (one face per lane) sums its side of every detached
+// face and the owner side appends the face record, and the map is cleared
+// again (it stays -1 between calls).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 #include "vofpc_internal.h"
+#include "wave_ops.h"
 
 namespace vofpc {
 
-constexpr int kRbBlock = 64;
+constexpr int kRbBlock = 256;
+constexpr int kRbLanes = 16;   // lanes per band cell (one DPP row)
 
 __global__ __launch_bounds__(256) void robin_map_kernel(const int32_t *mixed, const int32_t *counts, int64_t cap,
                                                         int32_t *entry, int32_t value_is_index, int32_t *n_face) {
@@ -65,11 +68,14 @@ __global__ __launch_bounds__(kRbBlock) void robin_kernel(RobinParams p) {
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells, NF = m.n_faces;
   const int64_t nb = p.counts[1];
-  for (int64_t k = blockIdx.x * (int64_t)kRbBlock + threadIdx.x; k < nb; k += (int64_t)gridDim.x * kRbBlock) {
+  constexpr int kCells = kRbBlock / kRbLanes;
+  const int lane = threadIdx.x % kRbLanes;
+  // a row of 16 lanes per band cell, one face per lane
+  for (int64_t k = blockIdx.x * (int64_t)kCells + threadIdx.x / kRbLanes; k < nb; k += (int64_t)gridDim.x * kCells) {
     const int C = p.band[k];
     const double aC = p.alpha[C];
     double sum = 0.0;
-    for (int64_t i = m.cell_face_off[C]; i < m.cell_face_off[C + 1]; ++i) {
+    for (int64_t i = m.cell_face_off[C] + lane; i < m.cell_face_off[C + 1]; i += kRbLanes) {
       const int Qn = m.cf_nbr[i];
       if (Qn < 0) continue;
       if (!((aC - 0.5) * (p.alpha[Qn] - 0.5) < 0.0)) continue;
@@ -93,8 +99,17 @@ __global__ __launch_bounds__(kRbBlock) void robin_kernel(RobinParams p) {
       const double cP = dP > 0.0 ? kP * area / dP : 0.0;
       const double cQ = dQ > 0.0 ? kQ * area / dQ : 0.0;
       sum += (C == P) ? cP : cQ;
-      if (C == P && p.n_face) {
-        const int j = atomicAdd(p.n_face, 1);
+      // the owner side appends the face record: one counter claim per
+      // wave for all its active lanes that append
+      const bool app = C == P && p.n_face;
+      const uint64_t bm = __ballot(app);
+      const int wl = threadIdx.x & 63;
+      const int leader = bm ? __ffsll((long long)bm) - 1 : 0;
+      int base = 0;
+      if (wl == leader && bm) base = atomicAdd(p.n_face, __popcll(bm));
+      base = __shfl(base, leader);
+      if (app) {
+        const int j = base + __popcll(bm & ((wl == 0) ? 0ull : (~0ull >> (64 - wl))));
         if (j < p.face_cap) {
           const int64_t fc = p.face_cap;
           if (p.face_idx) p.face_idx[j] = f;
@@ -104,7 +119,8 @@ __global__ __launch_bounds__(kRbBlock) void robin_kernel(RobinParams p) {
         }
       }
     }
-    if (p.a_diag) p.a_diag[k] = sum;
+    sum = gsum<kRbLanes>(sum);
+    if (lane == 0 && p.a_diag) p.a_diag[k] = sum;
   }
 }
 
@@ -157,8 +173,9 @@ extern "C" vofpc_status vofpc_robin(vofpc_ctx ctx, vofpc_mesh M, const double *a
   p.face_d = face_d;
   p.face_area = face_area;
   p.n_face = n_face;
-  const unsigned gB =
-      (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kRbBlock - 1) / kRbBlock, (int64_t)ctx->n_cu * 8));
+  const int64_t cells_per_block = kRbBlock / kRbLanes;
+  const unsigned gB = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>((N + cells_per_block - 1) / cells_per_block, (int64_t)ctx->n_cu * 4));
   robin_kernel<<<gB, kRbBlock, 0, s>>>(p);
   robin_map_kernel<<<gM, 256, 0, s>>>(mixed_idx, counts, itf->cap, M->rb_entry, 0, nullptr);
   VOFPC_HIP(hipGetLastError());

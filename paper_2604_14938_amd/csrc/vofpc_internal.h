@@ -133,8 +133,12 @@ struct vofpc_mesh_s {
   double *ex_theta = nullptr;      // per domain entry: pseudo-time fraction
   // interface coupling: mixed entry of each cell (-1 between calls)
   int32_t *rb_entry = nullptr;
-  // curvature scratch: [3][n_cells] (smoothing ping-pong, raw and step-1 curvature)
+  // curvature scratch: [3][n_cells] (smoothing ping-pong, raw and step-1
+  // curvature), the domain marks, list and length ([1])
   double *csf_buf = nullptr;
+  int8_t *csf_mark = nullptr;
+  int32_t *csf_list = nullptr;
+  int32_t *csf_len = nullptr;
   // vertex-neighbour gradient stencil (built by its first use): CSR over cells
   int64_t *xn_off = nullptr;
   int32_t *xn_cell = nullptr;
