@@ -130,3 +130,56 @@ def test_buckets_and_autotune(R, tmp_path):
         _say(f"flavour {flavour} ok")
     run.close()
     torch.cuda.synchronize()
+
+
+def test_follow_on_rows_on_a_concatenated_mesh(R):
+    """Extrapolated phase gradients, interface coupling and curvature on a
+    hexahedral and a Voronoi mesh joined on the device, against the oracle on
+    the union."""
+    import torch
+    import oracle
+    from paper_2604_14938_amd import vofpc as V
+    wls = [workloads.random_bubbles(meshes.hex_mesh(14), seed=41, n_max=12, K=12, r_hi_h=3.0),
+           workloads.random_bubbles(meshes.voronoi_box_mesh(9, seed=42), seed=43, n_max=12, K=12, r_hi_h=2.5)]
+    wl = workloads.concat_workloads(wls)
+    _say(f"follow-on rows on a union of {[w.mesh.n_cells for w in wls]} cells, {wl.n_mixed} mixed")
+    run = R.PathRun(wl, parts=[w.mesh for w in wls])
+    run.step()
+    g = run.results()
+    b = run.buf
+    N, NF = wl.mesh.n_cells, wl.mesh.n_faces
+    f64 = dict(dtype=torch.float64, device=run.dev)
+    gl, gv = torch.full((3, N), np.nan, **f64), torch.full((3, N), np.nan, **f64)
+    rep = torch.zeros(2, dtype=torch.int32, device=run.dev)
+    ad = torch.zeros(N, **f64)
+    fi = torch.zeros(NF, dtype=torch.int32, device=run.dev)
+    fa = torch.zeros(2, NF, **f64)
+    nfo = torch.zeros(1, dtype=torch.int32, device=run.dev)
+    ah, k = torch.zeros(N, **f64), torch.zeros(N, **f64)
+    cn, F = torch.zeros(3, N, **f64), torch.zeros(3, N, **f64)
+    torch.cuda.synchronize()
+    V.extrapolate(run.ctx, run.mesh, run.alpha, run.T, run.Tb, wl.T_sat, b.mixed_idx, b.counts, b.itf, gl, gv, rep)
+    V.robin(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.band_idx, b.counts, b.itf, wl.k_l, wl.k_v, a_diag=ad,
+            face_idx=fi, face_a=fa, n_face=nfo)
+    V.curvature(run.ctx, run.mesh, run.alpha, ah, cn, k, force=F)
+    torch.cuda.synchronize()
+    geom = oracle.geometry(wl.mesh)
+    rec = oracle.reconstruct(wl.mesh, wl.alpha, geom)
+    grad, _ = oracle.grad(wl.mesh, geom, wl.T, wl.T_bface, wl.T_sat, wl.alpha)
+    ogl, ogv, sweeps, dom = oracle.extrapolate(wl.mesh, geom, wl.alpha, grad, rec["n"], rec["A"])
+    assert int(rep[0].item()) == sweeps
+    scale = np.abs(grad[:, dom]).max()
+    for a, o in ((gl, ogl), (gv, ogv)):
+        assert np.abs(a.cpu().numpy()[:, dom] - o[:, dom]).max() <= 1e-9 * scale
+    rb = oracle.robin(wl.mesh, geom, wl.alpha, rec["n"], rec["A"], wl.k_l, wl.k_v)
+    nf = int(nfo.item())
+    assert nf == rb["crossing"].sum()
+    order = np.argsort(fi[:nf].cpu().numpy())
+    np.testing.assert_array_equal(fi[:nf].cpu().numpy()[order], np.nonzero(rb["crossing"])[0])
+    am = np.abs(rb["a_face"]).max()
+    np.testing.assert_allclose(fa[:, :nf].cpu().numpy()[:, order], rb["a_face"][:, rb["crossing"]], rtol=0,
+                               atol=1e-8 * am)
+    cs = oracle.csf(wl.mesh, geom, wl.alpha, n_smooth=2)
+    np.testing.assert_allclose(k.cpu().numpy(), cs["kappa"], rtol=0, atol=1e-9 * np.abs(cs["kappa"]).max())
+    np.testing.assert_allclose(F.cpu().numpy(), cs["F"], rtol=0, atol=1e-9 * np.abs(cs["F"]).max())
+    run.close()
