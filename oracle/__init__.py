@@ -65,7 +65,7 @@ def _lib():
     lib.orc_cut_cell.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_double, P]
     lib.orc_grad.argtypes = [P, P, P, P, P, ctypes.c_double, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                              ctypes.c_int, P, P]
-    lib.orc_reconstruct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_reconstruct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_mass_transfer.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, P, P]
     D, I = ctypes.c_double, ctypes.c_int
@@ -161,7 +161,10 @@ def cut_cell(mesh, P: int, xc, phi, s: float) -> dict:
 
 
 def reconstruct(mesh, alpha, geom: Geometry | None = None, *, eps_mixed=1e-8, tol_rel=1e-13, max_iter=100,
-                vertex_mode=0, fixed_iso=False, iso=0.5, phi=None, hint_lo=None, hint_hi=None) -> dict:
+                vertex_mode=0, fixed_iso=False, iso=0.5, phi=None, hint_lo=None, hint_hi=None, cells=None) -> dict:
+    """Volume-matched (or fixed-isovalue) reconstruction of every mixed cell;
+    `cells` (optional index array) restricts it to those cells, the others
+    getting status -1 (not processed)."""
     om = _om(mesh)
     geom = geom or geometry(om)
     N = om.n_cells
@@ -172,9 +175,13 @@ def reconstruct(mesh, alpha, geom: Geometry | None = None, *, eps_mixed=1e-8, to
     hl = None if hint_lo is None else np.ascontiguousarray(hint_lo, float)
     hh = None if hint_hi is None else np.ascontiguousarray(hint_hi, float)
     ph = None if phi is None else np.ascontiguousarray(phi, float)
+    only = None
+    if cells is not None:
+        only = np.zeros(N, np.int8)
+        only[np.asarray(cells)] = 1
     e = _lib().orc_reconstruct(om.ref, _p(geom.V), _p(geom.xc), _p(alpha), ctypes.byref(op), _p(ph), _p(hl),
                                _p(hh), _p(out["s"]), _p(out["n"]), _p(out["A"]), _p(out["d"]),
-                               _p(out["alpha_got"]), _p(out["status"]), _p(out["iters"]))
+                               _p(out["alpha_got"]), _p(out["status"]), _p(out["iters"]), _p(only))
     if e:
         raise RuntimeError(f"orc_reconstruct failed ({e})")
     return out

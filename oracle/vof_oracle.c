@@ -638,10 +638,12 @@ static double ulp_of(double x) {
  * alpha.  phi_in may supply the vertex field (else it is built from alpha);
  * hint_lo/hint_hi may supply a narrowed initial bracket per cell (NaN = none).
  */
+/* only (optional, int8 [N]): reconstruct the cells with only[P] != 0 and
+ * mark every other cell with status -1 (not processed); NULL: every cell. */
 int orc_reconstruct(const orc_mesh *m, const double *V, const double *xc, const double *alpha,
                     const orc_opts *op, const double *phi_in, const double *hint_lo, const double *hint_hi,
                     double *s_out, double *n_out, double *A_out, double *d_out, double *agot,
-                    int32_t *status, int32_t *iters) {
+                    int32_t *status, int32_t *iters, const int8_t *only) {
   int64_t N = m->n_cells;
   double *phi = NULL;
   if (phi_in) {
@@ -658,6 +660,7 @@ int orc_reconstruct(const orc_mesh *m, const double *V, const double *xc, const 
     s_out[P] = NAN;
     A_out[P] = 0; d_out[P] = 0; agot[P] = a; iters[P] = 0;
     for (int d = 0; d < 3; ++d) n_out[d * N + P] = 0;
+    if (only && !only[P]) { status[P] = -1; continue; }
     if (!(a >= 0.0 && a <= 1.0)) { status[P] = ORC_BAD_INPUT; continue; }
     if (!(a > op->eps_mixed && a < 1.0 - op->eps_mixed)) { status[P] = ORC_NOT_MIXED; continue; }
     double xP[3] = {xc[P], xc[N + P], xc[2 * N + P]};

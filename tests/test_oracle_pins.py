@@ -666,3 +666,19 @@ def test_robin_coefficients_phase_swap_and_rigid_motion():
     scale = {k: np.abs(r0[k]).max() for k in ("a_cell", "a_face", "d_face", "area_face")}
     for k in scale:
         np.testing.assert_allclose(r2[k], r0[k], atol=1e-9 * scale[k])
+
+
+def test_reconstruction_of_a_cell_subset_equals_the_full_run(small_voronoi_wl):
+    """Restricting the oracle to a list of cells (used for sampled checks on
+    meshes too large to reconstruct whole) changes nothing on those cells."""
+    wl = small_voronoi_wl
+    geom = oracle.geometry(wl.mesh)
+    full = oracle.reconstruct(wl.mesh, wl.alpha, geom)
+    mixed = np.nonzero(full["status"] != oracle.NOT_MIXED)[0]
+    pick = mixed[::7]
+    part = oracle.reconstruct(wl.mesh, wl.alpha, geom, cells=pick)
+    for k in ("s", "A", "d", "alpha_got", "status", "iters"):
+        np.testing.assert_array_equal(part[k][pick], full[k][pick])
+    np.testing.assert_array_equal(part["n"][:, pick], full["n"][:, pick])
+    rest = np.setdiff1d(np.arange(wl.mesh.n_cells), pick)
+    assert np.all(part["status"][rest] == -1)
