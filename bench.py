@@ -165,9 +165,11 @@ def main() -> int:
                     help="which forms to time (profiling runs time one)")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the reconstruction kernel flavours on the workload before timing")
-    ap.add_argument("--workload", choices=("voronoi_bubble", "batched"), default="voronoi_bubble",
+    ap.add_argument("--workload", choices=("voronoi_bubble", "batched", "pipe"), default="voronoi_bubble",
                     help="batched: a 128^3 hexahedral and a 986,078-cell Voronoi mesh with random bubbles, "
-                         "stepped as one (a throughput-regime check; the default is the metric's workload)")
+                         "stepped as one (a throughput-regime check); pipe: a Voronoi pipe with a wavy liquid "
+                         "film on its wall; the default is the metric's workload")
+    ap.add_argument("--pipe-radial", type=int, default=40, help="Voronoi seeds across the pipe diameter")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -205,6 +207,12 @@ def main() -> int:
         wl_desc = (f"batched: 128^3 hexahedra ({wls[0].meta['n_bubbles']} bubbles) + jittered-BCC Voronoi mesh "
                    f"of {wls[1].mesh.n_cells:,} cells ({wls[1].meta['n_bubbles']} bubbles), r ~ U[2h, 12h], "
                    f"per-bubble linear T, one disjoint union")
+    elif args.workload == "pipe":
+        wl = workloads.pipe_film(n_radial=args.pipe_radial, seed=4)
+        wl_desc = (f"pipe: Voronoi pipe of {wl.mesh.n_cells:,} cells (jittered BCC, {args.pipe_radial} seeds across "
+                   f"the diameter, length 52/9.5 R), liquid film on the wall of mean thickness 0.1 R with 5 axial "
+                   f"waves of amplitude 0.3 of the thickness, T rising linearly across the film from T_sat at its "
+                   f"surface to T_sat + 1 K at the wall")
     else:
         wl = workloads.voronoi_bubble()
         wl_desc = ("voronoi_bubble: 194,672-cell box-clipped jittered-BCC Voronoi mesh of the unit cube "
