@@ -165,11 +165,14 @@ def main() -> int:
                     help="which forms to time (profiling runs time one)")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the reconstruction kernel flavours on the workload before timing")
-    ap.add_argument("--workload", choices=("voronoi_bubble", "batched", "pipe"), default="voronoi_bubble",
+    ap.add_argument("--workload", choices=("voronoi_bubble", "batched", "pipe", "multi"), default="voronoi_bubble",
                     help="batched: a 128^3 hexahedral and a 986,078-cell Voronoi mesh with random bubbles, "
                          "stepped as one (a throughput-regime check); pipe: a Voronoi pipe with a wavy liquid "
-                         "film on its wall; the default is the metric's workload")
+                         "film on its wall; multi: 64 independent Voronoi meshes with a bubble each, stepped through "
+                         "time steps in one captured launch; the default is the metric's workload")
     ap.add_argument("--pipe-radial", type=int, default=40, help="Voronoi seeds across the pipe diameter")
+    ap.add_argument("--multi-sizes", type=float, nargs=2, default=[1e4, 5e5],
+                    help="range of the multi-instance mesh sizes (cells, log-uniform)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -194,7 +197,25 @@ def main() -> int:
     log("generating workload")
     t0 = time.time()
     parts = None
-    if args.workload == "batched":
+    step_fields = None   # multi-instance: host (alpha, T, T_bface) of each timed time step
+    if args.workload == "multi":
+        n_inst, n_steps, t_list = 64, 100, (0, 25, 50, 75)
+        n_lo, n_hi = args.multi_sizes
+        meshes_, _, _, field = workloads.multi_instance(n_inst=n_inst, n_lo=n_lo, n_hi=n_hi, seed=5, steps=n_steps,
+                                                        K=12, log=log)
+        step_fields = []
+        for t in t_list:
+            w = workloads.concat_workloads([field(i, t) for i in range(n_inst)])
+            step_fields.append((w.alpha, w.T, w.T_bface))
+            log(f"fields of time step {t}: {w.n_mixed} mixed")
+            if t == t_list[0]:
+                wl = w
+        parts = meshes_
+        wl_desc = (f"multi: {n_inst} independent jittered-BCC Voronoi meshes of log-uniform sizes in "
+                   f"[{n_lo:.0f}, {n_hi:.0f}] cells ({wl.mesh.n_cells:,} in all), one bubble r ~ U[0.10, 0.20] each "
+                   f"turning around the box axis (one revolution in {n_steps} steps), erf T profile; time steps "
+                   f"{list(t_list)} cycled through one captured step over the union")
+    elif args.workload == "batched":
         from synth import meshes as synth_meshes
         wls = []
         for i, build in enumerate((lambda: synth_meshes.hex_mesh(128), lambda: synth_meshes.voronoi_box_mesh(79, 3))):
@@ -234,20 +255,65 @@ def main() -> int:
         run.step()
         res = run.results()
         g = run.capture()
-        for _ in range(args.warmup):
+        if step_fields is not None:
+            # time steps resident on the device; before each timed replay the
+            # step's fields are copied into the captured inputs (not timed)
+            dev_fields = [tuple(torch.as_tensor(x, dtype=torch.float64, device=run.dev) for x in f)
+                          for f in step_fields]
+            torch.cuda.synchronize()
+
+            def load(t):
+                with torch.cuda.stream(stream):
+                    run.alpha.copy_(dev_fields[t][0])
+                    run.T.copy_(dev_fields[t][1])
+                    run.Tb.copy_(dev_fields[t][2])
+
+            mixed_t = []
+            for t in range(len(dev_fields)):
+                load(t)
+                g.launch()
+                torch.cuda.synchronize()
+                mixed_t.append(int(run.buf.counts[0].item()))
+            for i in range(args.warmup):
+                load(i % len(dev_fields))
+                g.launch()
+            torch.cuda.synchronize()
+            pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                     for _ in range(args.steps)]
+            cells = 0
+            t_start = time.perf_counter()
+            for i, (a, b_) in enumerate(pairs):
+                t = i % len(dev_fields)
+                load(t)
+                a.record(stream)
+                g.launch()
+                b_.record(stream)
+                cells += mixed_t[t]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t_start
+            per = [a.elapsed_time(b_) for a, b_ in pairs]
+            ms = sum(per) / args.steps
+            res["mixed_per_step"] = cells / args.steps
+            res["mixed_by_time_step"] = mixed_t
+            load(0)          # step 0 again, lists refreshed, for the kernel timing below
             g.launch()
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        ev[0].record(stream)
-        for i in range(args.steps):
-            g.launch()
-            ev[i + 1].record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t_start
-        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
-        ms = ev[0].elapsed_time(ev[-1]) / args.steps
+            torch.cuda.synchronize()
+        else:
+            for _ in range(args.warmup):
+                g.launch()
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            ev[0].record(stream)
+            for i in range(args.steps):
+                g.launch()
+                ev[i + 1].record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t_start
+            per = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+            ms = ev[0].elapsed_time(ev[-1]) / args.steps
+            res["mixed_per_step"] = res["n_mixed"]
         b = run.buf
         if mlp is None:
             rec = lambda: V.reconstruct(run.ctx, run.mesh, run.alpha, b.mixed_idx, b.counts, b.itf, b.opts)
@@ -406,15 +472,18 @@ def main() -> int:
         "step_algorithmic_bytes": sb,
         "step_GBps": sb / (ms_per_step * 1e-3) / 1e9,
     }
+    if step_fields is not None:
+        cfg["mixed_per_timed_step"] = head["mixed_per_step"]
+        cfg["mixed_by_time_step"] = head["mixed_by_time_step"]
     if two is not None:
         cfg["follow_on"] = two
     if plain is not None:
-        cfg["plain"] = {"cells_per_s": M / (ms_p * 1e-3), "ms_per_step": ms_p, "recon_us": rms_p * 1e3,
+        cfg["plain"] = {"cells_per_s": plain["mixed_per_step"] / (ms_p * 1e-3), "ms_per_step": ms_p, "recon_us": rms_p * 1e3,
                         "evals_per_cell_mean": float(plain["iters"].mean()),
                         "evals_per_cell_p99": float(np.percentile(plain["iters"], 99))}
     if learned is not None:
         cfg["learned"] = {
-            "cells_per_s": M / (ms_l * 1e-3), "ms_per_step": ms_l, "recon_us": rms_l * 1e3,
+            "cells_per_s": learned["mixed_per_step"] / (ms_l * 1e-3), "ms_per_step": ms_l, "recon_us": rms_l * 1e3,
             "evals_per_cell_mean": float(learned["iters"].mean()),
             "evals_per_cell_p99": float(np.percentile(learned["iters"], 99)),
             "fallback_rate": float(np.mean(learned["status"] == 2)),
@@ -432,7 +501,7 @@ def main() -> int:
         })
     out = {
         "metric": METRIC,
-        "value": M / (ms_per_step * 1e-3),
+        "value": head["mixed_per_step"] / (ms_per_step * 1e-3),
         "unit": "mixed cells/s",
         "n_gpus": 1,
         "steps": args.steps,

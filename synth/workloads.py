@@ -151,7 +151,7 @@ def _log_uniform_sizes(rng, n_inst: int, n_lo: float, n_hi: float) -> list:
 
 
 def multi_instance(n_inst: int = 64, n_lo: float = 1e4, n_hi: float = 5e5, seed: int = 5,
-                   steps: int = 100, K: int = 16, width: float = 0.05, dT: float = 1.25):
+                   steps: int = 100, K: int = 16, width: float = 0.05, dT: float = 1.25, log=None):
     """Meshes and per-step fields of the multi-instance batch: instance i is a
     box-clipped Voronoi mesh of about N_i = exp(U[ln n_lo, ln n_hi]) cells with
     one bubble r ~ U[0.10, 0.20] whose centre sits 0.15 from the vertical axis
@@ -159,13 +159,18 @@ def multi_instance(n_inst: int = 64, n_lo: float = 1e4, n_hi: float = 5e5, seed:
     erf profile of ``voronoi_bubble`` around the moving centre.
 
     Returns (meshes, radii, phases, field) where field(i, t) gives the
-    Workload of instance i at step t."""
+    Workload of instance i at step t.  `log` (optional) is called with a line
+    of progress after each mesh."""
     rng = np.random.default_rng(seed)
     ns = _log_uniform_sizes(rng, n_inst, n_lo, n_hi)
     radii = rng.uniform(0.10, 0.20, n_inst)
     phases = rng.uniform(0.0, 2.0 * np.pi, n_inst)
     seeds = rng.integers(1 << 30, size=n_inst)
-    meshes = [voronoi_box_mesh(n, int(s)) for n, s in zip(ns, seeds)]
+    meshes = []
+    for i, (n, sd) in enumerate(zip(ns, seeds)):
+        meshes.append(voronoi_box_mesh(n, int(sd)))
+        if log is not None:
+            log(f"instance mesh {i + 1}/{n_inst}: {meshes[-1].n_cells} cells")
 
     def field(i: int, t: int) -> Workload:
         m = meshes[i]
