@@ -107,7 +107,7 @@ def step_bytes(mesh, mixed, band, recon_b) -> int:
     return int(b)
 
 
-RECON_SOURCES = ("recon.hip", "mlp_core.h", "vofpc_internal.h")
+RECON_SOURCES = ("recon.hip", "mlp_core.h", "vofpc_internal.h", "wave_ops.h")
 
 
 def recon_source_hash() -> str:

@@ -54,15 +54,33 @@ __device__ __forceinline__ bf16x4 a_row0(const uint16_t *x, int lane, int k0) {
   return v;
 }
 
+// v[l & ~Z] + v[l | Z] on every lane l (Z = 16 or 32) by the gfx950 lane
+// swaps: the same two operands, in the same order, on both partners
+template <int Z>
+__device__ __forceinline__ float cross_sum_f(float v) {
+  const int b = __builtin_bit_cast(int, v);
+  int lo, hi;
+  if constexpr (Z == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    lo = r[0];
+    hi = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(b, b, false, false);
+    lo = r[0];
+    hi = r[1];
+  }
+  return __builtin_bit_cast(float, lo) + __builtin_bit_cast(float, hi);
+}
+
 // Sum of a float over the 64 lanes of a wavefront, the same on every lane
-// (DPP inside rows of 16, then cross-row shuffles).
+// (DPP inside rows of 16, then the cross-row lane swaps).
 __device__ __forceinline__ float wave_sum_f(float v) {
   v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
   v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
   v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
   v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
+  v = cross_sum_f<16>(v);
+  v = cross_sum_f<32>(v);
   return v;
 }
 

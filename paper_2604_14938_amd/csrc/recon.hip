@@ -230,15 +230,21 @@ __device__ __forceinline__ void loops_reg(int lane, bool valid, double p0, doubl
   const double len = valid ? sqrt(d0 * d0 + d1 * d1 + d2 * d2) : 0.0;
   double Vi = 0, S0 = 0, S1 = 0, S2 = 0, Asum = 0, cw0 = 0, cw1 = 0, cw2 = 0;
   if (nloops < 0) nloops = gsum_i<W>((valid && lab == lane) ? 1 : 0);
+  // the loop's first point on every lane of the group: a register read of
+  // one lane when the group is the whole wave, a shuffle within a segment
+  auto bcast = [&](double v, int src) {
+    if constexpr (W == 64) return readlane_d(v, __builtin_amdgcn_readfirstlane(src));
+    else return __shfl(v, src, W);
+  };
   if (nloops == 1) {
-    const double f0 = __shfl(p0, 0, W), f1 = __shfl(p1, 0, W), f2 = __shfl(p2, 0, W);
+    const double f0 = bcast(p0, 0), f1 = bcast(p1, 0), f2 = bcast(p2, 0);
     one_loop<W>(valid, len, p0, p1, p2, q0, q1, q2, f0, f1, f2, Vi, S0, S1, S2, Asum, cw0, cw1, cw2);
   } else if (nloops > 1) {
     int prev = -1;
     while (true) {
       const int cand = gmin_i<W>((valid && lab == lane && lane > prev) ? lane : 0x7fffffff);
       if (cand == 0x7fffffff) break;
-      const double f0 = __shfl(p0, cand, W), f1 = __shfl(p1, cand, W), f2 = __shfl(p2, cand, W);
+      const double f0 = bcast(p0, cand), f1 = bcast(p1, cand), f2 = bcast(p2, cand);
       one_loop<W>(valid && lab == cand, len, p0, p1, p2, q0, q1, q2, f0, f1, f2, Vi, S0, S1, S2, Asum, cw0, cw1,
                   cw2);
       prev = cand;

@@ -9,7 +9,7 @@ namespace vofpc {
 // Group reductions.  Within a row of 16 lanes they use DPP butterflies
 // (xor 1 and xor 2 inside quads, then the half-row and row mirrors), which
 // stay inside groups of 8 and 16 lanes and avoid the LDS permute latency;
-// wider groups finish with cross-row shuffles.  Every lane of the group ends
+// wider groups finish with the cross-row lane swaps.  Every lane of the group ends
 // with the same, bitwise identical, result (IEEE addition is commutative).
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
@@ -25,6 +25,32 @@ __device__ __forceinline__ double dpp_d(double v) {
 }
 constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kHalfMirror = 0x141, kRowMirror = 0x140;
 
+// The values of lanes l & ~16 and l | 16 (Z = 16), or l & ~32 and l | 32
+// (Z = 32), on every lane l, by the gfx950 lane swaps (registers only, no
+// LDS permute): the two operands of a cross-row step, in the same order on
+// both partners, so a sum, min or max of them is the same on both.
+template <int Z>
+__device__ __forceinline__ void pair_i(int v, int &lo, int &hi) {
+  static_assert(Z == 16 || Z == 32, "swap distance");
+  if constexpr (Z == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    lo = r[0];
+    hi = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    lo = r[0];
+    hi = r[1];
+  }
+}
+template <int Z>
+__device__ __forceinline__ void pair_d(double v, double &lo, double &hi) {
+  int a0, a1, b0, b1;
+  pair_i<Z>(__builtin_bit_cast(int2, v).x, a0, a1);
+  pair_i<Z>(__builtin_bit_cast(int2, v).y, b0, b1);
+  lo = __builtin_bit_cast(double, make_int2(a0, b0));
+  hi = __builtin_bit_cast(double, make_int2(a1, b1));
+}
+
 template <int W>
 __device__ __forceinline__ double gsum(double v) {
   static_assert(W == 8 || W == 16 || W == 32 || W == 64, "group width");
@@ -32,8 +58,8 @@ __device__ __forceinline__ double gsum(double v) {
   v += dpp_d<kQuadXor2>(v);
   v += dpp_d<kHalfMirror>(v);
   if (W >= 16) v += dpp_d<kRowMirror>(v);
-  if (W >= 32) v += __shfl_xor(v, 16, W);
-  if (W >= 64) v += __shfl_xor(v, 32, W);
+  if constexpr (W >= 32) { double lo, hi; pair_d<16>(v, lo, hi); v = lo + hi; }
+  if constexpr (W >= 64) { double lo, hi; pair_d<32>(v, lo, hi); v = lo + hi; }
   return v;
 }
 template <int W>
@@ -42,8 +68,8 @@ __device__ __forceinline__ int gsum_i(int v) {
   v += dpp_i<kQuadXor2>(v);
   v += dpp_i<kHalfMirror>(v);
   if (W >= 16) v += dpp_i<kRowMirror>(v);
-  if (W >= 32) v += __shfl_xor(v, 16, W);
-  if (W >= 64) v += __shfl_xor(v, 32, W);
+  if constexpr (W >= 32) { int lo, hi; pair_i<16>(v, lo, hi); v = lo + hi; }
+  if constexpr (W >= 64) { int lo, hi; pair_i<32>(v, lo, hi); v = lo + hi; }
   return v;
 }
 template <int W>
@@ -52,8 +78,8 @@ __device__ __forceinline__ int gmin_i(int v) {
   v = min(v, dpp_i<kQuadXor2>(v));
   v = min(v, dpp_i<kHalfMirror>(v));
   if (W >= 16) v = min(v, dpp_i<kRowMirror>(v));
-  if (W >= 32) v = min(v, __shfl_xor(v, 16, W));
-  if (W >= 64) v = min(v, __shfl_xor(v, 32, W));
+  if constexpr (W >= 32) { int lo, hi; pair_i<16>(v, lo, hi); v = min(lo, hi); }
+  if constexpr (W >= 64) { int lo, hi; pair_i<32>(v, lo, hi); v = min(lo, hi); }
   return v;
 }
 template <int W>
@@ -62,8 +88,8 @@ __device__ __forceinline__ double gmin(double v) {
   v = fmin(v, dpp_d<kQuadXor2>(v));
   v = fmin(v, dpp_d<kHalfMirror>(v));
   if (W >= 16) v = fmin(v, dpp_d<kRowMirror>(v));
-  if (W >= 32) v = fmin(v, __shfl_xor(v, 16, W));
-  if (W >= 64) v = fmin(v, __shfl_xor(v, 32, W));
+  if constexpr (W >= 32) { double lo, hi; pair_d<16>(v, lo, hi); v = fmin(lo, hi); }
+  if constexpr (W >= 64) { double lo, hi; pair_d<32>(v, lo, hi); v = fmin(lo, hi); }
   return v;
 }
 template <int W>
@@ -72,8 +98,8 @@ __device__ __forceinline__ double gmax(double v) {
   v = fmax(v, dpp_d<kQuadXor2>(v));
   v = fmax(v, dpp_d<kHalfMirror>(v));
   if (W >= 16) v = fmax(v, dpp_d<kRowMirror>(v));
-  if (W >= 32) v = fmax(v, __shfl_xor(v, 16, W));
-  if (W >= 64) v = fmax(v, __shfl_xor(v, 32, W));
+  if constexpr (W >= 32) { double lo, hi; pair_d<16>(v, lo, hi); v = fmax(lo, hi); }
+  if constexpr (W >= 64) { double lo, hi; pair_d<32>(v, lo, hi); v = fmax(lo, hi); }
   return v;
 }
 // value of lane l (uniform l) on every lane
