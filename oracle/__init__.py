@@ -64,7 +64,7 @@ def _lib():
     lib.orc_vertex_field.argtypes = [P, P, P, ctypes.c_int, P]
     lib.orc_cut_cell.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_double, P]
     lib.orc_grad.argtypes = [P, P, P, P, P, ctypes.c_double, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                             ctypes.c_int, P, P]
+                             ctypes.c_int, P, P, P]
     lib.orc_reconstruct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_mass_transfer.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, P, P]
@@ -187,17 +187,23 @@ def reconstruct(mesh, alpha, geom: Geometry | None = None, *, eps_mixed=1e-8, to
     return out
 
 
-def grad(mesh, geom: Geometry, T, Tb, T_sat, alpha, modified=True, printed=False, weight=0, extended=False):
+def grad(mesh, geom: Geometry, T, Tb, T_sat, alpha, modified=True, printed=False, weight=0, extended=False,
+         cells=None):
     """Least-squares gradient (App. B): weight 0 uniform, 1 inverse distance,
     2 inverse distance squared; extended: vertex neighbours instead of face
-    neighbours."""
+    neighbours.  `cells` (optional index array) restricts it to those cells,
+    the others getting status -1 and a NaN gradient."""
     om = _om(mesh)
     N = om.n_cells
     g = np.empty((3, N))
     st = np.empty(N, np.int32)
+    only = None
+    if cells is not None:
+        only = np.zeros(N, np.int8)
+        only[np.asarray(cells)] = 1
     e = _lib().orc_grad(om.ref, _p(geom.xc), _p(geom.xf), _p(np.ascontiguousarray(T, float)),
                         _p(np.ascontiguousarray(Tb, float)), float(T_sat), _p(np.ascontiguousarray(alpha, float)),
-                        int(modified), int(printed), int(weight), int(extended), _p(g), _p(st))
+                        int(modified), int(printed), int(weight), int(extended), _p(g), _p(st), _p(only))
     if e:
         raise RuntimeError("orc_grad failed")
     return g, st

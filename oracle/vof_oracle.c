@@ -558,7 +558,9 @@ static int vertex_neighbours(const orc_mesh *m, int64_t **off_out, int32_t **nb_
  * cells sharing a vertex with P instead of the face neighbours; the crossing
  * test and shortening apply to each centre connection alike.
  * Boundary faces with bc==1 act as neighbours at the face centroid with the
- * value Tb[f]; bc==2 (symmetry) faces are skipped.  grad is SoA [3][N]. */
+ * value Tb[f]; bc==2 (symmetry) faces are skipped.  grad is SoA [3][N].
+ * only (optional, int8 [N]): compute the cells with only[P] != 0 and give
+ * the others status -1 and a NaN gradient (a band is the usual subset). */
 static void lsq_add(double *G, double *b, const double *r, double dv, int weight) {
   double w = 1.0;
   if (weight == 1) w = 1.0 / sqrt(v_dot(r, r));
@@ -570,12 +572,17 @@ static void lsq_add(double *G, double *b, const double *r, double dv, int weight
 
 int orc_grad(const orc_mesh *m, const double *xc, const double *xf, const double *T, const double *Tb,
              double T_sat, const double *alpha, int modified, int printed, int weight, int extended,
-             double *grad, int32_t *status) {
+             double *grad, int32_t *status, const int8_t *only) {
   int64_t N = m->n_cells;
   int64_t *xoff = NULL;
   int32_t *xnb = NULL;
   if (extended && vertex_neighbours(m, &xoff, &xnb)) return 1;
   for (int64_t P = 0; P < N; ++P) {
+    if (only && !only[P]) {
+      if (status) status[P] = -1;
+      for (int d = 0; d < 3; ++d) grad[d * N + P] = NAN;
+      continue;
+    }
     double G[6] = {0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};
     double xP[3] = {xc[P], xc[N + P], xc[2 * N + P]};
     /* interior neighbours: the face neighbours, or every vertex neighbour */

@@ -682,3 +682,17 @@ def test_reconstruction_of_a_cell_subset_equals_the_full_run(small_voronoi_wl):
     np.testing.assert_array_equal(part["n"][:, pick], full["n"][:, pick])
     rest = np.setdiff1d(np.arange(wl.mesh.n_cells), pick)
     assert np.all(part["status"][rest] == -1)
+
+
+def test_gradient_of_a_cell_subset_equals_the_full_run(small_voronoi_wl):
+    """Restricting the oracle gradient to a list of cells (the band, in the
+    CPU timing) changes nothing on those cells; the others are marked."""
+    wl = small_voronoi_wl
+    geom = oracle.geometry(wl.mesh)
+    full, fst = oracle.grad(wl.mesh, geom, wl.T, wl.T_bface, wl.T_sat, wl.alpha)
+    band = np.nonzero(oracle.band_mask(wl.mesh, wl.alpha))[0]
+    part, pst = oracle.grad(wl.mesh, geom, wl.T, wl.T_bface, wl.T_sat, wl.alpha, cells=band)
+    np.testing.assert_array_equal(part[:, band], full[:, band])
+    np.testing.assert_array_equal(pst[band], fst[band])
+    rest = np.setdiff1d(np.arange(wl.mesh.n_cells), band)
+    assert np.all(pst[rest] == -1) and np.all(np.isnan(part[:, rest]))
