@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "vofpc_internal.h"
+#include "wave_ops.h"
 
 namespace vofpc {
 
@@ -87,7 +88,6 @@ __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t 
   uint8_t f = (P < n_cells) ? flags[P] : 0;
   bool mixed = f & 1, band = f & 2;
   uint64_t bm = __ballot(mixed), bb = __ballot(band);
-  const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
   if (l == 0) {
     wbase[0][w] = __popcll(bm);
     wbase[1][w] = __popcll(bb);
@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t 
     if (b == n_blk - 1) counts[threadIdx.x] = run;
   }
   __syncthreads();
-  if (mixed) mixed_idx[wbase[0][w] + __popcll(bm & below)] = (int32_t)P;
-  if (band) band_idx[wbase[1][w] + __popcll(bb & below)] = (int32_t)P;
+  if (mixed) mixed_idx[wbase[0][w] + lanes_below(bm)] = (int32_t)P;
+  if (band) band_idx[wbase[1][w] + lanes_below(bb)] = (int32_t)P;
 }
 
 vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, double eps, int32_t *mixed,

@@ -21,7 +21,9 @@
 // curvature one more, and each smoothing step one more.  The chain therefore
 // fills alpha_hat = alpha and zeros everywhere (one streaming pass), lists
 // that domain, and runs every stage on the list only, with 16 lanes per cell
-// (one face per lane, DPP row sums) like the band gradient.
+// (one face per lane, DPP row sums) like the band gradient.  The geometric
+// weight and the area of every cell-face slot depend on the mesh only and are
+// built once, by the first call on a mesh.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,19 +62,32 @@ __device__ __forceinline__ double colour_weight(double a) {
   for (int64_t j_ = blockIdx.x * (int64_t)kCsfCells + threadIdx.x / kCsfLanes; j_ < nd_;                       \
        j_ += (int64_t)gridDim.x * kCsfCells)
 
-__global__ __launch_bounds__(kCsfBlock) void csf_smooth_kernel(DevMesh m, const int32_t *list, const int32_t *len,
-                                                               const double *cur, double *nxt) {
-  const int64_t NF = m.n_faces;
+// per cell-face slot, once per mesh: the geometric weight of the neighbour
+// (as seen from the slot's cell) and the face area
+__global__ __launch_bounds__(kCsfBlock) void csf_slot_kernel(DevMesh m, double *slot) {
+  const int64_t NF = m.n_faces, NS = m.cell_face_off[m.n_cells];
+  for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < m.n_cells; P += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = m.cell_face_off[P]; i < m.cell_face_off[P + 1]; ++i) {
+      const int f = m.cell_face[i];
+      const int Q = m.cf_nbr[i];
+      const double S0 = m.Sf[f], S1 = m.Sf[NF + f], S2 = m.Sf[2 * NF + f];
+      slot[i] = Q >= 0 ? csf_face_weight(m, f, (int)P, Q) : 0.0;
+      slot[NS + i] = sqrt(S0 * S0 + S1 * S1 + S2 * S2);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kCsfBlock) void csf_smooth_kernel(DevMesh m, const double *slot, const int32_t *list,
+                                                               const int32_t *len, const double *cur, double *nxt) {
+  const int64_t NS = m.cell_face_off[m.n_cells];
   CSF_CELL_LOOP {
     const int P = list[j_];
     const double aP = cur[P];
     double num = 0.0, den = 0.0;
     for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kCsfLanes) {
-      const int f = m.cell_face[i];
       const int Q = m.cf_nbr[i];
-      const double S0 = m.Sf[f], S1 = m.Sf[NF + f], S2 = m.Sf[2 * NF + f];
-      const double A = sqrt(S0 * S0 + S1 * S1 + S2 * S2);
-      const double af = Q >= 0 ? aP + csf_face_weight(m, f, P, Q) * (cur[Q] - aP) : aP;
+      const double A = slot[NS + i];
+      const double af = Q >= 0 ? aP + slot[i] * (cur[Q] - aP) : aP;
       num += af * A;
       den += A;
     }
@@ -80,15 +95,6 @@ __global__ __launch_bounds__(kCsfBlock) void csf_smooth_kernel(DevMesh m, const 
     den = gsum<kCsfLanes>(den);
     if (lane == 0) nxt[P] = num / den;
   }
-}
-
-// seed of the domain: cells with alpha other than 0 or 1 (the face pass adds
-// the cells with a neighbour of another alpha); the list length is reset
-__global__ __launch_bounds__(kCsfBlock) void csf_seed_cells_kernel(int64_t n, const double *alpha, int8_t *mark,
-                                                                   int32_t *len) {
-  const int64_t P = blockIdx.x * (int64_t)kCsfBlock + threadIdx.x;
-  if (P < n) mark[P] = (alpha[P] == 0.0 || alpha[P] == 1.0) ? -1 : 0;
-  if (P == 0) *len = 0;
 }
 
 __global__ __launch_bounds__(kCsfBlock) void csf_seed_faces_kernel(DevMesh m, const double *alpha, int8_t *mark) {
@@ -104,12 +110,15 @@ __global__ __launch_bounds__(kCsfBlock) void csf_seed_faces_kernel(DevMesh m, co
 }
 
 // every cell: alpha_hat = alpha (both smoothing buffers) and every other
-// output 0, their values outside the domain
+// output 0, their values outside the domain; and the seed of the domain,
+// the cells with alpha other than 0 or 1 (the face pass adds the cells with
+// a neighbour of another alpha); the domain length is reset
 __global__ __launch_bounds__(kCsfBlock) void csf_fill_kernel(int64_t N, const double *alpha, double *ah, double *tmp,
                                                              double *n, double *kr, double *ks, double *kappa,
-                                                             double *F) {
+                                                             double *F, int8_t *mark, int32_t *len) {
   for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < N; P += (int64_t)gridDim.x * blockDim.x) {
     const double a = alpha[P];
+    mark[P] = (a == 0.0 || a == 1.0) ? -1 : 0;
     ah[P] = a;
     tmp[P] = a;
     n[P] = 0.0;
@@ -124,6 +133,7 @@ __global__ __launch_bounds__(kCsfBlock) void csf_fill_kernel(int64_t N, const do
       F[2 * N + P] = 0.0;
     }
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *len = 0;
 }
 
 // n = g / (|g| + eps) in place, on the domain
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(kCsfBlock) void csf_normalise_kernel(int64_t N, con
   }
 }
 
-__global__ __launch_bounds__(kCsfBlock) void csf_divergence_kernel(DevMesh m, const int32_t *list,
+__global__ __launch_bounds__(kCsfBlock) void csf_divergence_kernel(DevMesh m, const double *slot, const int32_t *list,
                                                                    const int32_t *len, const double *n, double *kraw) {
   const int64_t N = m.n_cells, NF = m.n_faces;
   CSF_CELL_LOOP {
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(kCsfBlock) void csf_divergence_kernel(DevMesh m, co
       const int Q = m.cf_nbr[i];
       double f0 = p0, f1 = p1, f2 = p2;
       if (Q >= 0) {
-        const double w = csf_face_weight(m, f, P, Q);
+        const double w = slot[i];
         f0 = p0 + w * (n[Q] - p0);
         f1 = p1 + w * (n[N + Q] - p1);
         f2 = p2 + w * (n[2 * N + Q] - p2);
@@ -262,6 +272,20 @@ extern "C" vofpc_status vofpc_curvature(vofpc_ctx ctx, vofpc_mesh M, const doubl
     M->csf_list = (int32_t *)c;
     M->csf_len = (int32_t *)d;
   }
+  if (!M->csf_slot) {
+    // per-slot weights and areas: fixed by the geometry, built once
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    VOFPC_HIP(hipStreamIsCapturing(s, &cs));
+    VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
+                  "curvature: the first call on a mesh sets up its buffers and must not be captured");
+    void *a = nullptr;
+    vofpc_status st = mesh_scratch_alloc(M, 16 * (size_t)std::max<int64_t>(M->ncf, 1), &a);
+    if (st) return st;
+    M->csf_slot = (double *)a;
+    csf_slot_kernel<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kCsfBlock - 1) / kCsfBlock, 4096)),
+                      kCsfBlock, 0, s>>>(M->d, M->csf_slot);
+    VOFPC_HIP(hipGetLastError());
+  }
   double *tmp = M->csf_buf;                                  // smoothing ping-pong
   double *kr = kappa_raw ? kappa_raw : M->csf_buf + N;       // raw curvature
   double *ks = M->csf_buf + 2 * N;                           // step-1 curvature
@@ -275,17 +299,16 @@ extern "C" vofpc_status vofpc_curvature(vofpc_ctx ctx, vofpc_mesh M, const doubl
   const unsigned gE = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kCsfBlock - 1) / kCsfBlock,
                                                                          (int64_t)ctx->n_cu * 8));
   // the domain: seed, then n_smooth + 3 rings
-  csf_seed_cells_kernel<<<gN, kCsfBlock, 0, s>>>(N, alpha, mark, len);
+  csf_fill_kernel<<<gE, kCsfBlock, 0, s>>>(N, alpha, alpha_hat, tmp, n, kr, ks, kappa, force, mark, len);
   csf_seed_faces_kernel<<<gF, kCsfBlock, 0, s>>>(M->d, alpha, mark);
   for (int l = 1; l <= o.n_smooth + 3; ++l) ring_grow_kernel<<<gF, kRingBlock, 0, s>>>(M->d, mark, l);
   ring_list_kernel<<<gN, kRingBlock, 0, s>>>(N, mark, list, len);
-  csf_fill_kernel<<<gE, kCsfBlock, 0, s>>>(N, alpha, alpha_hat, tmp, n, kr, ks, kappa, force);
   // smoothing: sweep k writes alpha_hat when n_smooth - 1 - k is even, so the
   // last sweep lands there
   const double *src = alpha;
   for (int k = 0; k < o.n_smooth; ++k) {
     double *dst = ((o.n_smooth - 1 - k) % 2 == 0) ? alpha_hat : tmp;
-    csf_smooth_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, list, len, src, dst);
+    csf_smooth_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, M->csf_slot, list, len, src, dst);
     src = dst;
   }
   VOFPC_HIP(hipGetLastError());
@@ -294,7 +317,7 @@ extern "C" vofpc_status vofpc_curvature(vofpc_ctx ctx, vofpc_mesh M, const doubl
                                 VOFPC_GRAD_STANDARD, n, nullptr);
   if (st) return st;
   csf_normalise_kernel<<<gE, kCsfBlock, 0, s>>>(N, list, len, n);
-  csf_divergence_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, list, len, n, kr);
+  csf_divergence_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, M->csf_slot, list, len, n, kr);
   csf_step1_kernel<<<gC, kCsfBlock, 0, s>>>(M->d, list, len, alpha_hat, kr, ks);
   if (force) {
     st = launch_grad(ctx, M, alpha, nullptr, 0.0, alpha, list, M->csf_len, VOFPC_SCOPE_BAND, VOFPC_GRAD_STANDARD,

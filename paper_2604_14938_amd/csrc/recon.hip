@@ -1000,8 +1000,11 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
             double xc;
             bool okc;
             {
-              const double tl = lane == 3 ? -0.0625 : lane == 4 ? 0.0625 : lane == 5 ? -1.0 : lane == 6 ? 1.0 : 0.0;
-              xc = se + tl * d;
+              // ladder offsets: lanes 3, 4 at -d/16, +d/16, lanes 5, 6 at -d, +d
+              // (selected from d itself, so no per-lane constant is held
+              // across the loop; scaling by 1/16 is exact)
+              const double dd = lane < 5 ? 0.0625 * d : d;
+              xc = (lane >= 3 && lane <= 6) ? ((lane & 1) ? se - dd : se + dd) : se;
               if (lane == 1) xc = nextafter(blo, __builtin_inf());
               if (lane == 2) xc = bhi;
               if (lane == 7) xc = lo + w0 / 2.0;
@@ -1174,7 +1177,6 @@ __global__ __launch_bounds__(256) void bucket_kernel(DevMesh m, const int32_t *m
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int c = (k < count) ? cell_class(m, mixed[k]) : -1;
   const int lane = threadIdx.x & 63;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int q = 0; q < kClasses; ++q) {
     const uint64_t bm = __ballot(c == q);
@@ -1183,7 +1185,7 @@ __global__ __launch_bounds__(256) void bucket_kernel(DevMesh m, const int32_t *m
     int base = 0;
     if (lane == leader) base = atomicAdd(&bcount[q], __popcll(bm));
     base = __shfl(base, leader);
-    if (c == q) lists[q * stride + base + __popcll(bm & below)] = (int32_t)k;
+    if (c == q) lists[q * stride + base + lanes_below(bm)] = (int32_t)k;
   }
 }
 

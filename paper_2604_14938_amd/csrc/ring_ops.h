@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "vofpc_internal.h"
+#include "wave_ops.h"
 
 namespace vofpc {
 
@@ -45,7 +46,7 @@ static __global__ __launch_bounds__(kRingBlock) void ring_list_kernel(int64_t n,
   if (!in) return;
   int off = base;
   for (int w = 0; w < wave; ++w) off += wave_cnt[w];
-  list[off + __popcll(bm & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))))] = (int32_t)P;
+  list[off + lanes_below(bm)] = (int32_t)P;
 }
 
 }  // namespace vofpc

@@ -64,63 +64,128 @@ __device__ __forceinline__ void area_vector(const RobinParams &p, int C, double 
   s[2] = A * p.itf.n[2 * cap + e];
 }
 
-__global__ __launch_bounds__(kRbBlock) void robin_kernel(RobinParams p) {
+// One interior slot of band cell C: whether the face is detached (its two
+// cells on opposite sides of alpha = 1/2), whether C owns it, and its record.
+struct FaceRec {
+  int f;
+  double cP, cQ, dP, dQ, area;
+};
+
+__device__ __forceinline__ bool face_coupling(const RobinParams &p, int C, double aC, const double *xC,
+                                              const double *sC, int64_t i, FaceRec &r, bool &cown) {
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells, NF = m.n_faces;
-  const int64_t nb = p.counts[1];
+  const int Qn = m.cf_nbr[i];
+  const int f = m.cell_face[i];
+  if (Qn < 0) return false;
+  // every load of the face is made before the crossing test (they depend
+  // only on the slot and its two cells) and the arithmetic runs on every
+  // face: a detached face waits for three rounds of dependent loads, not six
+  const int own = m.face_owner[f];
+  const double aN = p.alpha[Qn];
+  const double S0 = m.Sf[f], S1 = m.Sf[NF + f], S2 = m.Sf[2 * NF + f];
+  const double xN0 = m.xc[Qn], xN1 = m.xc[N + Qn], xN2 = m.xc[2 * N + Qn];
+  double sN[3];
+  area_vector(p, Qn, sN);
+  const bool cross = (aC - 0.5) * (aN - 0.5) < 0.0;
+  // the face's owner P and neighbour Q
+  cown = own == C;
+  const double aP = cown ? aC : aN, aQ = cown ? aN : aC;
+  const double xP0 = cown ? xC[0] : xN0, xP1 = cown ? xC[1] : xN1, xP2 = cown ? xC[2] : xN2;
+  const double xQ0 = cown ? xN0 : xC[0], xQ1 = cown ? xN1 : xC[1], xQ2 = cown ? xN2 : xC[2];
+  const double mag = sqrt(S0 * S0 + S1 * S1 + S2 * S2);
+  const double n0 = S0 / mag, n1 = S1 / mag, n2 = S2 / mag;
+  const double t = (aP - 0.5) / (aP - aQ);
+  const double xf0 = xP0 + t * (xQ0 - xP0), xf1 = xP1 + t * (xQ1 - xP1), xf2 = xP2 + t * (xQ2 - xP2);
+  const double sp0 = cown ? sC[0] : sN[0], sp1 = cown ? sC[1] : sN[1], sp2 = cown ? sC[2] : sN[2];
+  const double sq0 = cown ? sN[0] : sC[0], sq1 = cown ? sN[1] : sC[1], sq2 = cown ? sN[2] : sC[2];
+  r.f = f;
+  r.area = fabs(n0 * (sp0 + sq0) + n1 * (sp1 + sq1) + n2 * (sp2 + sq2));
+  r.dP = fabs(n0 * (xf0 - xP0) + n1 * (xf1 - xP1) + n2 * (xf2 - xP2));
+  r.dQ = fabs(n0 * (xf0 - xQ0) + n1 * (xf1 - xQ1) + n2 * (xf2 - xQ2));
+  const double kP = aP >= 0.5 ? p.k_l : p.k_v, kQ = aQ >= 0.5 ? p.k_l : p.k_v;
+  r.cP = r.dP > 0.0 ? kP * r.area / r.dP : 0.0;
+  r.cQ = r.dQ > 0.0 ? kQ * r.area / r.dQ : 0.0;
+  return cross;
+}
+
+__device__ __forceinline__ void write_record(const RobinParams &p, int64_t j, const FaceRec &r) {
+  if (j >= p.face_cap) return;
+  const int64_t fc = p.face_cap;
+  if (p.face_idx) p.face_idx[j] = r.f;
+  if (p.face_a) { p.face_a[j] = r.cP; p.face_a[fc + j] = r.cQ; }
+  if (p.face_d) { p.face_d[j] = r.dP; p.face_d[fc + j] = r.dQ; }
+  if (p.face_area) p.face_area[j] = r.area;
+}
+
+__global__ __launch_bounds__(kRbBlock) void robin_kernel(RobinParams p) {
   constexpr int kCells = kRbBlock / kRbLanes;
+  constexpr int kWaves = kRbBlock / 64;
+  __shared__ int wsum[kWaves];
+  __shared__ int bbase;
+  const DevMesh &m = p.m;
+  const int64_t N = m.n_cells;
+  const int64_t nb = p.counts[1];
   const int lane = threadIdx.x % kRbLanes;
-  // a row of 16 lanes per band cell, one face per lane
-  for (int64_t k = blockIdx.x * (int64_t)kCells + threadIdx.x / kRbLanes; k < nb; k += (int64_t)gridDim.x * kCells) {
-    const int C = p.band[k];
-    const double aC = p.alpha[C];
-    double sum = 0.0;
-    for (int64_t i = m.cell_face_off[C] + lane; i < m.cell_face_off[C + 1]; i += kRbLanes) {
-      const int Qn = m.cf_nbr[i];
-      if (Qn < 0) continue;
-      if (!((aC - 0.5) * (p.alpha[Qn] - 0.5) < 0.0)) continue;
-      const int f = m.cell_face[i];
-      const int P = m.face_owner[f], Q = m.face_neigh[f];
-      const double aP = p.alpha[P], aQ = p.alpha[Q];
-      const double S0 = m.Sf[f], S1 = m.Sf[NF + f], S2 = m.Sf[2 * NF + f];
-      const double mag = sqrt(S0 * S0 + S1 * S1 + S2 * S2);
-      const double n0 = S0 / mag, n1 = S1 / mag, n2 = S2 / mag;
-      const double t = (aP - 0.5) / (aP - aQ);
-      const double xP0 = m.xc[P], xP1 = m.xc[N + P], xP2 = m.xc[2 * N + P];
-      const double xQ0 = m.xc[Q], xQ1 = m.xc[N + Q], xQ2 = m.xc[2 * N + Q];
-      const double xf0 = xP0 + t * (xQ0 - xP0), xf1 = xP1 + t * (xQ1 - xP1), xf2 = xP2 + t * (xQ2 - xP2);
-      double sp[3], sq[3];
-      area_vector(p, P, sp);
-      area_vector(p, Q, sq);
-      const double area = fabs(n0 * (sp[0] + sq[0]) + n1 * (sp[1] + sq[1]) + n2 * (sp[2] + sq[2]));
-      const double dP = fabs(n0 * (xf0 - xP0) + n1 * (xf1 - xP1) + n2 * (xf2 - xP2));
-      const double dQ = fabs(n0 * (xf0 - xQ0) + n1 * (xf1 - xQ1) + n2 * (xf2 - xQ2));
-      const double kP = aP >= 0.5 ? p.k_l : p.k_v, kQ = aQ >= 0.5 ? p.k_l : p.k_v;
-      const double cP = dP > 0.0 ? kP * area / dP : 0.0;
-      const double cQ = dQ > 0.0 ? kQ * area / dQ : 0.0;
-      sum += (C == P) ? cP : cQ;
-      // the owner side appends the face record: one counter claim per
-      // wave for all its active lanes that append
-      const bool app = C == P && p.n_face;
-      const uint64_t bm = __ballot(app);
-      const int wl = threadIdx.x & 63;
-      const int leader = bm ? __ffsll((long long)bm) - 1 : 0;
-      int base = 0;
-      if (wl == leader && bm) base = atomicAdd(p.n_face, __popcll(bm));
-      base = __shfl(base, leader);
-      if (app) {
-        const int j = base + __popcll(bm & ((wl == 0) ? 0ull : (~0ull >> (64 - wl))));
-        if (j < p.face_cap) {
-          const int64_t fc = p.face_cap;
-          if (p.face_idx) p.face_idx[j] = f;
-          if (p.face_a) { p.face_a[j] = cP; p.face_a[fc + j] = cQ; }
-          if (p.face_d) { p.face_d[j] = dP; p.face_d[fc + j] = dQ; }
-          if (p.face_area) p.face_area[j] = area;
-        }
+  const int wl = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // a row of 16 lanes per band cell, one face per lane; the block walks the
+  // band in steps of 16 cells together (the face records are claimed once
+  // per block and step)
+  for (int64_t k0 = blockIdx.x * (int64_t)kCells; k0 < nb; k0 += (int64_t)gridDim.x * kCells) {
+    const int64_t k = k0 + threadIdx.x / kRbLanes;
+    int C = -1, cnt = 0;
+    double aC = 0.0, xC[3] = {0.0, 0.0, 0.0}, sC[3] = {0.0, 0.0, 0.0};
+    FaceRec last{0, 0.0, 0.0, 0.0, 0.0, 0.0};   // the lane's last detached face it owns
+    if (k < nb) {
+      C = p.band[k];
+      aC = p.alpha[C];
+      xC[0] = m.xc[C]; xC[1] = m.xc[N + C]; xC[2] = m.xc[2 * N + C];
+      area_vector(p, C, sC);
+      double sum = 0.0;
+      for (int64_t i = m.cell_face_off[C] + lane; i < m.cell_face_off[C + 1]; i += kRbLanes) {
+        FaceRec r;
+        bool cown;
+        if (!face_coupling(p, C, aC, xC, sC, i, r, cown)) continue;
+        sum += cown ? r.cP : r.cQ;
+        if (cown) { last = r; ++cnt; }
+      }
+      sum = gsum<kRbLanes>(sum);
+      if (lane == 0 && p.a_diag) p.a_diag[k] = sum;
+    }
+    if (!p.n_face) continue;
+    // records: the owner side appends each detached face; offsets from a
+    // block-wide prefix of the lanes' counts and one counter claim
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(incl, d);
+      if (wl >= d) incl += t;
+    }
+    if (wl == 63) wsum[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        const int t = wsum[w];
+        wsum[w] = tot;
+        tot += t;
+      }
+      bbase = tot ? atomicAdd(p.n_face, tot) : 0;
+    }
+    __syncthreads();
+    int64_t j = (int64_t)bbase + wsum[wave] + (incl - cnt);
+    if (cnt == 1) {
+      write_record(p, j, last);
+    } else if (cnt > 1) {
+      // more than one owned detached face on this lane (cells with more
+      // than 16 faces): walk the lane's faces again in the same order
+      for (int64_t i = m.cell_face_off[C] + lane; i < m.cell_face_off[C + 1]; i += kRbLanes) {
+        FaceRec r;
+        bool cown;
+        if (face_coupling(p, C, aC, xC, sC, i, r, cown) && cown) write_record(p, j++, r);
       }
     }
-    sum = gsum<kRbLanes>(sum);
-    if (lane == 0 && p.a_diag) p.a_diag[k] = sum;
+    __syncthreads();   // wsum and bbase are rewritten by the next step
   }
 }
 

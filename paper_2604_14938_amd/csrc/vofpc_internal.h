@@ -139,6 +139,7 @@ struct vofpc_mesh_s {
   int8_t *csf_mark = nullptr;
   int32_t *csf_list = nullptr;
   int32_t *csf_len = nullptr;
+  double *csf_slot = nullptr;      // [2][slots]: geometric weight of the neighbour, face area
   // vertex-neighbour gradient stencil (built by its first use): CSR over cells
   int64_t *xn_off = nullptr;
   int32_t *xn_cell = nullptr;

@@ -6,6 +6,12 @@
 
 namespace vofpc {
 
+// Set bits of a wave-wide lane mask below the calling lane (the lane's
+// rank among the set lanes), by the hardware bit counts v_mbcnt_lo/hi.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 // Group reductions.  Within a row of 16 lanes they use DPP butterflies
 // (xor 1 and xor 2 inside quads, then the half-row and row mirrors), which
 // stay inside groups of 8 and 16 lanes and avoid the LDS permute latency;
