@@ -45,7 +45,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAXF 96    /* faces per cell */
+#define ORC_MAXF 256   /* faces per cell */
 #define ORC_MAXV 256   /* vertices per cell */
 #define ORC_MAXFV 64   /* vertices per face */
 #define ORC_MAXX 512   /* crossings per cell */

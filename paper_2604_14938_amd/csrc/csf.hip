@@ -66,8 +66,10 @@ __device__ __forceinline__ double colour_weight(double a) {
 // (as seen from the slot's cell) and the face area
 __global__ __launch_bounds__(kCsfBlock) void csf_slot_kernel(DevMesh m, double *slot) {
   const int64_t NF = m.n_faces, NS = m.cell_face_off[m.n_cells];
-  for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < m.n_cells; P += (int64_t)gridDim.x * blockDim.x) {
-    for (int64_t i = m.cell_face_off[P]; i < m.cell_face_off[P + 1]; ++i) {
+  const int lane = threadIdx.x % kCsfLanes;
+  for (int64_t P = blockIdx.x * (int64_t)kCsfCells + threadIdx.x / kCsfLanes; P < m.n_cells;
+       P += (int64_t)gridDim.x * kCsfCells) {
+    for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kCsfLanes) {
       const int f = m.cell_face[i];
       const int Q = m.cf_nbr[i];
       const double S0 = m.Sf[f], S1 = m.Sf[NF + f], S2 = m.Sf[2 * NF + f];
@@ -282,7 +284,8 @@ extern "C" vofpc_status vofpc_curvature(vofpc_ctx ctx, vofpc_mesh M, const doubl
     vofpc_status st = mesh_scratch_alloc(M, 16 * (size_t)std::max<int64_t>(M->ncf, 1), &a);
     if (st) return st;
     M->csf_slot = (double *)a;
-    csf_slot_kernel<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kCsfBlock - 1) / kCsfBlock, 4096)),
+    csf_slot_kernel<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kCsfCells - 1) / kCsfCells,
+                                                                       (int64_t)ctx->n_cu * 16)),
                       kCsfBlock, 0, s>>>(M->d, M->csf_slot);
     VOFPC_HIP(hipGetLastError());
   }

@@ -418,7 +418,10 @@ __device__ CutRes cut_full(GroupMem<kSlotChords, NV, NF, NL, NCH> &L, int lane, 
       is_exit = false;
     }
     const uint64_t bal = __ballot(is_exit);
-    const int c = nch + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    // rank among the exits (both forms count the same bits; which one the
+    // register allocator handles better differs between the kernel variants,
+    // measured: the hardware count for the hexahedral variant)
+    const int c = nch + (NV <= 16 ? lanes_below(bal) : __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)))));
     if (is_exit) {
       const bool liquid_connected = (__popcll(ex) == 1) || (L.fmean[f] >= s);
       const int r = liquid_connected ? next_bit_after(en, q) : prev_bit_before(en, q);
@@ -1012,7 +1015,7 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
                     (lane != 2 || hi > bhi);
             }
             const uint64_t cm = __ballot(okc);
-            const int cpos = __popcll(cm & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            const int cpos = NV <= 16 ? lanes_below(cm) : __popcll(cm & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
             int np = __popcll(cm);
             np = np < K ? np : K;
             if (okc && cpos < K) L.sp_s[cpos] = xc;

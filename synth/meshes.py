@@ -177,6 +177,69 @@ def hex_mesh(n: int, length: float = 1.0, origin=(0.0, 0.0, 0.0)) -> Mesh:
     )
 
 
+def prism_column(n_sides: int, n_layers: int, radius: float = 0.5, height: float = 1.0, shear: float = 0.3,
+                 taper: float = 0.1, origin=(0.0, 0.0, 0.0), fan_caps: bool = False) -> Mesh:
+    """A column of n_layers cells, each the convex hull of two parallel
+    regular n_sides-gons (ring k at height k h, radius radius (1 + taper
+    sin k), centre shifted in x by shear k h): cells with 2 n_sides vertices,
+    n_sides + 2 faces and n_sides-gon faces, for the large-cell kernel
+    variants.  Side faces are planar trapezoids; all of them and the two end
+    caps are boundary faces.  fan_caps: every cap is split into n_sides
+    triangles around the ring centre (an extra vertex per ring), so a cell
+    has 3 n_sides faces of at most four vertices and a cut across the column
+    crosses every side face."""
+    n, L = n_sides, n_layers
+    h = height / L
+    ang = 2.0 * np.pi * np.arange(n) / n
+    nr = n + 1 if fan_caps else n            # vertices per ring (centre last)
+    xyz = np.empty((3, (L + 1) * nr))
+    for k in range(L + 1):
+        r = radius * (1.0 + taper * np.sin(k))
+        cx = origin[0] + shear * k * h
+        xyz[0, k * nr:k * nr + n] = cx + r * np.cos(ang)
+        xyz[1, k * nr:k * nr + n] = origin[1] + r * np.sin(ang)
+        xyz[2, k * nr:(k + 1) * nr] = origin[2] + k * h
+        if fan_caps:
+            xyz[0, k * nr + n] = cx
+            xyz[1, k * nr + n] = origin[1]
+    ring = lambda k: k * nr + np.arange(n)  # noqa: E731
+    loops, owners, neighs = [], [], []
+
+    def cap(k, own, nb, up):
+        # ring k, normal +z when up (counter-clockwise seen from +z)
+        if fan_caps:
+            c = k * nr + n
+            for j in range(n):
+                tri = np.array([c, k * nr + j, k * nr + (j + 1) % n])
+                loops.append(tri if up else tri[::-1]); owners.append(own); neighs.append(nb)
+        else:
+            loops.append(ring(k) if up else ring(k)[::-1]); owners.append(own); neighs.append(nb)
+
+    # caps: ring k between cell k-1 (owner, below) and cell k
+    cap(0, 0, -1, False)
+    for k in range(1, L):
+        cap(k, k - 1, k, True)
+    cap(L, L - 1, -1, True)
+    # side trapezoids, outward: (k, j) -> (k, j+1) -> (k+1, j+1) -> (k+1, j)
+    for k in range(L):
+        for j in range(n):
+            j1 = (j + 1) % n
+            loops.append(np.array([k * nr + j, k * nr + j1, (k + 1) * nr + j1, (k + 1) * nr + j]))
+            owners.append(k); neighs.append(-1)
+    fvo = np.zeros(len(loops) + 1, np.int64)
+    np.cumsum([len(lp) for lp in loops], out=fvo[1:])
+    owner = np.array(owners, np.int32)
+    neigh = np.array(neighs, np.int32)
+    cfo, cf = _cell_face_csr(L, owner, neigh)
+    return Mesh(
+        n_cells=L, n_faces=len(loops), n_verts=(L + 1) * nr,
+        cell_face_off=cfo, cell_face=cf,
+        face_vert_off=fvo, face_vert=np.concatenate(loops).astype(np.int32),
+        face_owner=owner, face_neigh=neigh, face_bc=(neigh < 0).astype(np.int8),
+        vert_xyz=xyz, kind="prism", h=h,
+    )
+
+
 def bcc_seeds(n, rng: np.random.Generator, jitter: float = 0.3,
               lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> np.ndarray:
     """Two interleaved lattices (BCC) of n[0]*n[1]*n[2] points each in [lo, hi],

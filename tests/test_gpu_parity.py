@@ -325,3 +325,54 @@ def test_repeated_launches_share_the_cell_queue(V, runner):
         assert np.all(st[m:] == -1)
         np.testing.assert_array_equal(b.itf.alpha_got[:m].cpu().numpy(), full["alpha_got"][:m])
     run.close()
+
+
+def _prism_workload(sides, layers=12, fan=False, tilt=0.3):
+    """Columns of n-gon prismatoids side by side (one column per entry of
+    `sides`), a tilted plane through each: cells of every kernel class, up
+    to 128 vertices, 66 faces and 64-vertex faces (with fan caps, 240 faces
+    and cuts of 80 chords)."""
+    parts = [meshes.prism_column(n, layers, origin=(2.0 * i, 0.0, 0.0), fan_caps=fan) for i, n in enumerate(sides)]
+    mesh = meshes.concat(parts)
+    c = mesh.cell_vertex_mean()
+    x0 = 2.0 * np.floor((c[:, 0] + 1.0) / 2.0)
+    d = (c[:, 2] - 0.5) - tilt * (c[:, 0] - x0 - 0.3 * c[:, 2])
+    h = 1.0 / layers
+    alpha = np.clip(0.5 - d / (6.0 * h), 0.0, 1.0)
+    fc = mesh.face_vertex_mean()
+    T = 373.15 + 2.0 * c[:, 2] + 0.5 * (c[:, 0] - x0)
+    Tb = 373.15 + 2.0 * fc[:, 2] + 0.5 * (fc[:, 0] - 2.0 * np.floor((fc[:, 0] + 1.0) / 2.0))
+    wl = workloads.Workload(f"prisms{sides}", mesh, alpha, T, Tb)
+    return wl, parts
+
+
+@pytest.mark.parametrize("sides,fan", [((4, 8, 24, 40, 64), False), ((64,), False), ((80,), True)])
+def test_large_cells_use_the_wide_kernel_variants(V, runner, sides, fan):
+    """Cells beyond the Voronoi sizes (n-gon faces up to 64 vertices, up to
+    162 vertices and 240 faces per cell) run in the wide kernel variants,
+    bucketed by class with the small ones or alone, and give the oracle's
+    results; their cuts have more chords than a cached topology holds, so the
+    search runs on full evaluations, and the nearly flat cuts of the fan-capped
+    column (80 chords, more than the lanes of a wave) label their loop
+    through LDS."""
+    wl, parts = _prism_workload(sides, fan=fan, tilt=0.02 if fan else 0.3)
+    _say(f"large cells {sides}: {wl.mesh.n_cells} cells, {wl.n_mixed} mixed")
+    run = runner.PathRun(wl, parts=parts if len(parts) > 1 else None)
+    cls = run.mesh.classes()
+    if len(sides) > 1:
+        assert cls["bucketed"] and all(k > 0 for k in cls["cells"]), cls
+    else:
+        assert not cls["bucketed"] and cls["cells"][3] == wl.mesh.n_cells, cls
+    run.step()
+    g = run.results()
+    ref = parity.oracle_path(wl)
+    parity.check_lists(wl, g)
+    rep = {}
+    parity.check_interface(wl, g, ref["rec"], report=rep)
+    assert np.all(g["status"] == V.CELL_OK) and np.all(g["A"] > 0)
+    band = g["band_idx"]
+    parity.check_grad(wl, g["gradT"], ref["grad"], band)
+    np.testing.assert_array_equal(g["grad_status"][band], ref["grad_status"][band])
+    parity.check_mdot(g["mdot"], ref["mdot"][g["mixed_idx"]])
+    _say(f"large cells ok: {rep}; {g['n_mixed']} mixed, mean iters {g['iters'].mean():.1f}")
+    run.close()

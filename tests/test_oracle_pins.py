@@ -696,3 +696,37 @@ def test_gradient_of_a_cell_subset_equals_the_full_run(small_voronoi_wl):
     np.testing.assert_array_equal(pst[band], fst[band])
     rest = np.setdiff1d(np.arange(wl.mesh.n_cells), band)
     assert np.all(pst[rest] == -1) and np.all(np.isnan(part[:, rest]))
+
+
+@pytest.mark.parametrize("n_sides,fan", [(5, False), (24, False), (64, False), (80, True)])
+def test_prismatoid_horizontal_cut_matches_the_cross_section_integral(n_sides, fan):
+    """Cells bounded by two parallel regular n-gons (faces with up to 64
+    vertices, the large-cell sizes) cut by the field phi = z: the liquid part
+    (phi >= s) is the part above the plane z = s, whose volume is the
+    integral of the cross-section area, a regular n-gon of radius varying
+    linearly in z (the sideways shift of the rings does not change it); the
+    interface is that cross-section, with the normal +z (with fan caps the
+    cut crosses all 80 side faces: one iso-loop of 80 chords)."""
+    mesh = meshes.prism_column(n_sides, 3, radius=0.4, height=0.9, shear=0.25, taper=0.2, fan_caps=fan)
+    om = oracle.OMesh(mesh)
+    geom = oracle.geometry(om)
+    phi = mesh.vert_xyz[2].copy()
+    an = 0.5 * n_sides * np.sin(2 * np.pi / n_sides)    # area of the unit-radius n-gon
+    h = 0.9 / 3
+    for P in range(3):
+        z0, z1 = P * h, (P + 1) * h
+        r0 = 0.4 * (1 + 0.2 * np.sin(P))
+        r1 = 0.4 * (1 + 0.2 * np.sin(P + 1))
+        rad = lambda z: r0 + (r1 - r0) * (z - z0) / h  # noqa: E731
+        # integral of an * r(z)^2 from s to z1, r linear: (r(s)^3 - r1^3) / (3 dr/dz) form
+        def above(s):
+            k = (r1 - r0) / h
+            return an * (r1 ** 3 - rad(s) ** 3) / (3 * k) if abs(k) > 0 else an * r0 ** 2 * (z1 - s)
+        assert geom.V[P] == pytest.approx(above(z0), rel=1e-13)
+        for t in (0.1, 0.37, 0.5, 0.81):
+            s = z0 + t * h
+            res = oracle.cut_cell(om, P, geom.xc, phi, s)
+            assert res["V"] == pytest.approx(above(s), rel=1e-12, abs=1e-15)
+            assert res["A"] == pytest.approx(an * rad(s) ** 2, rel=1e-12)
+            np.testing.assert_allclose(res["S"] / np.linalg.norm(res["S"]), [0, 0, 1], atol=1e-12)
+            assert res["nloops"] == 1
