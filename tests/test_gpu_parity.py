@@ -376,3 +376,42 @@ def test_large_cells_use_the_wide_kernel_variants(V, runner, sides, fan):
     parity.check_mdot(g["mdot"], ref["mdot"][g["mixed_idx"]])
     _say(f"large cells ok: {rep}; {g['n_mixed']} mixed, mean iters {g['iters'].mean():.1f}")
     run.close()
+
+
+def test_out_of_range_and_nan_fractions(V, runner):
+    """Volume fractions outside [0, 1] or NaN are never mixed (the lists
+    skip them, the crossing test sees them as they are), and a mixed list
+    that names them explicitly gets the BAD_INPUT status for them with the
+    empty interface, while the other entries are reconstructed as usual."""
+    import torch
+    base = workloads.hex_sphere()
+    N = base.mesh.n_cells
+    alpha = base.alpha.copy()
+    bad = [0, 15, N - 1]
+    alpha[bad] = [np.nan, -0.1, 1.2]
+    wl = workloads.Workload("bad_fractions", base.mesh, alpha, base.T, base.T_bface)
+    _say(f"bad fractions at {bad}")
+    run = runner.PathRun(wl)
+    run.step()
+    g = run.results()
+    parity.check_lists(wl, g)
+    assert not set(bad) & set(g["mixed_idx"].tolist())
+    ref = parity.oracle_path(wl)
+    parity.check_interface(wl, g, ref["rec"])
+    band = g["band_idx"]
+    parity.check_grad(wl, g["gradT"], ref["grad"], band)
+    parity.check_mdot(g["mdot"], ref["mdot"][g["mixed_idx"]])
+    # an explicit list with the bad cells and one mixed cell
+    good = int(g["mixed_idx"][0])
+    lst = torch.tensor(bad + [good] + [0] * (N - 4), dtype=torch.int32, device=run.dev)
+    cnt = torch.tensor([4, 0], dtype=torch.int32, device=run.dev)
+    itf = V.Interface.empty(N, run.dev)
+    torch.cuda.synchronize()
+    V.reconstruct(run.ctx, run.mesh, run.alpha, lst, cnt, itf)
+    torch.cuda.synchronize()
+    st = itf.status[:4].cpu().numpy()
+    np.testing.assert_array_equal(st, [V.CELL_BAD_INPUT] * 3 + [ref["rec"]["status"][good]])
+    assert np.all(np.isnan(itf.s[:3].cpu().numpy())) and np.all(itf.A[:3].cpu().numpy() == 0)
+    assert abs(itf.alpha_got[3].item() - ref["rec"]["alpha_got"][good]) <= 1e-10
+    np.testing.assert_array_equal(ref["rec"]["status"][bad], [oracle.BAD_INPUT] * 3)
+    run.close()
