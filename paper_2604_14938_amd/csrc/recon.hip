@@ -548,9 +548,20 @@ __device__ CutRes cut_fast(const FastSlot<kSlotChords> &F, int c, double s) {
   return R;
 }
 
+// Spacing of the doubles above |x|: the bit patterns of non-negative
+// doubles are ordered as their values, so the next double up is the pattern
+// plus one (+inf gives NaN, as nextafter(inf, inf) - inf does).
 __device__ __forceinline__ double ulp_of(double x) {
-  x = fabs(x);
-  return nextafter(x, __builtin_inf()) - x;
+  const double a = fabs(x);
+  return __longlong_as_double(__double_as_longlong(a) + 1) - a;
+}
+
+// The next double toward +inf (nextafter(x, +inf) for every x).
+__device__ __forceinline__ double next_up(double x) {
+  if (x == 0.0) return __longlong_as_double(1ll);   // either zero: the smallest subnormal
+  if (!(x < __builtin_inf())) return x;              // +inf and NaN stay
+  const long long b = __double_as_longlong(x);
+  return __longlong_as_double(x > 0.0 ? b + 1 : b - 1);
 }
 
 // The topology of a cut (which vertices are liquid, how faces with four or
@@ -1008,7 +1019,7 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
               // across the loop; scaling by 1/16 is exact)
               const double dd = lane < 5 ? 0.0625 * d : d;
               xc = (lane >= 3 && lane <= 6) ? ((lane & 1) ? se - dd : se + dd) : se;
-              if (lane == 1) xc = nextafter(blo, __builtin_inf());
+              if (lane == 1) xc = next_up(blo);
               if (lane == 2) xc = bhi;
               if (lane == 7) xc = lo + w0 / 2.0;
               okc = lane < 8 && xc > lo && xc < hi && xc > blo && xc <= bhi && (lane != 1 || lo <= blo) &&
