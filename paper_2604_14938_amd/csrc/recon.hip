@@ -637,29 +637,45 @@ __device__ __forceinline__ void store_end(GM &L, int lane, int side, const CutRe
 // The bracket network's normalised isovalue for the staged cell: its 32
 // inputs from the staged vertex values and the cell's faces, then the
 // forward pass on MFMA.
-template <int NF, class GM>
-__device__ float net_guess(GM &L, int lane, const ReconParams &p, int64_t k, int P, double aP, int nv, int nf,
-                           int64_t f0, double pmin, double Wd) {
-  constexpr int W = 64;
+// A face of the cell as the bracket network sees it: the area vector
+// oriented out of the cell and the neighbour's volume fraction.
+struct NetFace {
+  double S0, S1, S2, aQ;
+  bool inner;
+};
+
+__device__ __forceinline__ NetFace load_net_face(const ReconParams &p, int P, double aP, int64_t slot) {
   const DevMesh &m = p.m;
   const int64_t NFg = m.n_faces;
+  const int fid = m.cell_face[slot];
+  const int q = m.cf_nbr[slot];
+  const double sg = (m.face_owner[fid] == P) ? 1.0 : -1.0;
+  NetFace r;
+  r.S0 = sg * m.Sf[fid];
+  r.S1 = sg * m.Sf[NFg + fid];
+  r.S2 = sg * m.Sf[2 * NFg + fid];
+  r.inner = q >= 0;
+  r.aQ = r.inner ? p.alpha[q] : aP;
+  return r;
+}
+
+template <int NF, class GM>
+__device__ float net_guess(GM &L, int lane, const ReconParams &p, int64_t k, int P, double aP, int nv, int nf,
+                           int64_t f0, double pmin, double Wd, const NetFace &pf) {
+  constexpr int W = 64;
   // face sums (see the feature definitions) into L.nsum
   double amin = __builtin_inf(), amax = -__builtin_inf();
-  auto face = [&](int f, double &A, double &n0, double &n1, double &n2, double &aQ, bool &inner) {
-    const int fid = m.cell_face[f0 + f];
-    const double sg = (m.face_owner[fid] == P) ? 1.0 : -1.0;
-    const double S0 = sg * m.Sf[fid], S1 = sg * m.Sf[NFg + fid], S2 = sg * m.Sf[2 * NFg + fid];
-    A = sqrt(S0 * S0 + S1 * S1 + S2 * S2);
-    n0 = S0 / A; n1 = S1 / A; n2 = S2 / A;
-    const int q = m.cf_nbr[f0 + f];
-    inner = q >= 0;
-    aQ = inner ? p.alpha[q] : aP;
+  auto face = [&](const NetFace &g, double &A, double &n0, double &n1, double &n2, double &aQ, bool &inner) {
+    A = sqrt(g.S0 * g.S0 + g.S1 * g.S1 + g.S2 * g.S2);
+    n0 = g.S0 / A; n1 = g.S1 / A; n2 = g.S2 / A;
+    inner = g.inner;
+    aQ = g.aQ;
   };
   if constexpr (NF <= W) {
     // one face per lane: each sum is reduced as soon as it is formed
     double A = 0, n0 = 0, n1 = 0, n2 = 0, aQ = aP;
     bool inner = false;
-    if (lane < nf) face(lane, A, n0, n1, n2, aQ, inner);
+    if (lane < nf) face(pf, A, n0, n1, n2, aQ, inner);   // loaded before the staging
     const double da = A * (aQ - aP);
     if (inner) {
       amin = aQ;
@@ -687,7 +703,7 @@ __device__ float net_guess(GM &L, int lane, const ReconParams &p, int64_t k, int
     for (int f = lane; f < nf; f += W) {
       double A, n0, n1, n2, aQ;
       bool inner;
-      face(f, A, n0, n1, n2, aQ, inner);
+      face(load_net_face(p, P, aP, f0 + f), A, n0, n1, n2, aQ, inner);
       const double da = A * (aQ - aP);
       const double o[6] = {n0 * n0, n1 * n1, n2 * n2, n0 * n1, n0 * n2, n1 * n2};
       t[0] += A;
@@ -775,6 +791,10 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
     } else {
       const double xP0 = m.xc[P], xP1 = m.xc[N + P], xP2 = m.xc[2 * N + P];
       const double VP = m.V[P];
+      // learned form with one face per lane: the network's face data are
+      // loaded first, so their loads are in flight during the staging
+      NetFace pf{0.0, 0.0, 0.0, a, false};
+      if (NF <= W && p.net_wb && lane < nf) pf = load_net_face(p, P, a, f0 + lane);
       // ---- stage the polyhedron (vertex field by inverse-distance weights;
       // the incidences of a vertex are read four at a time, summed in order)
       for (int i = lane; i < nv; i += W) {
@@ -912,7 +932,7 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
           double hl = 0, hh = 0;
           if (p.net_wb && st == VOFPC_CELL_OK) {
             const double Wd = pmax - pmin;
-            const float u = net_guess<NF>(L, lane, p, k, P, a, nv, nf, f0, pmin, Wd);
+            const float u = net_guess<NF>(L, lane, p, k, P, a, nv, nf, f0, pmin, Wd, pf);
             if (!isnan(u)) {
               const double uc = u < 0.f ? 0.0 : (u > 1.f ? 1.0 : (double)u);
               const double sh = pmin + uc * Wd, dl = p.net_delta * Wd;
