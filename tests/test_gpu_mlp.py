@@ -232,3 +232,35 @@ def test_fused_network_bracket_matches_the_separate_kernels(V):
     assert np.percentile(d_lo, 99) <= 1e-3 and np.percentile(d_hi, 99) <= 1e-3
     run.close()
     mlp.close()
+
+
+def test_trained_network_saves_evaluations(V):
+    """What the trained network gains: on a Voronoi bubble (different seed
+    and size from the training meshes) the learned bracket reaches the same
+    results with fewer volume evaluations per cell than the plain search."""
+    import torch
+    from paper_2604_14938_amd import runner
+    w = _weights()
+    if w is None:
+        pytest.skip("no trained weights")
+    params, dscale, _ = w
+    wl = workloads.voronoi_bubble(n=24, seed=13, r=0.27)
+    _say(f"evaluations, plain vs learned: {wl.mesh.n_cells} cells, {wl.n_mixed} mixed")
+    ctx = V.Context(0, stream=torch.cuda.Stream())
+    plain = runner.PathRun(wl, ctx=ctx)
+    plain.step()
+    gp = plain.results()
+    mlp = V.Mlp(ctx)
+    mlp.set_params(params)
+    learned = runner.PathRun(wl, ctx=ctx, mlp=mlp, delta_scale=dscale)
+    learned.step()
+    gl = learned.results()
+    np.testing.assert_array_equal(gl["mixed_idx"], gp["mixed_idx"])
+    assert np.abs(gl["alpha_got"] - gp["alpha_got"]).max() <= 1e-10
+    ep, el = gp["iters"].mean(), gl["iters"].mean()
+    fb = (gl["status"] == V.CELL_LEARNED_FALLBACK).mean()
+    _say(f"mean evaluations per cell: plain {ep:.2f}, learned {el:.2f}; fallback rate {fb:.3f}")
+    assert el < 0.95 * ep
+    plain.close()
+    learned.close()
+    mlp.close()
