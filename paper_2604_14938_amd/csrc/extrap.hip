@@ -347,11 +347,13 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   p.max_iter = o.max_iter;
   p.gl = gradT_l;
   p.gv = gradT_v;
-  // sweeps: 16 domain cells per block; the finish kernel one cell per thread
+  // sweeps: 16 domain cells per block, four blocks per CU (a domain of
+  // 16k cells in one pass: each pass is a chain of dependent gathers); the
+  // finish kernel one cell per thread
   const unsigned gS = (unsigned)std::max<int64_t>(1, std::min<int64_t>(gN, (int64_t)ctx->n_cu * 2));
   const unsigned gW = (unsigned)std::max<int64_t>(
       1, std::min<int64_t>((N + kExBlock / kExLanes - 1) / (kExBlock / kExLanes),
-                           std::min<int64_t>((int64_t)ctx->n_cu * 2, kExMaxGrid)));
+                           std::min<int64_t>((int64_t)ctx->n_cu * 4, kExMaxGrid)));
   // the upwind stencil once; then one kernel per sweep: the kernel boundary
   // orders the sweeps, and once the tolerance is met the remaining sweep
   // kernels return at once
