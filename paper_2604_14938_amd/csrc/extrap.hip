@@ -153,19 +153,25 @@ __global__ __launch_bounds__(kExBlock) void ex_stencil_kernel(ExParams p) {
     ex_stencil(p, j, lane);
 }
 
-// Upwind update of domain entry j from iterate cur into nxt by the 16 lanes
-// of one row, one face slot per lane; returns (on lane 0) the largest change
-// of its three advanced components.  The kept field was written to both
-// iterates at the start and is not touched.
-__device__ __forceinline__ double ex_update(const ExParams &p, int64_t j, int lane, const double *cur,
-                                            double *nxt) {
+// Upwind update of domain entry j from iterate cur by the 16 lanes of one
+// row, one face slot per lane: the new values of its three advanced
+// components and their largest change (ex_compute), written into the next
+// iterate by ex_store.  The kept field was written to both iterates at the
+// start and is not touched.
+struct ExNew {
+  int P, adv;
+  double n0, n1, n2, change;
+};
+
+__device__ __forceinline__ ExNew ex_compute(const ExParams &p, int64_t j, int lane, const double *cur) {
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells;
-  const int P = p.list[j];
-  const int adv = p.alpha[P] >= 0.5 ? 3 : 0;   // G_v advances in liquid, G_l in vapour
-  const double *ca = cur + (int64_t)adv * N;
+  ExNew r;
+  r.P = p.list[j];
+  r.adv = p.alpha[r.P] >= 0.5 ? 3 : 0;   // G_v advances in liquid, G_l in vapour
+  const double *ca = cur + (int64_t)r.adv * N;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int64_t i = m.cell_face_off[P] + lane; i < m.cell_face_off[P + 1]; i += kExLanes) {
+  for (int64_t i = m.cell_face_off[r.P] + lane; i < m.cell_face_off[r.P + 1]; i += kExLanes) {
     const double wf = p.wup[i];
     if (wf == 0.0) continue;
     const int Q = m.cf_nbr[i];
@@ -176,15 +182,22 @@ __device__ __forceinline__ double ex_update(const ExParams &p, int64_t j, int la
   a0 = gsum<kExLanes>(a0);
   a1 = gsum<kExLanes>(a1);
   a2 = gsum<kExLanes>(a2);
-  if (lane != 0) return 0.0;
   const double th = p.theta[j];
+  const int P = r.P;
   const double o0 = ca[P], o1 = ca[N + P], o2 = ca[2 * N + P];
-  const double n0 = o0 + th * (a0 - o0), n1 = o1 + th * (a1 - o1), n2 = o2 + th * (a2 - o2);
-  double *na = nxt + (int64_t)adv * N;
-  na[P] = n0;
-  na[N + P] = n1;
-  na[2 * N + P] = n2;
-  return fmax(fabs(n0 - o0), fmax(fabs(n1 - o1), fabs(n2 - o2)));
+  r.n0 = o0 + th * (a0 - o0);
+  r.n1 = o1 + th * (a1 - o1);
+  r.n2 = o2 + th * (a2 - o2);
+  r.change = fmax(fabs(r.n0 - o0), fmax(fabs(r.n1 - o1), fabs(r.n2 - o2)));
+  return r;
+}
+
+__device__ __forceinline__ void ex_store(const ExParams &p, const ExNew &r, double *nxt) {
+  const int64_t N = p.m.n_cells;
+  double *na = nxt + (int64_t)r.adv * N;
+  na[r.P] = r.n0;
+  na[N + r.P] = r.n1;
+  na[2 * N + r.P] = r.n2;
 }
 
 // Sweep `it` (0-based) of the Jacobi iteration.  From the second sweep on it
@@ -196,6 +209,19 @@ __global__ __launch_bounds__(kExBlock) void ex_sweep_kernel(ExParams p, int it) 
   const int converged = p.info[4];
   const int64_t nd = p.info[1];
   if (converged) return;
+  const int64_t N = p.m.n_cells;
+  const double *cur = p.buf + (int64_t)(it & 1) * 6 * N;
+  double *nxt = p.buf + (int64_t)((it + 1) & 1) * 6 * N;
+  // rows of 16 lanes take the domain cells; every lane of a row sees the
+  // same cells, so the row reductions see all its lanes.  The row's first
+  // cell is computed before the convergence test of the previous sweep (its
+  // gathers and that test's reads are in flight together) and stored after.
+  constexpr int kCells = kExBlock / kExLanes;
+  const int lane = threadIdx.x % kExLanes;
+  const int64_t j0 = blockIdx.x * (int64_t)kCells + threadIdx.x / kExLanes;
+  const int64_t stride = (int64_t)gridDim.x * kCells;
+  ExNew first{0, 0, 0.0, 0.0, 0.0, 0.0};
+  if (j0 < nd) first = ex_compute(p, j0, lane, cur);
   if (it > 0) {
     // largest change of the previous sweep: the maximum of its blocks'
     // partial maxima (every block of that kernel wrote its slot)
@@ -216,16 +242,18 @@ __global__ __launch_bounds__(kExBlock) void ex_sweep_kernel(ExParams p, int it) 
       return;
     }
   }
-  const int64_t N = p.m.n_cells;
-  const double *cur = p.buf + (int64_t)(it & 1) * 6 * N;
-  double *nxt = p.buf + (int64_t)((it + 1) & 1) * 6 * N;
   double change = 0.0;
-  // rows of 16 lanes take the domain cells; every lane of a row sees the
-  // same cells, so the row reductions see all its lanes
-  constexpr int kCells = kExBlock / kExLanes;
-  const int lane = threadIdx.x % kExLanes;
-  for (int64_t j = blockIdx.x * (int64_t)kCells + threadIdx.x / kExLanes; j < nd; j += (int64_t)gridDim.x * kCells)
-    change = fmax(change, ex_update(p, j, lane, cur, nxt));
+  if (j0 < nd && lane == 0) {
+    ex_store(p, first, nxt);
+    change = first.change;
+  }
+  for (int64_t j = j0 + stride; j < nd; j += stride) {
+    const ExNew r = ex_compute(p, j, lane, cur);
+    if (lane == 0) {
+      ex_store(p, r, nxt);
+      change = fmax(change, r.change);
+    }
+  }
   // this block's largest change into its slot of this sweep's partials
   // (plain stores: the next sweep kernel reads them after the kernel boundary)
   for (int o = 32; o > 0; o >>= 1) change = fmax(change, __shfl_xor(change, o));
