@@ -74,21 +74,6 @@ __global__ __launch_bounds__(kExBlock) void ex_interface_normal_kernel(int64_t N
   nrm[2 * N + P] = itf.n[2 * itf.cap + k];
 }
 
-// both fields start from the gradient
-__global__ __launch_bounds__(kExBlock) void ex_fields_kernel(int64_t N, const int32_t *list, const int32_t *info,
-                                                             const double *grad, double *buf) {
-  const int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x;
-  if (j >= info[1]) return;
-  const int P = list[j];
-  for (int d = 0; d < 3; ++d) {
-    const double g = grad[d * N + P];
-    buf[d * N + P] = g;
-    buf[(3 + d) * N + P] = g;
-    buf[(6 + d) * N + P] = g;
-    buf[(9 + d) * N + P] = g;
-  }
-}
-
 struct ExParams {
   DevMesh m;
   const double *alpha;
@@ -107,7 +92,8 @@ struct ExParams {
 
 constexpr int kExLanes = 16;   // lanes per domain cell in the stencil and sweeps (one DPP row)
 
-// The upwind stencil of domain entry j, fixed for the whole iteration: with
+// The upwind stencil of domain entry j, fixed for the whole iteration (and
+// the start of both fields, the gradient p.gl, written to both iterates): with
 // c = sgn(alpha - 1/2) n, the faces with c.S_f < 0 (S_f outward) whose
 // neighbour is in the domain get w_f = -c.S_f; each such cell-face slot keeps
 // w_f / sum w, every other slot 0, and the entry keeps
@@ -116,6 +102,14 @@ __device__ __forceinline__ void ex_stencil(const ExParams &p, int64_t j, int lan
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells, NF = m.n_faces;
   const int P = p.list[j];
+  if (lane < 3) {
+    // both fields start from the gradient (each iterate)
+    const double g = p.gl[lane * N + P];
+    p.buf[lane * N + P] = g;
+    p.buf[(3 + lane) * N + P] = g;
+    p.buf[(6 + lane) * N + P] = g;
+    p.buf[(9 + lane) * N + P] = g;
+  }
   const double sgn = p.alpha[P] >= 0.5 ? 1.0 : -1.0;
   const double c0 = sgn * p.nrm[P], c1 = sgn * p.nrm[N + P], c2 = sgn * p.nrm[2 * N + P];
   const int64_t i0 = m.cell_face_off[P], i1 = m.cell_face_off[P + 1];
@@ -349,16 +343,12 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   // neighbours only) on the domain; the domain length sits in ex_info[1],
   // where the gradient kernel reads its band count
   const int32_t *dom_counts = M->ex_info;
-  vofpc_status st = launch_grad(ctx, M, T, T_bface, T_sat, alpha, M->ex_list, dom_counts, VOFPC_SCOPE_BAND,
-                                VOFPC_GRAD_MODIFIED, gradT_l, nullptr);
-  if (st) return st;
-  st = launch_grad(ctx, M, alpha, nullptr, 0.0, alpha, M->ex_list, dom_counts, VOFPC_SCOPE_BAND, VOFPC_GRAD_STANDARD,
-                   M->ex_nrm, nullptr);
+  vofpc_status st = launch_grad2(ctx, M, M->ex_list, dom_counts, T, T_bface, T_sat, alpha, VOFPC_GRAD_MODIFIED,
+                                 gradT_l, alpha, nullptr, 0.0, alpha, VOFPC_GRAD_STANDARD, M->ex_nrm);
   if (st) return st;
   ex_normalise_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_list, M->ex_info, M->ex_nrm);
   const unsigned gM = (unsigned)((std::min<int64_t>(itf->cap, N) + kExBlock - 1) / kExBlock);
   ex_interface_normal_kernel<<<gM, kExBlock, 0, s>>>(N, mixed_idx, counts, *itf, M->ex_nrm);
-  ex_fields_kernel<<<gN, kExBlock, 0, s>>>(N, M->ex_list, M->ex_info, gradT_l, M->ex_buf);
   ExParams p;
   p.m = M->d;
   p.alpha = alpha;

@@ -132,9 +132,24 @@ __global__ __launch_bounds__(256) void grad_kernel(GradParams p) {
   }
 }
 
-vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh M, const double *T, const double *Tb, double T_sat,
-                         const double *alpha, const int32_t *band, const int32_t *counts, int32_t scope,
-                         int32_t variant, double *grad, int32_t *status) {
+// Two gradients over the same band list in one launch (the row computes
+// both for its cell; used where a caller needs two fields' gradients on one
+// domain).
+__global__ __launch_bounds__(256) void grad2_kernel(GradParams a, GradParams b) {
+  const int64_t n = a.counts[1];
+  constexpr int kCellsPerBlock = 256 / kGradLanes;
+  const int j = threadIdx.x % kGradLanes;
+  const int64_t stride = (int64_t)gridDim.x * kCellsPerBlock;
+  for (int64_t k = blockIdx.x * (int64_t)kCellsPerBlock + threadIdx.x / kGradLanes; k < n; k += stride) {
+    const int P = a.band[k];
+    grad_cell(a, P, j);
+    grad_cell(b, P, j);
+  }
+}
+
+static vofpc_status grad_params(vofpc_mesh M, const double *T, const double *Tb, double T_sat, const double *alpha,
+                                const int32_t *band, const int32_t *counts, int32_t scope, int32_t variant,
+                                double *grad, int32_t *status, GradParams &p) {
   VOFPC_REQUIRE(T && alpha && grad, VOFPC_E_INVALID_ARG, "grad_T: null argument");
   VOFPC_REQUIRE(scope == VOFPC_SCOPE_BAND || scope == VOFPC_SCOPE_ALL, VOFPC_E_INVALID_ARG, "grad_T: unknown scope");
   VOFPC_REQUIRE(scope == VOFPC_SCOPE_ALL || (band && counts), VOFPC_E_INVALID_ARG,
@@ -147,7 +162,6 @@ vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh M, const double *T, const dou
                 VOFPC_E_INVALID_ARG, "grad_T: unknown variant");
   VOFPC_REQUIRE(!(flags & VOFPC_GRAD_VERTEX_STENCIL) || M->xn_off, VOFPC_E_STATE,
                 "grad_T: the vertex stencil of this mesh is not built");
-  GradParams p;
   p.m = M->d;
   p.T = T; p.Tb = Tb; p.alpha = alpha; p.T_sat = T_sat;
   p.band = band; p.counts = counts;
@@ -156,11 +170,37 @@ vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh M, const double *T, const dou
   p.xn_off = (flags & VOFPC_GRAD_VERTEX_STENCIL) ? M->xn_off : nullptr;
   p.xn_cell = (flags & VOFPC_GRAD_VERTEX_STENCIL) ? M->xn_cell : nullptr;
   p.grad = grad; p.status = status;
-  const int64_t N = M->d.n_cells;
-  int64_t grid = (N + 15) / 16;
+  return VOFPC_OK;
+}
+
+static unsigned grad_grid(vofpc_ctx ctx, vofpc_mesh M) {
+  int64_t grid = (M->d.n_cells + 15) / 16;
   const int64_t cap = (int64_t)ctx->n_cu * 16;
   if (grid > cap) grid = cap;
-  grad_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(p);
+  return (unsigned)(grid > 0 ? grid : 1);
+}
+
+vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh M, const double *T, const double *Tb, double T_sat,
+                         const double *alpha, const int32_t *band, const int32_t *counts, int32_t scope,
+                         int32_t variant, double *grad, int32_t *status) {
+  GradParams p;
+  vofpc_status st = grad_params(M, T, Tb, T_sat, alpha, band, counts, scope, variant, grad, status, p);
+  if (st) return st;
+  grad_kernel<<<grad_grid(ctx, M), 256, 0, ctx->stream>>>(p);
+  VOFPC_HIP(hipGetLastError());
+  return VOFPC_OK;
+}
+
+vofpc_status launch_grad2(vofpc_ctx ctx, vofpc_mesh M, const int32_t *band, const int32_t *counts, const double *T1,
+                          const double *Tb1, double T_sat1, const double *alpha1, int32_t variant1, double *grad1,
+                          const double *T2, const double *Tb2, double T_sat2, const double *alpha2, int32_t variant2,
+                          double *grad2) {
+  GradParams a, b;
+  vofpc_status st = grad_params(M, T1, Tb1, T_sat1, alpha1, band, counts, VOFPC_SCOPE_BAND, variant1, grad1, nullptr, a);
+  if (st) return st;
+  st = grad_params(M, T2, Tb2, T_sat2, alpha2, band, counts, VOFPC_SCOPE_BAND, variant2, grad2, nullptr, b);
+  if (st) return st;
+  grad2_kernel<<<grad_grid(ctx, M), 256, 0, ctx->stream>>>(a, b);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;
 }

@@ -180,6 +180,11 @@ vofpc_status mesh_vertex_stencil(vofpc_mesh M);
 const uint16_t *mlp_weights_bf16(vofpc_mlp M);
 const float *mlp_params_f32(vofpc_mlp M);
 int mlp_device(vofpc_mlp M);
+// two band-scope gradients over one list in a single launch
+vofpc_status launch_grad2(vofpc_ctx ctx, vofpc_mesh m, const int32_t *band, const int32_t *counts, const double *T1,
+                          const double *Tb1, double T_sat1, const double *alpha1, int32_t variant1, double *grad1,
+                          const double *T2, const double *Tb2, double T_sat2, const double *alpha2, int32_t variant2,
+                          double *grad2);
 vofpc_status launch_grad(vofpc_ctx ctx, vofpc_mesh m, const double *T, const double *Tb, double T_sat,
                          const double *alpha, const int32_t *band, const int32_t *counts, int32_t scope,
                          int32_t variant, double *grad, int32_t *status);
