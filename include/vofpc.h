@@ -375,8 +375,10 @@ vofpc_status vofpc_robin(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, co
  * n [3][n_cells], kappa [n_cells] required; kappa_raw [n_cells] and force
  * [3][n_cells] optional (NULL skips; without force the gradient of alpha is
  * not computed).  opts NULL: defaults.  The first call on a mesh allocates
- * its scratch (24 B per cell, mesh-owned) and must not be captured; later
- * calls are graph-capturable.  Calls on one mesh must not overlap. */
+ * its scratch (about 29 B per cell plus a table of 16 B per cell-face slot,
+ * the neighbour weights and face areas, mesh-owned) and must not be
+ * captured; later calls are graph-capturable.  Calls on one mesh must not
+ * overlap. */
 typedef struct {
   int32_t n_smooth;  /* smoothing sweeps of alpha (2) */
   double sigma;      /* surface tension coefficient for the force (1.0) */
