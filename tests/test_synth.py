@@ -75,3 +75,29 @@ def test_host_concat_is_the_disjoint_union():
     np.testing.assert_array_equal(gw.Sf, np.concatenate([g.Sf for g in gp], 1))
     assert whole.n_cells == sum(p.n_cells for p in parts)
     assert np.all(whole.face_owner[parts[0].n_faces:] >= parts[0].n_cells)
+
+
+@pytest.mark.parametrize("n_sides,fan", [(4, False), (24, False), (64, False), (40, True)])
+def test_prism_columns_are_closed_outward_polyhedra(n_sides, fan):
+    """Every cell of a prismatoid column is closed (its outward face area
+    vectors sum to zero) and every face is planar, and the caps are shared
+    by consecutive cells."""
+    m = meshes.prism_column(n_sides, 5, fan_caps=fan)
+    X = m.vert_xyz
+    S = np.zeros((m.n_faces, 3))
+    for f in range(m.n_faces):
+        v = m.face_vert[m.face_vert_off[f]:m.face_vert_off[f + 1]]
+        p = X[:, v].T
+        c = p.mean(0)
+        for a in range(len(v)):
+            S[f] += 0.5 * np.cross(p[a] - c, p[(a + 1) % len(v)] - c)
+        nrm = S[f] / np.linalg.norm(S[f])
+        assert np.abs((p - c) @ nrm).max() < 1e-12       # planar
+    for P in range(m.n_cells):
+        tot = np.zeros(3)
+        for f in m.cell_face[m.cell_face_off[P]:m.cell_face_off[P + 1]]:
+            tot += S[f] if m.face_owner[f] == P else -S[f]
+        assert np.abs(tot).max() < 1e-13
+    inner = m.face_neigh >= 0
+    assert np.all(m.face_neigh[inner] == m.face_owner[inner] + 1)
+    assert inner.sum() == (m.n_cells - 1) * (n_sides if fan else 1)
