@@ -191,7 +191,7 @@ def load(path: str = DEFAULT_WEIGHTS) -> tuple[np.ndarray, float, dict]:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=600_000)
-    ap.add_argument("--steps", type=int, default=12000)
+    ap.add_argument("--steps", type=int, default=120000)
     ap.add_argument("--seed", type=int, default=2604)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     a = ap.parse_args()
