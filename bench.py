@@ -11,7 +11,13 @@ vertex-value range) and learned (the bracket network inside the
 reconstruction kernel gives the first guess).  The headline value is the
 learned form when trained weights are present, else the plain one.
 
-Prints one JSON line (see the README of the repository for the fields).
+Prints one JSON line: the metric and its value (mixed cells per second of
+the headline form), the step time, `config` (the workload, both forms'
+figures: evaluations per cell, fallback rate, agreement of the two forms,
+and the follow-on rows timed on the same interface), `roofline` (the
+reconstruction kernel against the FP64 vector peak, its HBM fraction beside
+it, and the HBM traffic measured by rocprofv3 for the current kernel sources,
+else null) and `cpu_baseline` (the CPU oracle on one host thread).
 """
 from __future__ import annotations
 
