@@ -183,3 +183,30 @@ def test_follow_on_rows_on_a_concatenated_mesh(R):
     np.testing.assert_allclose(k.cpu().numpy(), cs["kappa"], rtol=0, atol=1e-9 * np.abs(cs["kappa"]).max())
     np.testing.assert_allclose(F.cpu().numpy(), cs["F"], rtol=0, atol=1e-9 * np.abs(cs["F"]).max())
     run.close()
+
+
+def test_learned_form_in_the_bucketed_launch(R):
+    """The learned bracket inside both kernel classes of a bucketed launch
+    (hexahedral and Voronoi cells together) gives the oracle's results."""
+    import os
+    import torch
+    from paper_2604_14938_amd import train, vofpc as V
+    if not os.path.exists(train.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    params, dscale, _ = train.load()
+    wls = workloads.batched(hex_n=24, vor_n=12, seed=9, n_max=200, K=12, r_hi_h=3.0)
+    wl = workloads.concat_workloads(wls)
+    _say(f"learned, bucketed: {[w.mesh.n_cells for w in wls]} cells, {wl.n_mixed} mixed")
+    ctx = V.Context(0, stream=torch.cuda.Stream())
+    mlp = V.Mlp(ctx)
+    mlp.set_params(params)
+    run = R.PathRun(wl, ctx=ctx, parts=[w.mesh for w in wls], mlp=mlp, delta_scale=dscale)
+    assert run.mesh.classes()["bucketed"]
+    run.step()
+    g = run.results()
+    fb = g["status"] == V.CELL_LEARNED_FALLBACK
+    g["status"] = np.where(fb, V.CELL_OK, g["status"])
+    rep = _check_step(wl, g)
+    _say(f"learned bucketed ok: {rep}; fallback rate {fb.mean():.3f}, mean evaluations {g['iters'].mean():.1f}")
+    run.close()
+    mlp.close()
