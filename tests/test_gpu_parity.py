@@ -415,3 +415,66 @@ def test_out_of_range_and_nan_fractions(V, runner):
     assert abs(itf.alpha_got[3].item() - ref["rec"]["alpha_got"][good]) <= 1e-10
     np.testing.assert_array_equal(ref["rec"]["status"][bad], [oracle.BAD_INPUT] * 3)
     run.close()
+
+
+def test_iteration_cap_gives_consistent_cuts(V, runner):
+    """With the evaluation cap far below what the tolerance needs, cells end
+    with MAX_ITER (or OK when the cap sufficed, NO_ROOT where the volume
+    jumps over the target) and report the kept bracket end; whatever the
+    search did, every reported interface must be the cut at the reported
+    isovalue.  Both sides take the oracle's vertex field (the library's
+    caller-supplied field option), so that the breakpoints of the volume
+    function, where it may jump, are the same numbers on both: the oracle's
+    cut at the GPU's s then gives the same liquid fraction, area, normal and
+    distance."""
+    import torch
+    wl = _wl("vor12")
+    geom = oracle.geometry(wl.mesh)
+    phi = oracle.vertex_field(wl.mesh, geom.xc, wl.alpha)
+    h = wl.mesh.h
+    for cap in (3, 9):
+        phi_d = torch.as_tensor(phi, dtype=torch.float64, device="cuda")
+        run = runner.PathRun(wl, opts=V.recon_opts(max_iter=cap, phi_vertex=phi_d))
+        run.step()
+        g = run.results()
+        st = g["status"]
+        _say(f"iteration cap {cap}: {len(st)} mixed, statuses {np.bincount(st, minlength=8)}")
+        assert set(np.unique(st).tolist()) <= {V.CELL_OK, V.CELL_MAX_ITER, V.CELL_NO_ROOT}
+        assert (st == V.CELL_MAX_ITER).any()
+        for k, P in enumerate(g["mixed_idx"]):
+            c = oracle.cut_cell(wl.mesh, int(P), geom.xc, phi, float(g["s"][k]))
+            assert abs(c["V"] / geom.V[P] - g["alpha_got"][k]) <= 1e-12, (cap, int(P))
+            assert abs(c["A"] - g["A"][k]) <= 1e-9 * c["A"] + 1e-9 * h * h
+            n = c["S"] / np.linalg.norm(c["S"])
+            assert np.linalg.norm(n - g["n"][:, k]) <= 1e-9
+            assert abs(-(n @ c["c"]) - g["d"][k]) <= 1e-9 * h
+        run.close()
+    torch.cuda.synchronize()
+
+
+def test_singular_least_squares_matrix(V):
+    """A column of cells with only the cells above and below as neighbours
+    (every side face a symmetry face): the least-squares matrix has rank one,
+    so every cell gets G_SINGULAR and a zero gradient, as in the oracle."""
+    import torch
+    mesh = meshes.prism_column(6, 5)
+    mesh.face_bc = np.where(mesh.face_neigh < 0, 2, 0).astype(np.int8)
+    N = mesh.n_cells
+    T = 373.15 + 2.0 * mesh.cell_vertex_mean()[:, 2]
+    alpha = np.ones(N)
+    geom = oracle.geometry(mesh)
+    og, ost = oracle.grad(mesh, geom, T, np.zeros(mesh.n_faces), 373.15, alpha)
+    assert np.all(ost == oracle.G_SINGULAR) and np.all(og == 0)
+    ctx = V.Context(0, stream=torch.cuda.Stream())
+    m = V.Mesh(ctx, mesh)
+    f64 = dict(dtype=torch.float64, device=ctx.device)
+    g = torch.full((3, N), np.nan, **f64)
+    st = torch.full((N,), -1, dtype=torch.int32, device=ctx.device)
+    torch.cuda.synchronize()
+    V.grad_T(ctx, m, torch.as_tensor(T, **f64), torch.zeros(mesh.n_faces, **f64), 373.15,
+             torch.as_tensor(alpha, **f64), None, None, g, st, scope=V.SCOPE_ALL)
+    torch.cuda.synchronize()
+    _say("singular least squares on a symmetric column")
+    np.testing.assert_array_equal(st.cpu().numpy(), np.full(N, V.CELL_G_SINGULAR))
+    assert np.all(g.cpu().numpy() == 0)
+    m.close()
