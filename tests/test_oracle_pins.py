@@ -730,3 +730,47 @@ def test_prismatoid_horizontal_cut_matches_the_cross_section_integral(n_sides, f
             assert res["A"] == pytest.approx(an * rad(s) ** 2, rel=1e-12)
             np.testing.assert_allclose(res["S"] / np.linalg.norm(res["S"]), [0, 0, 1], atol=1e-12)
             assert res["nloops"] == 1
+
+
+def test_vertex_field_invariants():
+    """The vertex field (the reading of the paper's vertex values: the
+    inverse-distance average of the cells sharing the vertex): a constant
+    fraction gives that constant; every vertex value is a convex
+    combination of its cells' fractions (both up to the rounding of the
+    normalised weights); on a uniform hexahedral mesh an
+    interior vertex is equidistant from its eight cells, so its value is
+    their plain mean, and the plain-mean mode gives the same there.  These
+    fix the set of cells and the normalisation; the inverse-distance weight
+    itself is the reading of the silent paper, with no reference beyond its
+    definition."""
+    rng = np.random.default_rng(17)
+    vm = meshes.voronoi_box_mesh(5, seed=4)
+    om = oracle.OMesh(vm)
+    geom = oracle.geometry(om)
+    phi = oracle.vertex_field(om, geom.xc, np.full(vm.n_cells, 0.37))
+    np.testing.assert_allclose(phi, 0.37, rtol=0, atol=1e-15)
+    a = rng.uniform(0, 1, vm.n_cells)
+    phi = oracle.vertex_field(om, geom.xc, a)
+    # cells of each vertex
+    lo = np.full(vm.n_verts, np.inf)
+    hi = np.full(vm.n_verts, -np.inf)
+    for P in range(vm.n_cells):
+        ids = _cell_vertex_ids(vm, P)
+        lo[ids] = np.minimum(lo[ids], a[P])
+        hi[ids] = np.maximum(hi[ids], a[P])
+    assert np.all(phi >= lo - 1e-15) and np.all(phi <= hi + 1e-15)
+    n = 4
+    hm = meshes.hex_mesh(n)
+    omh = oracle.OMesh(hm)
+    gh = oracle.geometry(omh)
+    a = rng.uniform(0, 1, hm.n_cells)
+    pi = oracle.vertex_field(omh, gh.xc, a)
+    pm = oracle.vertex_field(omh, gh.xc, a, mode=1)
+    m = n + 1
+    for k in range(1, n):
+        for j in range(1, n):
+            for i in range(1, n):
+                v = i + m * (j + m * k)
+                cells = [(i - di) + n * ((j - dj) + n * (k - dk)) for di in (0, 1) for dj in (0, 1) for dk in (0, 1)]
+                mean = np.mean(a[cells])
+                assert abs(pi[v] - mean) < 1e-15 and abs(pm[v] - mean) < 1e-15
