@@ -1,5 +1,6 @@
-// Mixed-cell and gradient-band compaction: a face pass for the band test,
-// a cell pass with wavefront ballots and block totals, and a scatter whose
+// Mixed-cell and gradient-band compaction: a face pass for the band test
+// (meshes with cells of at most eight faces test it in the cell pass), a
+// cell pass with wavefront ballots and block totals, and a scatter whose
 // blocks sum the totals before them, giving stable (ascending) index lists
 // and their lengths in device memory.
 #include <hip/hip_runtime.h>
@@ -43,6 +44,45 @@ __global__ __launch_bounds__(kCompactBlock) void compact_flags_kernel(DevMesh m,
     const uint8_t cr = cross[P];
     band = mixed || cr;
     if (cr) cross[P] = 0;
+    flags[P] = (uint8_t)((mixed ? 1 : 0) | (band ? 2 : 0));
+  }
+  uint64_t bm = __ballot(mixed), bb = __ballot(band);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    wsum[0][w] = __popcll(bm);
+    wsum[1][w] = __popcll(bb);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    int32_t t = 0;
+    for (int i = 0; i < kWaves; ++i) t += wsum[threadIdx.x][i];
+    blk_cnt[threadIdx.x * n_blk + blockIdx.x] = t;
+  }
+}
+
+// The same flags and totals without the face pass, for meshes whose cells
+// have at most eight faces (hexahedra): each cell tests the band over its own
+// face neighbours, the eight slots' loads in flight together.  With more
+// faces per cell these reads scatter and the face pass is faster.
+__global__ __launch_bounds__(kCompactBlock) void compact_cells_kernel(DevMesh m, const double *alpha, double eps,
+                                                                      uint8_t *flags, int32_t *blk_cnt,
+                                                                      int64_t n_blk) {
+  __shared__ int32_t wsum[2][kWaves];
+  const int64_t P = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
+  bool mixed = false, band = false;
+  if (P < m.n_cells) {
+    const double a = alpha[P];
+    mixed = (a > eps) && (a < 1.0 - eps);
+    band = mixed;
+    const int64_t i0 = m.cell_face_off[P], i1 = m.cell_face_off[P + 1];
+    int q[8];
+    double aq[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) q[t] = (i0 + t < i1) ? m.cf_nbr[i0 + t] : -1;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) aq[t] = q[t] >= 0 ? alpha[q[t]] : 0.5;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) band = band || ((a - 0.5) * (aq[t] - 0.5) < 0.0);
     flags[P] = (uint8_t)((mixed ? 1 : 0) | (band ? 2 : 0));
   }
   uint64_t bm = __ballot(mixed), bb = __ballot(band);
@@ -114,9 +154,14 @@ vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, do
   VOFPC_REQUIRE(eps >= 0 && eps < 0.5, VOFPC_E_INVALID_ARG, "compact: eps_mixed must be in [0, 0.5)");
   const int64_t nb = M->n_blk;
   hipStream_t s = ctx->stream;
-  const int64_t nfb = (M->d.n_faces + kCompactBlock - 1) / kCompactBlock;
-  compact_faces_kernel<<<(unsigned)nfb, kCompactBlock, 0, s>>>(M->d, alpha, M->cross);
-  compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->cross, M->flags, M->blk_cnt, nb);
+  if (M->max_nf <= 8) {
+    compact_cells_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->flags, M->blk_cnt, nb);
+  } else {
+    const int64_t nfb = (M->d.n_faces + kCompactBlock - 1) / kCompactBlock;
+    compact_faces_kernel<<<(unsigned)nfb, kCompactBlock, 0, s>>>(M->d, alpha, M->cross);
+    compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->cross, M->flags, M->blk_cnt,
+                                                                 nb);
+  }
   compact_scatter_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, M->flags, M->blk_cnt, nb, mixed, band,
                                                                   counts);
   VOFPC_HIP(hipGetLastError());
