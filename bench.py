@@ -194,8 +194,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--form", choices=("both", "plain", "learned"), default="both",
                     help="which forms to time (profiling runs time one)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="autotune the reconstruction kernel flavours on the workload before timing")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default kernel flavours instead of autotuning them on the workload before timing")
     ap.add_argument("--workload", choices=("voronoi_bubble", "batched", "pipe", "multi"), default="voronoi_bubble",
                     help="batched: a 128^3 hexahedral and a 986,078-cell Voronoi mesh with random bubbles, "
                          "stepped as one (a throughput-regime check); pipe: a Voronoi pipe with a wavy liquid "
