@@ -13,17 +13,28 @@ Every mesh is returned in the CSR form the library and the oracle both take:
 The Voronoi mesh stands in for the dualised GMSH polyhedra of the paper's
 polyhedral runs (Sec. 3.3), which are not available: a body-centred cubic
 lattice jittered by +-0.3 h_eff per coordinate gives about 14 faces per cell.
-Clipping to the unit box uses mirror seeds: the Voronoi cell of a seed among
-the seeds and their reflections in the six box planes is exactly the box-clipped
-cell, because a reflected seed is never nearer than its original to a point of
-the box.
+Two constructions give the same cells: a native one (``_voronoi.c``: each
+cell is the box clipped by the bisectors of its nearest seeds, OpenMP over
+cells; millions of cells in seconds), the default, and scipy's Qhull with
+mirror seeds (the Voronoi cell of a seed among the seeds and their
+reflections in the six box planes is exactly the box-clipped cell, because a
+reflected seed is never nearer than its original to a point of the box),
+kept to cross-check the native one.
 """
 from __future__ import annotations
 
+import ctypes
 import itertools
+import os
+import subprocess
 from dataclasses import dataclass, field
+from functools import lru_cache
 
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_VSRC = os.path.join(_HERE, "_voronoi.c")
+_VSO = os.path.join(_HERE, "_voronoi.so")
 
 
 @dataclass
@@ -400,18 +411,107 @@ def _finish(owner, neigh, fo, fv, X, keep_idx, kind, h, seeds, extra=None, other
     )
 
 
+def build_voronoi_helper(force: bool = False) -> str:
+    """Compile the native Voronoi helper in place (gcc, OpenMP)."""
+    if force or not os.path.exists(_VSO) or os.path.getmtime(_VSO) < os.path.getmtime(_VSRC):
+        tmp = _VSO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _VSRC, "-lm"])
+        os.replace(tmp, _VSO)
+    return _VSO
+
+
+class _VGResult(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("n_faces", ctypes.c_int64), ("n_verts", ctypes.c_int64),
+                ("n_fv", ctypes.c_int64), ("cell_face_off", ctypes.c_void_p), ("cell_face", ctypes.c_void_p),
+                ("face_vert_off", ctypes.c_void_p), ("face_vert", ctypes.c_void_p), ("face_owner", ctypes.c_void_p),
+                ("face_neigh", ctypes.c_void_p), ("vert_xyz", ctypes.c_void_p), ("face_plane", ctypes.c_void_p),
+                ("cell_seed", ctypes.c_void_p)]
+
+
+@lru_cache(maxsize=1)
+def _vlib():
+    build_voronoi_helper()
+    lib = ctypes.CDLL(_VSO)
+    P = ctypes.c_void_p
+    lib.vg_build.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int, P, P]
+    lib.vg_build.restype = ctypes.c_int
+    lib.vg_free.argtypes = [P]
+    lib.vg_free.restype = None
+    return lib
+
+
+def _take(ptr, n, ctype, dtype):
+    if n == 0:
+        return np.zeros(0, dtype)
+    a = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctype)), shape=(n,))
+    return np.array(a, dtype=dtype, copy=True)
+
+
+def _voronoi_native(seeds: np.ndarray, lo, hi, keep=None, threads: int | None = None) -> dict:
+    """Box-clipped Voronoi cells of the kept seeds by the native helper."""
+    P = np.ascontiguousarray(seeds, np.float64)
+    N = len(P)
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    kp = np.ascontiguousarray(np.ones(N, np.uint8) if keep is None else np.asarray(keep, np.uint8))
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    r = _VGResult()
+    err = ctypes.c_int64(-1)
+    vp = ctypes.c_void_p
+    rc = _vlib().vg_build(N, P.ctypes.data_as(vp), lo.ctypes.data_as(vp), hi.ctypes.data_as(vp),
+                          kp.ctypes.data_as(vp), int(threads), ctypes.byref(r), ctypes.byref(err))
+    if rc != 0:
+        raise RuntimeError(f"native Voronoi construction failed ({rc}) at seed {err.value}")
+    try:
+        NC, NF, NV, NFV = r.n_cells, r.n_faces, r.n_verts, r.n_fv
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        out = dict(
+            cell_face_off=_take(r.cell_face_off, NC + 1, i64, np.int64),
+            cell_face=_take(r.cell_face, int(_take(r.cell_face_off, NC + 1, i64, np.int64)[-1]), i32, np.int32),
+            face_vert_off=_take(r.face_vert_off, NF + 1, i64, np.int64),
+            face_vert=_take(r.face_vert, NFV, i32, np.int32),
+            face_owner=_take(r.face_owner, NF, i32, np.int32),
+            face_neigh=_take(r.face_neigh, NF, i32, np.int32),
+            vert_xyz=_take(r.vert_xyz, 3 * NV, f64, np.float64).reshape(3, NV),
+            face_plane=_take(r.face_plane, 4 * NF, f64, np.float64).reshape(NF, 4),
+            cell_seed=_take(r.cell_seed, NC, i32, np.int64),
+            n_cells=NC, n_faces=NF, n_verts=NV,
+        )
+    finally:
+        _vlib().vg_free(ctypes.byref(r))
+    return out
+
+
+def _native_mesh(seeds, lo, hi, keep, kind, h, extra=None) -> Mesh:
+    o = _voronoi_native(seeds, lo, hi, keep)
+    ex = dict(extra or {})
+    ex["face_plane"] = o["face_plane"]
+    return Mesh(
+        n_cells=o["n_cells"], n_faces=o["n_faces"], n_verts=o["n_verts"],
+        cell_face_off=o["cell_face_off"], cell_face=o["cell_face"], face_vert_off=o["face_vert_off"],
+        face_vert=o["face_vert"], face_owner=o["face_owner"], face_neigh=o["face_neigh"],
+        face_bc=(o["face_neigh"] < 0).astype(np.int8), vert_xyz=np.ascontiguousarray(o["vert_xyz"]),
+        kind=kind, h=h, seeds=np.asarray(seeds)[o["cell_seed"]], extra=ex,
+    )
+
+
 def voronoi_box_mesh(n: int, seed: int, jitter: float = 0.3,
-                     lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Mesh:
-    """Voronoi cells of 2 n^3 jittered BCC seeds, clipped to the box [lo, hi]."""
+                     lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), engine: str = "native") -> Mesh:
+    """Voronoi cells of 2 n^3 jittered BCC seeds, clipped to the box [lo, hi]
+    (engine "native" or "qhull": the same cells, numbered differently)."""
     rng = np.random.default_rng(seed)
     seeds = bcc_seeds(n, rng, jitter, lo, hi)
-    owner, neigh, fo, fv, X, oth = _voronoi_from_seeds(seeds, lo, hi)
     N = len(seeds)
     h = (np.prod(np.asarray(hi) - np.asarray(lo)) / N) ** (1.0 / 3.0)
+    if engine == "native":
+        return _native_mesh(seeds, lo, hi, None, "voronoi", h)
+    owner, neigh, fo, fv, X, oth = _voronoi_from_seeds(seeds, lo, hi)
     return _finish(owner, neigh, fo, fv, X, np.arange(N), "voronoi", h, seeds, other_pt=oth)
 
 
-def voronoi_pipe_mesh(n_radial: int, R: float, L: float, seed: int, jitter: float = 0.3) -> Mesh:
+def voronoi_pipe_mesh(n_radial: int, R: float, L: float, seed: int, jitter: float = 0.3,
+                      engine: str = "native") -> Mesh:
     """Voronoi cells of a pipe r <= R, 0 <= y <= L (axis along y).
 
     BCC seeds fill the bounding box; cells whose seed lies in the pipe are
@@ -425,10 +525,12 @@ def voronoi_pipe_mesh(n_radial: int, R: float, L: float, seed: int, jitter: floa
     seeds = bcc_seeds((n_radial, ny, n_radial), rng, jitter, lo, hi)
     r = np.hypot(seeds[:, 0], seeds[:, 2])
     keep = r <= R
-    owner, neigh, fo, fv, X, oth = _voronoi_from_seeds(seeds, lo, hi, keep=keep)
-    keep_idx = np.nonzero(keep)[0]
     N = len(seeds)
     h = (np.prod(hi - lo) / N) ** (1.0 / 3.0)
+    if engine == "native":
+        return _native_mesh(seeds, lo, hi, keep, "voronoi-pipe", h, extra={"R": R, "L": L})
+    owner, neigh, fo, fv, X, oth = _voronoi_from_seeds(seeds, lo, hi, keep=keep)
+    keep_idx = np.nonzero(keep)[0]
     return _finish(owner, neigh, fo, fv, X, keep_idx, "voronoi-pipe", h, seeds,
                    extra={"R": R, "L": L}, other_pt=oth)
 

@@ -101,3 +101,54 @@ def test_prism_columns_are_closed_outward_polyhedra(n_sides, fan):
     inner = m.face_neigh >= 0
     assert np.all(m.face_neigh[inner] == m.face_owner[inner] + 1)
     assert inner.sum() == (m.n_cells - 1) * (n_sides if fan else 1)
+
+
+def _cell_geometry_by_seed(m):
+    import oracle
+    g = oracle.geometry(m)
+    order = np.lexsort(m.seeds.T[::-1])
+    return g.V[order], g.xc[:, order], np.diff(m.cell_face_off)[order]
+
+
+@pytest.mark.parametrize("n,seed", [(5, 9), (9, 4)])
+def test_native_voronoi_equals_qhull(n, seed):
+    """The native construction (cells clipped by bisectors) and scipy's Qhull
+    (mirror seeds) give the same box-clipped cells: counts, faces per cell,
+    volumes and centroids per seed."""
+    a = meshes.voronoi_box_mesh(n, seed)
+    b = meshes.voronoi_box_mesh(n, seed, engine="qhull")
+    assert (a.n_cells, a.n_faces, a.n_verts) == (b.n_cells, b.n_faces, b.n_verts)
+    Va, xa, fa = _cell_geometry_by_seed(a)
+    Vb, xb, fb = _cell_geometry_by_seed(b)
+    np.testing.assert_array_equal(fa, fb)
+    np.testing.assert_allclose(Va, Vb, rtol=1e-11, atol=0)
+    np.testing.assert_allclose(xa, xb, rtol=0, atol=1e-13)
+    _closed_and_oriented(a)
+
+
+def test_native_pipe_equals_qhull():
+    """The pipe (kept seeds r <= R, dropped neighbours give boundary faces)."""
+    a = meshes.voronoi_pipe_mesh(8, 1.0, 52.0 / 9.5, 4)
+    b = meshes.voronoi_pipe_mesh(8, 1.0, 52.0 / 9.5, 4, engine="qhull")
+    assert (a.n_cells, a.n_faces, a.n_verts) == (b.n_cells, b.n_faces, b.n_verts)
+    assert np.sum(a.face_neigh < 0) == np.sum(b.face_neigh < 0)
+    Va, xa, fa = _cell_geometry_by_seed(a)
+    Vb, xb, fb = _cell_geometry_by_seed(b)
+    np.testing.assert_array_equal(fa, fb)
+    np.testing.assert_allclose(Va, Vb, rtol=1e-11, atol=0)
+    np.testing.assert_allclose(xa, xb, rtol=0, atol=1e-13)
+    _closed_and_oriented(a)
+
+
+def test_native_face_planes_hold_their_vertices():
+    """Every face's half-space n.x <= c (owner side) passes through the face's
+    vertices, and the owner's seed lies inside it."""
+    m = meshes.voronoi_pipe_mesh(6, 1.0, 52.0 / 9.5, 5)
+    fp = m.extra["face_plane"]
+    fid = np.repeat(np.arange(m.n_faces), np.diff(m.face_vert_off))
+    X = m.vert_xyz[:, m.face_vert].T
+    nrm = np.linalg.norm(fp[:, :3], axis=1)
+    res = (np.einsum("ij,ij->i", X, fp[fid, :3]) - fp[fid, 3]) / nrm[fid]
+    assert np.abs(res).max() < 1e-12
+    own = m.seeds[m.face_owner]
+    assert np.all(np.einsum("ij,ij->i", own, fp[:, :3]) < fp[:, 3])
