@@ -8,9 +8,10 @@
  *      vertices; the cell is cut by the iso-polygons of that vertex field
  *      (edge intersections by linear interpolation, Eq. edge_intersection,
  *      assembled through the faces into closed polygons, Sec. 2.1); the
- *      isovalue is bisected until the liquid volume equals alpha V_P; the
- *      result is the interface normal n (vapour -> liquid), area A_int and
- *      centre-to-interface distance d;
+ *      paper cuts at a fixed threshold, this library searches the isovalue
+ *      until the liquid volume equals alpha V_P (its volume-matched reading
+ *      of Sec. 2.1); the result is the interface normal n (vapour -> liquid),
+ *      area A_int and centre-to-interface distance d;
  *   3. the interface-modified least-squares temperature gradient (Sec. 2.4.4,
  *      Eq. front_interpolation, App. B): across a face crossed by the
  *      interface the neighbour is replaced by the alpha-interpolated crossing
@@ -58,7 +59,7 @@ typedef int vofpc_status;
 #define VOFPC_CELL_NOT_MIXED 1        /* alpha <= eps or >= 1-eps: no interface */
 #define VOFPC_CELL_LEARNED_FALLBACK 2 /* the narrowed bracket failed its check */
 #define VOFPC_CELL_DEGENERATE 3       /* constant vertex field: linear alpha used */
-#define VOFPC_CELL_MAX_ITER 4         /* bisection stopped at max_iter */
+#define VOFPC_CELL_MAX_ITER 4         /* the isovalue search stopped at max_iter evaluations */
 #define VOFPC_CELL_G_SINGULAR 5       /* least-squares matrix singular: grad = 0 */
 #define VOFPC_CELL_BAD_INPUT 6        /* alpha NaN or outside [0,1] */
 #define VOFPC_CELL_NO_ROOT 7          /* liquid volume jumps across alpha V_P */
@@ -134,13 +135,29 @@ vofpc_status vofpc_mesh_info(vofpc_mesh mesh, int64_t info[8]);
 /* Kernel classes of the mesh's cells (HOST outputs, any may be NULL): cells[c]
  * = number of cells whose size (vertices, faces, loop positions, edges) fits
  * class c = 0 (<= 16, 8, 48, 24), 1 (<= 48, 32, 128, 64), 2 (<= 64, 64, 256,
- * 128) or 3 (larger); tune[c] = occupancy flavour (3 or 4 waves per SIMD) the
- * reconstruction uses for class c; *bucketed = 1 when the cells spread over
+ * 128) or 3 (larger); tune[c] = the reconstruction kernel flavour used for
+ * class c (see vofpc_mesh_set_tune); *bucketed = 1 when the cells spread over
  * several classes (each with >= 1 % of the cells): then the reconstruction
  * splits the mixed entries by class and launches each class's kernel on its
  * own entries (face-count buckets), else one kernel sized for the largest
  * cell runs. */
 vofpc_status vofpc_mesh_classes(vofpc_mesh mesh, int64_t cells[4], int32_t tune[4], int32_t *bucketed);
+/* Reconstruction kernel flavours (tile shapes) per class:
+ *   3, 4   one cell per wavefront (64 lanes over its loop positions), with
+ *          the register budget of 3 or 4 waves per SIMD; every class;
+ *   10+G   a group of G lanes per cell (the lanes share the cell's edges and
+ *          faces), 64/G cells per wavefront: G = 1, 2, 4 for class 0 when
+ *          its cells are at most hexahedra (8 vertices, 6 faces), else
+ *          G = 2, 4; G = 4, 8, 16 for class 1.
+ * The learned form runs the network inside the reconstruction for every
+ * flavour.  Results of all flavours agree within the parity tolerances. */
+#define VOFPC_FLAVOUR_WAVE3 3
+#define VOFPC_FLAVOUR_WAVE4 4
+#define VOFPC_FLAVOUR_GROUP(G) (10 + (G))
+/* Set the flavour of every class (HOST tune[4]); classes without cells
+ * accept any value.  VOFPC_E_INVALID_ARG (nothing changed) when a class with
+ * cells is given a flavour that has no build for it. */
+vofpc_status vofpc_mesh_set_tune(vofpc_mesh mesh, const int32_t tune[4]);
 /* Copy the computed geometry into caller DEVICE buffers (any may be NULL):
  * V[n_cells], xc[3][n_cells], Sf[3][n_faces], xf[3][n_faces]. */
 vofpc_status vofpc_mesh_geometry(vofpc_mesh mesh, double *V, double *xc, double *Sf, double *xf);
@@ -148,7 +165,10 @@ vofpc_status vofpc_mesh_geometry(vofpc_mesh mesh, double *V, double *xc, double 
 /* ------------------------------------------------------------- compaction */
 /* Mixed-cell list M (cells with eps_mixed < alpha < 1-eps_mixed, ascending)
  * and band list B (cells that are mixed or own a face with
- * (alpha_P - 1/2)(alpha_Q - 1/2) < 0, ascending).  alpha: DEVICE [n_cells].
+ * (alpha_P - 1/2)(alpha_Q - 1/2) < 0, ascending): the crossing test of the
+ * interface-modified gradient (Sec. 2.4.4) marks the cells whose gradient
+ * changes, and with the mixed cells it gives the one-to-two-cell band where
+ * the latent source lives (Eq. latent_source).  alpha: DEVICE [n_cells].
  * mixed_idx and band_idx: DEVICE int32 [n_cells] (capacity n_cells);
  * counts: DEVICE int32 [2] receives |M| and |B|.  No host readback. */
 vofpc_status vofpc_compact(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, double eps_mixed,
@@ -189,10 +209,12 @@ typedef struct {
   int64_t cap;
 } vofpc_interface;
 
-/* Reconstruct the interface in every listed mixed cell (Sec. 2.3: the
- * isovalue of the vertex field is iterated until the cut liquid volume
- * matches alpha V_P; Eq. edge_intersection for the cut points, divergence
- * theorem for the volume).  alpha: DEVICE [n_cells]; mixed_idx/counts from
+/* Reconstruct the interface in every listed mixed cell.  The cut is the
+ * paper's iso-surface of a vertex field (Sec. 2.1: edge intersections by
+ * Eq. edge_intersection, assembled through the faces into iso-polygons);
+ * the paper takes a fixed threshold, while this library moves the isovalue
+ * until the cut liquid volume (divergence theorem) matches alpha V_P, its
+ * volume-matched reading of Sec. 2.1.  alpha: DEVICE [n_cells]; mixed_idx/counts from
  * vofpc_compact.
  * The isovalue search keeps a bracket [lo, hi] of [phi_min, phi_max] with
  * V(lo) > alpha V_P > V(hi) and stops at the first isovalue whose residual
@@ -223,15 +245,16 @@ vofpc_status vofpc_reconstruct_learned(vofpc_ctx ctx, vofpc_mesh mesh, const dou
                                        const vofpc_recon_opts *opts, vofpc_mlp mlp, double delta_scale,
                                        double *hint_lo, double *hint_hi, const vofpc_interface *out);
 
-/* Autotune the reconstruction of a mesh: for each class that has two kernel
- * flavours (classes 0 and 1: register budgets for 3 or 4 waves per SIMD),
- * time both on the mixed cells of `alpha` (DEVICE [n_cells]; opts may be
- * NULL) and keep the faster in the mesh.  cache_path (optional, a text file):
- * a line for the same device, CU count, mesh sizes and class counts is used
- * without timing (*from_cache = 1); otherwise the choice is appended.
- * choice: optional HOST int32[4] receiving the flavour per class.  Allocates
- * trial buffers and synchronises the context stream (a set-up call, not for
- * capture). */
+/* Autotune the reconstruction of a mesh: for each class with cells and more
+ * than one flavour (see vofpc_mesh_set_tune: lanes per cell and register
+ * budget), time every flavour on the mixed cells of `alpha` (DEVICE
+ * [n_cells]; opts may be NULL) and keep the fastest in the mesh.
+ * cache_path (optional, a text file): a line for the same device, CU count,
+ * mesh sizes, class counts and options is used without timing
+ * (*from_cache = 1); otherwise the choice is appended.  choice: optional
+ * HOST int32[4] receiving the flavour per class.  On error the mesh keeps
+ * the flavours it had.  Allocates trial buffers and synchronises the context
+ * stream (a set-up call, not for capture). */
 vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const vofpc_recon_opts *opts,
                             const char *cache_path, int32_t *choice, int32_t *from_cache);
 

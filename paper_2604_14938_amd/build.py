@@ -24,7 +24,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
 ]
-SOURCES = ["api.hip", "mesh.hip", "compact.hip", "recon.hip", "grad.hip", "mlp.hip", "extrap.hip", "robin.hip", "csf.hip"]
+SOURCES = ["api.hip", "mesh.hip", "compact.hip", "recon.hip", "recon_thin.hip", "grad.hip", "mlp.hip", "extrap.hip", "robin.hip", "csf.hip"]
 
 
 def _compile(src: str, obj: str) -> None:

@@ -1,8 +1,11 @@
 // Mixed-cell and gradient-band compaction: a face pass for the band test
 // (meshes with cells of at most eight faces test it in the cell pass), a
-// cell pass with wavefront ballots and block totals, and a scatter whose
-// blocks sum the totals before them, giving stable (ascending) index lists
-// and their lengths in device memory.
+// cell pass with wavefront ballots and block totals, the exclusive prefix of
+// the block totals, and a scatter, giving stable (ascending) index lists and
+// their lengths in device memory.  Up to kScanBlocks blocks each scatter
+// block sums the totals before it itself (no extra launch); beyond that a
+// one-block scan kernel computes the prefix once, so the work stays linear
+// in the number of blocks.
 #include <hip/hip_runtime.h>
 
 #include "vofpc_internal.h"
@@ -12,6 +15,8 @@ namespace vofpc {
 
 constexpr int kCompactBlock = kCompactBlockCells;
 constexpr int kWaves = kCompactBlock / 64;
+constexpr int64_t kScanBlocks = 4096;   // above this many blocks the prefix is scanned once
+constexpr int kScanThreads = 1024;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -99,30 +104,81 @@ __global__ __launch_bounds__(kCompactBlock) void compact_cells_kernel(DevMesh m,
   }
 }
 
-// Scatter the cell ids into both lists in ascending order.  Each block sums
-// the totals of the blocks before it (a few hundred words from L2); the last
-// block also writes the list lengths.
+// Exclusive prefix of both rows of block totals, in place, by one block:
+// each thread sums a contiguous chunk, the chunk sums are scanned (within
+// each wavefront by shuffles, then across the wavefronts), then every thread
+// rewrites its chunk.  Writes the list lengths.
+__global__ __launch_bounds__(kScanThreads) void compact_scan_kernel(int32_t *blk_cnt, int64_t n_blk,
+                                                                    int32_t *counts) {
+  constexpr int kW = kScanThreads / 64;
+  __shared__ int32_t wtot[2][kW];
+  const int t = threadIdx.x, w = t >> 6, l = lane_id();
+  const int64_t chunk = (n_blk + kScanThreads - 1) / kScanThreads;
+  const int64_t i0 = t * chunk < n_blk ? t * chunk : n_blk, i1 = (i0 + chunk < n_blk) ? i0 + chunk : n_blk;
+  int32_t ex[2];
+  for (int r = 0; r < 2; ++r) {
+    int32_t s = 0;
+    for (int64_t i = i0; i < i1; ++i) s += blk_cnt[r * n_blk + i];
+    int32_t inc = s;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t u = __shfl_up(inc, d);
+      if (l >= d) inc += u;
+    }
+    ex[r] = inc - s;
+    if (l == 63) wtot[r][w] = inc;
+  }
+  __syncthreads();
+  for (int r = 0; r < 2; ++r) {
+    int32_t base = 0, all = 0;
+    for (int i = 0; i < kW; ++i) {
+      base += (i < w) ? wtot[r][i] : 0;
+      all += wtot[r][i];
+    }
+    ex[r] += base;
+    if (t == 0) counts[r] = all;
+  }
+  for (int r = 0; r < 2; ++r) {
+    int32_t run = ex[r];
+    for (int64_t i = i0; i < i1; ++i) {
+      const int32_t v = blk_cnt[r * n_blk + i];
+      blk_cnt[r * n_blk + i] = run;
+      run += v;
+    }
+  }
+}
+
+// Scatter the cell ids into both lists in ascending order.  With `scanned`
+// the block totals already hold their exclusive prefix; otherwise each block
+// sums the totals of the blocks before it and the last block writes the list
+// lengths.
 __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t n_cells, const uint8_t *flags,
                                                                         const int32_t *blk_cnt, int64_t n_blk,
-                                                                        int32_t *mixed_idx, int32_t *band_idx,
-                                                                        int32_t *counts) {
+                                                                        int scanned, int32_t *mixed_idx,
+                                                                        int32_t *band_idx, int32_t *counts) {
   __shared__ int32_t wbase[2][kWaves];
   __shared__ int32_t part[2][kWaves];
   const int64_t b = blockIdx.x;
-  // exclusive prefix of the block totals
-  int32_t s0 = 0, s1 = 0;
-  for (int64_t i = threadIdx.x; i < b; i += kCompactBlock) {
-    s0 += blk_cnt[i];
-    s1 += blk_cnt[n_blk + i];
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    s0 += __shfl_xor(s0, o);
-    s1 += __shfl_xor(s1, o);
-  }
   const int w = threadIdx.x >> 6, l = lane_id();
-  if (l == 0) {
-    part[0][w] = s0;
-    part[1][w] = s1;
+  if (scanned) {
+    if (threadIdx.x < 2) {
+      part[threadIdx.x][0] = blk_cnt[threadIdx.x * n_blk + b];
+      for (int i = 1; i < kWaves; ++i) part[threadIdx.x][i] = 0;
+    }
+  } else {
+    // exclusive prefix of the block totals
+    int32_t s0 = 0, s1 = 0;
+    for (int64_t i = threadIdx.x; i < b; i += kCompactBlock) {
+      s0 += blk_cnt[i];
+      s1 += blk_cnt[n_blk + i];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o);
+      s1 += __shfl_xor(s1, o);
+    }
+    if (l == 0) {
+      part[0][w] = s0;
+      part[1][w] = s1;
+    }
   }
   const int64_t P = b * kCompactBlock + threadIdx.x;
   uint8_t f = (P < n_cells) ? flags[P] : 0;
@@ -141,7 +197,7 @@ __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t 
       wbase[threadIdx.x][i] = run;
       run += t;
     }
-    if (b == n_blk - 1) counts[threadIdx.x] = run;
+    if (!scanned && b == n_blk - 1) counts[threadIdx.x] = run;
   }
   __syncthreads();
   if (mixed) mixed_idx[wbase[0][w] + lanes_below(bm)] = (int32_t)P;
@@ -162,8 +218,10 @@ vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, do
     compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->cross, M->flags, M->blk_cnt,
                                                                  nb);
   }
-  compact_scatter_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, M->flags, M->blk_cnt, nb, mixed, band,
-                                                                  counts);
+  const int scanned = nb > kScanBlocks ? 1 : 0;
+  if (scanned) compact_scan_kernel<<<1, kScanThreads, 0, s>>>(M->blk_cnt, nb, counts);
+  compact_scatter_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, M->flags, M->blk_cnt, nb, scanned,
+                                                                  mixed, band, counts);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;
 }

@@ -228,12 +228,13 @@ vofpc_status mesh_vertex_stencil(vofpc_mesh M) {
 // Kernel classes of a mesh: the class of its largest cell, and whether its
 // cells spread over several classes (each holding at least 1 % of the cells),
 // in which case the reconstruction buckets its mixed entries by class.
-static vofpc_status setup_classes(vofpc_mesh M, const int64_t *class_cnt) {
+static vofpc_status setup_classes(vofpc_mesh M, const int64_t *class_cnt, const int64_t (*cmax)[4]) {
   const int64_t N = M->d.n_cells;
   int big = 0;
   M->max_class = 0;
   for (int c = 0; c < kClasses; ++c) {
     M->class_cells[c] = class_cnt[c];
+    for (int t = 0; t < 4; ++t) M->class_max[c][t] = cmax[c][t];
     M->tune[c] = 3;
     if (class_cnt[c] > 0) M->max_class = c;
     if (class_cnt[c] > 0 && class_cnt[c] * 100 >= N) ++big;
@@ -297,6 +298,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   std::vector<int32_t> cv_gid;
   std::vector<uint8_t> cl_lv;
   std::vector<uint16_t> cl_eid;            // local undirected edge id per loop position
+  std::vector<uint32_t> ce;                // per local edge: u, v, face running u -> v, the other face
   std::vector<uint32_t> cl_info;           // face (bits 0-7), index in face (8-15), next position (16-31)
   std::vector<int32_t> edge_stamp(65536, -1), edge_id(65536, 0);
   std::vector<int32_t> cf_nbr(ncf);
@@ -306,6 +308,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   cl_lv.reserve(nfv * 2);
   int64_t max_nf = 0, max_nv = 0, max_fv = 0, max_ne = 0, max_loop = 0;
   int64_t class_cnt[kClasses] = {0, 0, 0, 0};
+  int64_t class_max[kClasses][4] = {};
   std::vector<int32_t> loc;
   std::vector<uint16_t> dedge;
   for (int64_t P = 0; P < N; ++P) {
@@ -360,9 +363,13 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
         for (int64_t k = 0; k < n; ++k) {
           int a = cl_lv[o + k], b = cl_lv[o + (k + 1 == n ? 0 : k + 1)];
           int key = a < b ? (a << 8 | b) : (b << 8 | a);
+          const uint32_t fl = (uint32_t)(i - cfo[P]);
           if (edge_stamp[key] != (int32_t)P) {
             edge_stamp[key] = (int32_t)P;
             edge_id[key] = ne++;
+            ce.push_back((uint32_t)a | (uint32_t)b << 8 | fl << 16);
+          } else {
+            ce[ce.size() - ne + edge_id[key]] |= fl << 24;   // the second face runs b -> a
           }
           cl_eid.push_back((uint16_t)edge_id[key]);
         }
@@ -375,8 +382,13 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
     max_nv = std::max<int64_t>(max_nv, (int64_t)loc.size());
     max_ne = std::max<int64_t>(max_ne, (int64_t)dedge.size() / 2);
     max_loop = std::max<int64_t>(max_loop, cl_off[P + 1] - cl_off[P]);
-    class_cnt[class_of((int64_t)loc.size(), cfo[P + 1] - cfo[P], cl_off[P + 1] - cl_off[P],
-                       (int64_t)dedge.size() / 2)]++;
+    {
+      const int64_t sz[4] = {(int64_t)loc.size(), cfo[P + 1] - cfo[P], cl_off[P + 1] - cl_off[P],
+                             (int64_t)dedge.size() / 2};
+      const int c = class_of(sz[0], sz[1], sz[2], sz[3]);
+      class_cnt[c]++;
+      for (int t = 0; t < 4; ++t) class_max[c][t] = std::max(class_max[c][t], sz[t]);
+    }
   }
   // vertex -> cell incidence (cells ascending)
   std::vector<int64_t> vc_off(NV + 1, 0);
@@ -422,6 +434,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   COPY(cl_lv, cl_lv.data(), cl_lv.size(), uint8_t);
   COPY(cl_eid, cl_eid.data(), cl_eid.size(), uint16_t);
   COPY(cl_info, cl_info.data(), cl_info.size(), uint32_t);
+  COPY(ce, ce.data(), ce.size(), uint32_t);
   COPY(vc_off, vc_off.data(), NV + 1, int64_t);
   COPY(vc_cell, vc_cell.data(), vc_cell.size(), int32_t);
   COPY(vc_w, (const double *)nullptr, vc_cell.size(), double);
@@ -457,7 +470,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   M->max_nf = max_nf; M->max_nv = max_nv; M->max_fv = max_fv; M->max_ne = max_ne; M->max_loop = max_loop;
   M->ncf = ncf; M->nfv = nfv; M->ncv = (int64_t)cv_gid.size(); M->ncl = (int64_t)cl_lv.size();
   M->nvc = (int64_t)vc_cell.size();
-  if ((st = setup_classes(M, class_cnt))) {
+  if ((st = setup_classes(M, class_cnt, class_max))) {
     vofpc_mesh_free(M);
     return st;
   }
@@ -568,6 +581,7 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
   ALLOC(cl_lv, ncl, uint8_t);
   ALLOC(cl_eid, ncl, uint16_t);
   ALLOC(cl_info, ncl, uint32_t);
+  ALLOC(ce, ncl / 2, uint32_t);
   ALLOC(vc_off, NV + 1, int64_t);
   ALLOC(vc_cell, nvc, int32_t);
   ALLOC(vc_w, nvc, double);
@@ -599,12 +613,16 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
   M->ncf = ncf; M->nfv = nfv; M->ncv = ncv; M->ncl = ncl; M->nvc = nvc;
   {
     int64_t cc[kClasses] = {0, 0, 0, 0};
+    int64_t cm[kClasses][4] = {};
     M->min_centre_dist = ms[0]->min_centre_dist;
     for (int i = 0; i < n; ++i) {
-      for (int c = 0; c < kClasses; ++c) cc[c] += ms[i]->class_cells[c];
+      for (int c = 0; c < kClasses; ++c) {
+        cc[c] += ms[i]->class_cells[c];
+        for (int t = 0; t < 4; ++t) cm[c][t] = std::max(cm[c][t], ms[i]->class_max[c][t]);
+      }
       M->min_centre_dist = std::min(M->min_centre_dist, ms[i]->min_centre_dist);
     }
-    if ((st = setup_classes(M, cc))) {
+    if ((st = setup_classes(M, cc, cm))) {
       vofpc_mesh_free(M);
       return st;
     }
@@ -641,6 +659,7 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
     CC((uint8_t *)m.cl_lv + bcl, a.cl_lv, A.ncl, 0, 0);
     CC((uint16_t *)m.cl_eid + bcl, a.cl_eid, A.ncl, 0, 0);
     CC((uint32_t *)m.cl_info + bcl, a.cl_info, A.ncl, 0, 0);
+    CC((uint32_t *)m.ce + bcl / 2, a.ce, A.ncl / 2, 0, 0);
     CC((double *)m.vc_w + bvc, a.vc_w, A.nvc, 0, 0);
     CC((double *)m.vc_wmean + bvc, a.vc_wmean, A.nvc, 0, 0);
     CC((double *)m.V + bN, a.V, n_, 0, 0);

@@ -46,14 +46,6 @@ __device__ __forceinline__ bf16x4 b_weightT(const uint16_t *W, int ldk, int lane
   return v;
 }
 
-// A operand holding one input row (row 0 of the tile) from a BF16 vector in
-// LDS (8-byte aligned); the other fifteen rows are zero
-__device__ __forceinline__ bf16x4 a_row0(const uint16_t *x, int lane, int k0) {
-  bf16x4 v = {0, 0, 0, 0};
-  if ((lane & 15) == 0) v = *reinterpret_cast<const bf16x4 *>(x + k0 + 4 * (lane >> 4));
-  return v;
-}
-
 // v[l & ~Z] + v[l | Z] on every lane l (Z = 16 or 32) by the gfx950 lane
 // swaps: the same two operands, in the same order, on both partners
 template <int Z>

@@ -1,7 +1,7 @@
 // Volume-matched iso-polygon reconstruction of the mixed cells.
 //
-// One cell per group of W lanes (W divides 64; a block is one wavefront, so a
-// block holds 64/W cells).  The cell's polyhedron is staged in LDS: vertex
+// One cell per wavefront (a block is one wavefront of 64 lanes).  The cell's
+// polyhedron is staged in LDS: vertex
 // positions relative to the centroid, the vertex field, the outward face
 // loops as local vertex ids with a local edge id and the reciprocal of the
 // vertex-value difference for every loop position.
@@ -30,10 +30,13 @@
 // their edges and redoes the chord and loop sums.  Two such records are kept,
 // so a bracket closing in on a breakpoint from both sides stays on the short
 // path.  It evaluates the same volume function (same construction, fewer
-// operations) at the same bisection points.
+// operations) at the same isovalues.
 //
-// The isovalue is bisected until |V/V_P - alpha| <= tol_rel min(alpha,1-alpha);
-// when the bracket collapses first, the end nearer to alpha V_P is kept.
+// The isovalue search keeps a bracket [lo, hi] with V(lo) > alpha V_P > V(hi)
+// and picks its isovalues by regula falsi (Illinois weight) and inverse
+// quadratic interpolation, with a bisection step after a slow update, until
+// |V/V_P - alpha| <= tol_rel min(alpha,1-alpha); when the bracket collapses
+// first, the end nearer to alpha V_P is kept.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,19 +44,11 @@
 #include <cstring>
 #include <string>
 
-#include "vofpc_internal.h"
+#include "recon_common.h"
 #include "mlp_core.h"
-#include "wave_ops.h"
 
 namespace vofpc {
 
-// Order LDS traffic between the lanes of one wavefront (no hardware barrier:
-// the groups of a wave run independent loops).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // exclusive prefix sum over the group
 template <int W>
@@ -67,10 +62,6 @@ __device__ __forceinline__ int gscan_excl(int v, int lane) {
   return inc - v;
 }
 
-__device__ __forceinline__ double det3(double a0, double a1, double a2, double b0, double b1, double b2, double c0,
-                                       double c1, double c2) {
-  return a0 * (b1 * c2 - b2 * c1) + a1 * (b2 * c0 - b0 * c2) + a2 * (b0 * c1 - b1 * c0);
-}
 
 // Chord data of a fixed topology, one chord per lane (see the file comment),
 // valid for isovalues in (bp_lo, bp_hi].
@@ -124,36 +115,7 @@ struct GroupMem {
   alignas(16) uint16_t nh2[net::kHid];
 };
 
-struct CutRes {
-  double V, S0, S1, S2, A, c0, c1, c2;
-  int nch;
-  bool err;
-};
 
-struct ReconParams {
-  DevMesh m;
-  const double *alpha;
-  const int32_t *mixed;
-  const int32_t *counts;
-  const double *phi_override;
-  const double *hint_lo, *hint_hi;
-  double eps, tol_rel, iso;
-  int max_iter, vertex_mode, fixed_iso, use_hint;
-  int *queue;   // claim counter of the cells beyond the first grid-size ones
-  // optional entry list of this launch (a face-count bucket): entries[j] for
-  // j < *entry_count instead of every mixed entry
-  const int32_t *entries;
-  const int32_t *entry_count;
-  // bracket network run inside the kernel (null: none): BF16 weights, FP32
-  // parameters, half-width factor, optional outputs of the bracket
-  const uint16_t *net_wb;
-  const float *net_master;
-  double net_delta;
-  double *net_lo, *net_hi;
-  // mass transfer written with the interface (null gradT: not fused)
-  MdotFuse mf;
-  vofpc_interface out;
-};
 
 __device__ __forceinline__ int next_bit_after(uint64_t mask, int q) {
   uint64_t hi = (q >= 63) ? 0ull : (mask & (~0ull << (q + 1)));
@@ -548,21 +510,6 @@ __device__ CutRes cut_fast(const FastSlot<kSlotChords> &F, int c, double s) {
   return R;
 }
 
-// Spacing of the doubles above |x|: the bit patterns of non-negative
-// doubles are ordered as their values, so the next double up is the pattern
-// plus one (+inf gives NaN, as nextafter(inf, inf) - inf does).
-__device__ __forceinline__ double ulp_of(double x) {
-  const double a = fabs(x);
-  return __longlong_as_double(__double_as_longlong(a) + 1) - a;
-}
-
-// The next double toward +inf (nextafter(x, +inf) for every x).
-__device__ __forceinline__ double next_up(double x) {
-  if (x == 0.0) return __longlong_as_double(1ll);   // either zero: the smallest subnormal
-  if (!(x < __builtin_inf())) return x;              // +inf and NaN stay
-  const long long b = __double_as_longlong(x);
-  return __longlong_as_double(x > 0.0 ? b + 1 : b - 1);
-}
 
 // The topology of a cut (which vertices are liquid, how faces with four or
 // more crossings pair them) is constant for isovalues between consecutive
@@ -619,12 +566,6 @@ __device__ __forceinline__ bool fast_round(const GroupMem<kSlotChords, NV, NF, N
   return seg < npts && c == 0;
 }
 
-// Root of the inverse quadratic through three (isovalue, residual) points;
-// NaN or infinite when two residuals coincide.
-__device__ __forceinline__ double iqi(double x0, double f0, double x1, double f1, double x2, double f2) {
-  return x0 * f1 * f2 / ((f0 - f1) * (f0 - f2)) + x1 * f0 * f2 / ((f1 - f0) * (f1 - f2)) +
-         x2 * f0 * f1 / ((f2 - f0) * (f2 - f1));
-}
 
 template <class GM>
 __device__ __forceinline__ void store_end(GM &L, int lane, int side, const CutRes &c) {
@@ -634,31 +575,10 @@ __device__ __forceinline__ void store_end(GM &L, int lane, int side, const CutRe
   }
 }
 
+
 // The bracket network's normalised isovalue for the staged cell: its 32
 // inputs from the staged vertex values and the cell's faces, then the
-// forward pass on MFMA.
-// A face of the cell as the bracket network sees it: the area vector
-// oriented out of the cell and the neighbour's volume fraction.
-struct NetFace {
-  double S0, S1, S2, aQ;
-  bool inner;
-};
-
-__device__ __forceinline__ NetFace load_net_face(const ReconParams &p, int P, double aP, int64_t slot) {
-  const DevMesh &m = p.m;
-  const int64_t NFg = m.n_faces;
-  const int fid = m.cell_face[slot];
-  const int q = m.cf_nbr[slot];
-  const double sg = (m.face_owner[fid] == P) ? 1.0 : -1.0;
-  NetFace r;
-  r.S0 = sg * m.Sf[fid];
-  r.S1 = sg * m.Sf[NFg + fid];
-  r.S2 = sg * m.Sf[2 * NFg + fid];
-  r.inner = q >= 0;
-  r.aQ = r.inner ? p.alpha[q] : aP;
-  return r;
-}
-
+// forward pass of one row, one hidden unit per lane with FP32 FMAs.
 template <int NF, class GM>
 __device__ float net_guess(GM &L, int lane, const ReconParams &p, int64_t k, int P, double aP, int nv, int nf,
                            int64_t f0, double pmin, double Wd, const NetFace &pf) {
@@ -928,7 +848,7 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
           int lru = 0, probe = -1;
           // learned bracket: its centre is the first isovalue tried; the
           // status records whether the root fell outside it
-          bool hint = false, first = true;
+          bool hint = false;
           double hl = 0, hh = 0;
           if (p.net_wb && st == VOFPC_CELL_OK) {
             const double Wd = pmax - pmin;
@@ -949,6 +869,11 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
               p.net_lo[k] = __builtin_nan("");
               p.net_hi[k] = __builtin_nan("");
             }
+          } else if (p.net_wb) {
+            if (lane == 0 && p.net_lo) {   // no network bracket for this cell
+              p.net_lo[k] = __builtin_nan("");
+              p.net_hi[k] = __builtin_nan("");
+            }
           } else if (p.use_hint) {
             hl = p.hint_lo[k];
             hh = p.hint_hi[k];
@@ -958,7 +883,31 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
               hint = hl <= hh;
             }
           }
-          while (true) {
+          if (hint) {
+            // check the narrowed bracket with a cut at each end: it is kept
+            // when the ends straddle the root; otherwise the root lies beyond
+            // the end that failed (LEARNED_FALLBACK)
+            const CutRes cl = full_step(L, lane, nv, nf, nl, hl, lru);
+            const CutRes ch = full_step(L, lane, nv, nf, nl, hh, lru);
+            it += 2;
+            const double rl = cl.V / VP - a, rh = ch.V / VP - a;
+            if (fabs(rl) <= tol) {
+              s = hl; c = cl; cut_ok = true;
+            } else if (fabs(rh) <= tol) {
+              s = hh; c = ch; cut_ok = true;
+            } else if (rl > 0 && rh < 0) {
+              lo = hl; rlo = rl; have_lo = true; store_end(L, lane, 0, cl);
+              hi = hh; rhi = rh; have_hi = true; store_end(L, lane, 1, ch);
+            } else if (rl <= 0) {
+              hi = hl; rhi = rl; have_hi = true; store_end(L, lane, 1, cl);
+              if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+            } else {
+              lo = hh; rlo = rh; have_lo = true; store_end(L, lane, 0, ch);
+              if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+            }
+            wave_sync();
+          }
+          while (!cut_ok) {
             const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
             if (hi - lo <= 2.0 * ulp_of(big)) { collapsed = true; break; }
             if (it >= p.max_iter) { st = VOFPC_CELL_MAX_ITER; break; }
@@ -976,12 +925,10 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
                 se = q;
               }
             }
-            if (first && hint) se = 0.5 * (hl + hh);
             if (slow || !(se > lo && se < hi)) {
               se = lo + w0 / 2.0;
               d = 0.125 * w0;
             }
-            first = false;
             if (!(se > lo && se < hi)) { collapsed = true; break; }
             const double du = 8.0 * ulp_of(se);
             d = d > du ? d : du;
@@ -1141,7 +1088,6 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
             cut_ok = true;
             if (collapsed && fabs(take_lo ? rlo : rhi) > 1e-10) st = VOFPC_CELL_NO_ROOT;
           }
-          if (hint && cut_ok && st == VOFPC_CELL_OK && !(s >= hl && s <= hh)) st = VOFPC_CELL_LEARNED_FALLBACK;
         }
         if (cut_ok && c.err) {
           st = VOFPC_CELL_BAD_INPUT;
@@ -1238,9 +1184,12 @@ vofpc_status launch_t(vofpc_ctx ctx, const ReconParams &p, int64_t n_cells) {
   return VOFPC_OK;
 }
 
-// Launch the variant of class c in flavour `occ` (waves per SIMD the
-// register budget is sized for; the two common classes have two flavours).
-vofpc_status launch_class(vofpc_ctx ctx, const ReconParams &p, int64_t n_cells, int c, int occ) {
+// Launch the variant of class c in flavour `flav`: 3 or 4 = one cell per
+// wavefront with the register budget of that many waves per SIMD (the two
+// common classes have both), 10 + G = G lanes per cell (recon_thin.hip).
+vofpc_status launch_class(vofpc_ctx ctx, vofpc_mesh M, const ReconParams &p, int64_t n_cells, int c, int flav) {
+  if (flav >= 10) return launch_thin(ctx, p, n_cells, c, flav - 10, M->class_max[c]);
+  const int occ = flav == 4 ? 4 : 3;
   switch (c) {
     case 0:
       return occ == 4 ? launch_t<16, 8, 48, 24, 4>(ctx, p, n_cells) : launch_t<16, 8, 48, 24, 3>(ctx, p, n_cells);
@@ -1304,7 +1253,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   const int64_t N = M->d.n_cells;
   p.entries = nullptr;
   p.entry_count = nullptr;
-  if (!M->bucketed) return launch_class(ctx, p, N, M->max_class, M->tune[M->max_class]);
+  if (!M->bucketed) return launch_class(ctx, M, p, N, M->max_class, M->tune[M->max_class]);
   // one launch per class present in the mesh, each over its own entries
   bucket_zero_kernel<<<1, 64, 0, ctx->stream>>>(M->bucket_counts);
   const int64_t span = std::min<int64_t>(out->cap, N);
@@ -1315,7 +1264,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
     if (M->class_cells[c] == 0) continue;
     p.entries = M->bucket_lists + (int64_t)c * N;
     p.entry_count = M->bucket_counts + c;
-    vofpc_status st = launch_class(ctx, p, M->class_cells[c], c, M->tune[c]);
+    vofpc_status st = launch_class(ctx, M, p, M->class_cells[c], c, M->tune[c]);
     if (st) return st;
   }
   return VOFPC_OK;
@@ -1333,21 +1282,52 @@ struct TuneBuffers {
   }
 };
 
-std::string tune_key(vofpc_ctx ctx, vofpc_mesh M) {
+// Whether class c of mesh M has a build of flavour f.
+bool flavour_ok(vofpc_mesh M, int c, int f) {
+  if (f == VOFPC_FLAVOUR_WAVE3) return true;
+  if (f == VOFPC_FLAVOUR_WAVE4) return c <= 1;
+  if (f >= 10 && f <= 26) return thin_available(c, f - 10, M->class_max[c]);
+  return false;
+}
+
+// The flavours the tuner tries for class c.
+int candidates(vofpc_mesh M, int c, int out[8]) {
+  int n = 0;
+  const int all[] = {VOFPC_FLAVOUR_WAVE3, VOFPC_FLAVOUR_WAVE4, 11, 12, 14, 18, 26};
+  for (int f : all)
+    if (flavour_ok(M, c, f)) out[n++] = f;
+  return n;
+}
+
+std::string tune_key(vofpc_ctx ctx, vofpc_mesh M, const vofpc_recon_opts &o) {
   hipDeviceProp_t prop;
   std::string arch = "gpu";
   if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
   for (char &ch : arch)
     if (ch == ' ' || ch == ':') ch = '_';
-  char buf[256];
-  snprintf(buf, sizeof buf, "%s cu%d n%lld f%lld v%lld c%lld,%lld,%lld,%lld", arch.c_str(), ctx->n_cu,
-           (long long)M->d.n_cells, (long long)M->d.n_faces, (long long)M->d.n_verts, (long long)M->class_cells[0],
-           (long long)M->class_cells[1], (long long)M->class_cells[2], (long long)M->class_cells[3]);
+  char buf[384];
+  snprintf(buf, sizeof buf, "%s cu%d n%lld f%lld v%lld c%lld,%lld,%lld,%lld o%d,%d,%d,%d,%.3g", arch.c_str(),
+           ctx->n_cu, (long long)M->d.n_cells, (long long)M->d.n_faces, (long long)M->d.n_verts,
+           (long long)M->class_cells[0], (long long)M->class_cells[1], (long long)M->class_cells[2],
+           (long long)M->class_cells[3], o.vertex_mode, o.fixed_iso, o.bracket, o.max_iter, o.tol_rel);
   return buf;
 }
 }  // namespace
 
 }  // namespace vofpc
+
+extern "C" vofpc_status vofpc_mesh_set_tune(vofpc_mesh M, const int32_t tune[4]) {
+  using namespace vofpc;
+  clear_error();
+  VOFPC_REQUIRE(M && tune, VOFPC_E_INVALID_ARG, "mesh_set_tune: null argument");
+  for (int c = 0; c < kClasses; ++c)
+    VOFPC_REQUIRE(M->class_cells[c] == 0 || flavour_ok(M, c, tune[c]), VOFPC_E_INVALID_ARG,
+                  "mesh_set_tune: flavour " + std::to_string(tune[c]) + " has no build for class " +
+                      std::to_string(c));
+  for (int c = 0; c < kClasses; ++c)
+    if (M->class_cells[c] > 0) M->tune[c] = tune[c];
+  return VOFPC_OK;
+}
 
 extern "C" vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, const vofpc_recon_opts *opts,
                                        const char *cache_path, int32_t *choice, int32_t *from_cache) {
@@ -1359,22 +1339,27 @@ extern "C" vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh M, const double
   vofpc_recon_opts o;
   if (opts) o = *opts; else vofpc_recon_opts_default(&o);
   if (from_cache) *from_cache = 0;
-  const std::string key = tune_key(ctx, M);
+  const std::string key = tune_key(ctx, M, o);
   const std::string tag = "vofpc-tune " + key + " :";
   if (cache_path) {
     if (FILE *f = fopen(cache_path, "r")) {
       char line[512];
-      bool hit = false;
+      int hit[kClasses];
+      bool found = false;
       while (fgets(line, sizeof line, f)) {
         if (strncmp(line, tag.c_str(), tag.size()) != 0) continue;
         int t[kClasses];
-        if (sscanf(line + tag.size(), "%d %d %d %d", &t[0], &t[1], &t[2], &t[3]) == kClasses) {
-          for (int c = 0; c < kClasses; ++c) M->tune[c] = (t[c] == 4) ? 4 : 3;
-          hit = true;
-        }
+        if (sscanf(line + tag.size(), "%d %d %d %d", &t[0], &t[1], &t[2], &t[3]) != kClasses) continue;
+        bool ok = true;
+        for (int c = 0; c < kClasses; ++c) ok = ok && (M->class_cells[c] == 0 || flavour_ok(M, c, t[c]));
+        if (!ok) continue;
+        for (int c = 0; c < kClasses; ++c) hit[c] = t[c];
+        found = true;
       }
       fclose(f);
-      if (hit) {
+      if (found) {
+        for (int c = 0; c < kClasses; ++c)
+          if (M->class_cells[c] > 0) M->tune[c] = hit[c];
         if (from_cache) *from_cache = 1;
         if (choice)
           for (int c = 0; c < kClasses; ++c) choice[c] = M->tune[c];
@@ -1384,6 +1369,8 @@ extern "C" vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh M, const double
   }
   // time the flavours on this field (greedy per class, all classes launched)
   const int64_t N = M->d.n_cells;
+  int saved[kClasses];
+  for (int c = 0; c < kClasses; ++c) saved[c] = M->tune[c];
   TuneBuffers b;
   if (hipMalloc(&b.mixed, 4 * N) || hipMalloc(&b.band, 4 * N) || hipMalloc(&b.counts, 8) ||
       hipMalloc(&b.status, 4 * N) || hipMalloc(&b.iters, 4 * N) || hipMalloc(&b.s, 8 * N) ||
@@ -1398,31 +1385,46 @@ extern "C" vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh M, const double
   if (st) return st;
   hipEvent_t e0, e1;
   VOFPC_HIP(hipEventCreate(&e0));
-  VOFPC_HIP(hipEventCreate(&e1));
-  for (int c = 0; c < 2; ++c) {
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("autotune: hipEventCreate failed");
+    return VOFPC_E_HIP;
+  }
+  for (int c = 0; c < kClasses && !st; ++c) {
     if (M->class_cells[c] == 0 || (!M->bucketed && c != M->max_class)) continue;
+    int cand[8];
+    const int nc = candidates(M, c, cand);
+    if (nc < 2) continue;
     float best = 0.f;
-    int best_f = 3;
-    for (int f = 3; f <= 4; ++f) {
-      M->tune[c] = f;
+    int best_f = M->tune[c];
+    for (int i = 0; i < nc && !st; ++i) {
+      M->tune[c] = cand[i];
       st = launch_reconstruct(ctx, M, alpha, b.mixed, b.counts, &o, nullptr, nullptr, &itf);
       if (st) break;
-      (void)hipEventRecord(e0, ctx->stream);
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = VOFPC_E_HIP; set_error("autotune: event record"); break; }
       for (int r = 0; r < 3 && !st; ++r) st = launch_reconstruct(ctx, M, alpha, b.mixed, b.counts, &o, nullptr, nullptr, &itf);
-      (void)hipEventRecord(e1, ctx->stream);
       if (st) break;
-      if (hipEventSynchronize(e1) != hipSuccess) { st = VOFPC_E_HIP; set_error("autotune: event wait failed"); break; }
+      if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = VOFPC_E_HIP;
+        set_error("autotune: event wait failed");
+        break;
+      }
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (f == 3 || ms < best) { best = ms; best_f = f; }
+      if (i == 0 || ms < best) { best = ms; best_f = cand[i]; }
     }
-    if (st) break;
     M->tune[c] = best_f;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st) return st;
-  VOFPC_HIP(hipStreamSynchronize(ctx->stream));
+  if (!st && hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    st = VOFPC_E_HIP;
+    set_error("autotune: stream synchronisation failed");
+  }
+  if (st) {
+    for (int c = 0; c < kClasses; ++c) M->tune[c] = saved[c];
+    return st;
+  }
   if (cache_path) {
     if (FILE *f = fopen(cache_path, "a")) {
       fprintf(f, "%s %d %d %d %d\n", tag.c_str(), M->tune[0], M->tune[1], M->tune[2], M->tune[3]);
@@ -1433,4 +1435,3 @@ extern "C" vofpc_status vofpc_autotune(vofpc_ctx ctx, vofpc_mesh M, const double
     for (int c = 0; c < kClasses; ++c) choice[c] = M->tune[c];
   return VOFPC_OK;
 }
-

@@ -1,0 +1,916 @@
+// Volume-matched iso-polygon reconstruction with a group of G lanes per mixed
+// cell (G = 1 to 16) and 64/G cells per wavefront.
+//
+// The one-cell-per-wavefront kernel (recon.hip) spreads a cell's loop
+// positions over 64 lanes, so most lanes idle on hexahedra and on the search
+// control.  Here a group of G lanes shares a cell's edges and faces, combines
+// its lanes' sums by DPP butterflies, and a wavefront works on 64/G cells at
+// once, staged side by side in LDS (arrays indexed [item][cell slot], so the
+// cells of a wavefront read different banks).
+//
+// One volume evaluation at isovalue s (divergence theorem, each face's
+// liquid polygon fanned from a point of its plane, here its first vertex):
+//   - per edge: the two faces' terms of the whole edge, D_e = det(c1, u, v) +
+//     det(c2, v, u), are fixed per cell; an evaluation adds D_e times the
+//     edge's liquid fraction (1, 0, or for a cut edge the fraction from its
+//     liquid end, which scales both faces' liquid pieces of the edge alike),
+//     and registers a cut edge with the face the iso-curve leaves through it
+//     and the face it enters through it;
+//   - per face: a face with two crossings has one chord, exit -> entry; a
+//     face with four or more pairs each exit with the next entry in loop
+//     order when the face-mean vertex value is >= s, else with the previous
+//     one (the oracle's rule); the chord closes the face's liquid polygon;
+//     crossing points follow Eq. edge_intersection from the liquid end of
+//     the edge, computed once per edge, so both faces get the same point;
+//   - per chord, the terms of its iso-loop: a loop is the chain of chords
+//     (the chord entering through edge e follows the chord leaving through
+//     e), and fanning a loop from its length-weighted polyline centroid k
+//     gives volume k . Y / 6 and area vector -Y / 2 with Y = sum over its
+//     chords of (entry point x exit point), the centroid from sum l and
+//     sum l (entry + exit): chord-local sums, taken about a reference
+//     vertex of the cell.  A single loop (the usual case, found by walking
+//     the chord links once) needs nothing else; several loops are labelled
+//     through LDS and their sums gathered loop by loop in a second pass over
+//     the faces.
+//
+// Search: the same bracket invariant, estimates (regula falsi with the
+// Illinois weight, inverse quadratic interpolation, bisection after a slow
+// update) and stopping rule as the wavefront kernel, one evaluation per
+// step; a narrowed bracket [h_lo, h_hi] is first checked with two
+// evaluations at its ends, kept when they straddle the root and otherwise
+// replaced by the part of the full bracket beyond the failed end (status
+// LEARNED_FALLBACK).
+//
+// Scheduling: a wavefront takes 64/G consecutive mixed entries (a batch),
+// stages them together, runs their searches side by side until the last one
+// stops, writes them out and claims the next batch from a counter that
+// wraps back to zero after the launch's last claim.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "recon_common.h"
+#include "mlp_core.h"
+
+namespace vofpc {
+namespace {
+
+// ---------------------------------------------------------- group reductions
+// Sums, minima and maxima over the G consecutive lanes of a group by DPP quad,
+// half-row and row butterflies; every lane of the group ends with the same
+// bits.
+template <int G>
+__device__ __forceinline__ double tsum(double v) {
+  if constexpr (G >= 2) v += dpp_d<kQuadXor1>(v);
+  if constexpr (G >= 4) v += dpp_d<kQuadXor2>(v);
+  if constexpr (G >= 8) v += dpp_d<kHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_d<kRowMirror>(v);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int tsum_i(int v) {
+  if constexpr (G >= 2) v += dpp_i<kQuadXor1>(v);
+  if constexpr (G >= 4) v += dpp_i<kQuadXor2>(v);
+  if constexpr (G >= 8) v += dpp_i<kHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_i<kRowMirror>(v);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int tmin_i(int v) {
+  if constexpr (G >= 2) v = min(v, dpp_i<kQuadXor1>(v));
+  if constexpr (G >= 4) v = min(v, dpp_i<kQuadXor2>(v));
+  if constexpr (G >= 8) v = min(v, dpp_i<kHalfMirror>(v));
+  if constexpr (G >= 16) v = min(v, dpp_i<kRowMirror>(v));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double tmin(double v) {
+  if constexpr (G >= 2) v = fmin(v, dpp_d<kQuadXor1>(v));
+  if constexpr (G >= 4) v = fmin(v, dpp_d<kQuadXor2>(v));
+  if constexpr (G >= 8) v = fmin(v, dpp_d<kHalfMirror>(v));
+  if constexpr (G >= 16) v = fmin(v, dpp_d<kRowMirror>(v));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double tmax(double v) {
+  if constexpr (G >= 2) v = fmax(v, dpp_d<kQuadXor1>(v));
+  if constexpr (G >= 4) v = fmax(v, dpp_d<kQuadXor2>(v));
+  if constexpr (G >= 8) v = fmax(v, dpp_d<kHalfMirror>(v));
+  if constexpr (G >= 16) v = fmax(v, dpp_d<kRowMirror>(v));
+  return v;
+}
+
+// ------------------------------------------------------------ fast division
+// Quotient a/b from the hardware reciprocal, refined by two Newton steps and
+// one residual correction (within an ulp of the rounded quotient; b finite
+// and nonzero): a few instructions instead of the IEEE division sequence.
+__device__ __forceinline__ double qdiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+// Square root of x >= 0 from the hardware reciprocal square root, refined by
+// two Newton steps and one residual correction (0 for x = 0).
+__device__ __forceinline__ double qsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  const double t = x * y;
+  return x > 0.0 ? fma(fma(-t, t, x), 0.5 * y, t) : 0.0;
+}
+// Root of the inverse quadratic through three (isovalue, residual) points,
+// about x0 over one common denominator; NaN or infinite when two residuals
+// coincide.
+__device__ __forceinline__ double iqi1(double x0, double f0, double x1, double f1, double x2, double f2) {
+  const double d01 = f0 - f1, d02 = f0 - f2, d12 = f1 - f2;
+  return x0 + qdiv((x2 - x0) * f0 * f1 * d01 - (x1 - x0) * f0 * f2 * d02, d01 * d02 * d12);
+}
+
+// ----------------------------------------------------------------- LDS layout
+// The staged cells of one wavefront, item-major and cell-slot-minor; the
+// 4- and 8-byte arrays have an odd slot stride CP, so the lanes of a group,
+// which read different items of one cell, spread over the LDS banks.
+template <int C, int NV, int NF, int NL, int NE>
+struct ThinMem {
+  static constexpr int CP = C | 1;
+  double X[3][NV][CP];  // vertex positions relative to the cell centroid
+  double phi[NV][CP];   // vertex field
+  double D[NE][CP];     // volume term of an edge taken whole by both of its faces
+  double fr[NE][CP];    // liquid fraction of each cut edge (this evaluation)
+  int32_t cnt[NF][CP];  // crossings of each face (this evaluation)
+  uint8_t eu[NE][C], ev[NE][C];    // end vertices of each edge
+  uint8_t ef1[NE][C], ef2[NE][C];  // face whose loop runs eu -> ev, and the other face
+  uint8_t fx[NF][C], fn[NF][C];    // exit and entry edge of a face with two crossings
+  uint8_t lv[NL][C];    // local vertex of each loop position
+  uint8_t eid[NL][C];   // local edge of each loop position
+  uint8_t foff[NF][C];  // first loop position of each face
+  uint8_t fsz[NF][C];   // positions of each face
+  uint8_t link[NE][C];  // exit edge of the chord entering through edge e (0xff: e not cut)
+  uint8_t lab[NE][C];   // loop of each cut edge (evaluations with several loops)
+};
+
+// per-lane sums of the chords of one loop (or of all loops)
+struct ChordAcc {
+  double L, M0, M1, M2, Y0, Y1, Y2;
+};
+
+template <int G>
+__device__ __forceinline__ void reduce_acc(ChordAcc &a) {
+  a.L = tsum<G>(a.L);
+  a.M0 = tsum<G>(a.M0); a.M1 = tsum<G>(a.M1); a.M2 = tsum<G>(a.M2);
+  a.Y0 = tsum<G>(a.Y0); a.Y1 = tsum<G>(a.Y1); a.Y2 = tsum<G>(a.Y2);
+}
+
+// Crossing point of cut edge e at isovalue s: Eq. edge_intersection from
+// the edge's liquid end, with the liquid fraction of this evaluation, so
+// both faces of the edge get the same point.
+template <class TM>
+__device__ __forceinline__ void edge_point(const TM &M, int sl, int e, double s, double &p0, double &p1, double &p2) {
+  const int u = M.eu[e][sl], v = M.ev[e][sl];
+  const bool ul = M.phi[u][sl] >= s;
+  const int i = ul ? u : v, j = ul ? v : u;
+  const double lam = M.fr[e][sl];
+  p0 = M.X[0][i][sl] + lam * (M.X[0][j][sl] - M.X[0][i][sl]);
+  p1 = M.X[1][i][sl] + lam * (M.X[1][j][sl] - M.X[1][i][sl]);
+  p2 = M.X[2][i][sl] + lam * (M.X[2][j][sl] - M.X[2][i][sl]);
+}
+
+// One chord from exit point x to entry point e (edges ex, en) of a face with
+// fan point c.  mode 0: the face volume term, the link and the chord sums;
+// mode 1: only the sums, and only when the chord lies on loop `loop`.
+template <class TM>
+__device__ __forceinline__ void add_chord(TM &M, int sl, int mode, int loop, const double *r, double c0, double c1,
+                                          double c2, double x0, double x1, double x2, double e0, double e1, double e2,
+                                          int ex, int en, double &vf, ChordAcc &acc, int &nch, int &estart) {
+  if (mode == 0) {
+    vf += det3(c0, c1, c2, x0, x1, x2, e0, e1, e2);
+    M.link[en][sl] = (uint8_t)ex;
+    estart = en < estart ? en : estart;
+    ++nch;
+  } else if (M.lab[en][sl] != loop) {
+    return;
+  }
+  // the chord as a loop segment, from its entry point u to its exit point w,
+  // both relative to the cell's reference point r (near a small cut piece,
+  // so the cross products of a small loop do not cancel)
+  const double u0 = e0 - r[0], u1 = e1 - r[1], u2 = e2 - r[2];
+  const double w0 = x0 - r[0], w1 = x1 - r[1], w2 = x2 - r[2];
+  const double d0 = w0 - u0, d1 = w1 - u1, d2 = w2 - u2;
+  const double l = qsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  acc.L += l;
+  acc.M0 += l * (u0 + w0);
+  acc.M1 += l * (u1 + w1);
+  acc.M2 += l * (u2 + w2);
+  acc.Y0 += u1 * w2 - u2 * w1;
+  acc.Y1 += u2 * w0 - u0 * w2;
+  acc.Y2 += u0 * w1 - u1 * w0;
+}
+
+// The chords of face f at isovalue s (see add_chord for mode): one chord,
+// exit -> entry, for a face with two crossings; with four or more, each exit
+// pairs with the next entry in loop order when the face-mean vertex value is
+// >= s, else with the previous one.  The fan point is the face's first
+// vertex.
+template <class TM>
+__device__ void chords_of_face(TM &M, int sl, int f, double s, int mode, int loop, const double *r, double &vf,
+                               ChordAcc &acc, int &nch, int &estart, bool &err) {
+  const int c = M.cnt[f][sl];
+  if (c == 0) return;
+  const int o = M.foff[f][sl];
+  const int a0 = M.lv[o][sl];
+  const double c0 = M.X[0][a0][sl], c1 = M.X[1][a0][sl], c2 = M.X[2][a0][sl];
+  if (c == 2) {
+    const int ex = M.fx[f][sl], en = M.fn[f][sl];
+    double x0, x1, x2, e0, e1, e2;
+    edge_point(M, sl, ex, s, x0, x1, x2);
+    edge_point(M, sl, en, s, e0, e1, e2);
+    add_chord(M, sl, mode, loop, r, c0, c1, c2, x0, x1, x2, e0, e1, e2, ex, en, vf, acc, nch, estart);
+    return;
+  }
+  if (c & 1) {
+    err = true;   // a closed loop alternates exits and entries
+    return;
+  }
+  const int n = M.fsz[f][sl];
+  double fm = 0.0;
+  for (int k = 0; k < n; ++k) fm += M.phi[M.lv[o + k][sl]][sl];
+  const bool conn = fm / (double)n >= s;
+  for (int k = 0; k < n; ++k) {
+    const int u = M.lv[o + k][sl], v = M.lv[o + ((k + 1 == n) ? 0 : k + 1)][sl];
+    if (!(M.phi[u][sl] >= s) || M.phi[v][sl] >= s) continue;   // not an exit
+    int rr = k;
+    bool found = false;
+    for (int t = 0; t < n && !found; ++t) {
+      rr = conn ? ((rr + 1 == n) ? 0 : rr + 1) : ((rr == 0) ? n - 1 : rr - 1);
+      const int ru = M.lv[o + rr][sl], rv = M.lv[o + ((rr + 1 == n) ? 0 : rr + 1)][sl];
+      found = !(M.phi[ru][sl] >= s) && M.phi[rv][sl] >= s;
+    }
+    if (!found) {
+      err = true;
+      continue;
+    }
+    const int ex = M.eid[o + k][sl], en = M.eid[o + rr][sl];
+    double x0, x1, x2, e0, e1, e2;
+    edge_point(M, sl, ex, s, x0, x1, x2);
+    edge_point(M, sl, en, s, e0, e1, e2);
+    add_chord(M, sl, mode, loop, r, c0, c1, c2, x0, x1, x2, e0, e1, e2, ex, en, vf, acc, nch, estart);
+  }
+}
+
+// Add one loop's fan: centroid k = r + M/(2L) from the length sums (relative
+// to r), volume k . Y, area vector -Y/2.
+__device__ __forceinline__ void finish_loop(const ChordAcc &a, const double *r, double &Vi, double &S0, double &S1,
+                                            double &S2, double &A, double &cw0, double &cw1, double &cw2) {
+  double k0 = r[0], k1 = r[1], k2 = r[2];   // a loop of zero length has zero area: its centre does not matter
+  if (a.L > 0) {
+    const double h = qdiv(0.5, a.L);
+    k0 += a.M0 * h; k1 += a.M1 * h; k2 += a.M2 * h;
+  }
+  Vi += k0 * a.Y0 + k1 * a.Y1 + k2 * a.Y2;
+  const double t0 = -0.5 * a.Y0, t1 = -0.5 * a.Y1, t2 = -0.5 * a.Y2;
+  const double Ak = qsqrt(t0 * t0 + t1 * t1 + t2 * t2);
+  S0 += t0; S1 += t1; S2 += t2;
+  A += Ak;
+  cw0 += Ak * k0; cw1 += Ak * k1; cw2 += Ak * k2;
+}
+
+// One volume evaluation of the cell in slot sl at isovalue s by its group.
+template <int G, class TM>
+__device__ CutRes thin_eval(TM &M, int sl, int q, int nf, int ne, double s, const double *r) {
+  for (int e = q; e < ne; e += G) M.link[e][sl] = 0xff;
+  for (int f = q; f < nf; f += G) M.cnt[f][sl] = 0;
+  wave_sync();
+  // edges: the liquid parts of the faces (an edge's term times its liquid
+  // fraction: 1, 0, or, for a cut edge, the fraction from its liquid end,
+  // which scales both faces' pieces alike), and each crossing registered
+  // with the face the iso-curve leaves through it and the one it enters
+  double vf = 0.0;
+  for (int e = q; e < ne; e += G) {
+    const int u = M.eu[e][sl], v = M.ev[e][sl];
+    const double pu = M.phi[u][sl], pv = M.phi[v][sl];
+    const bool lu = pu >= s, lw = pv >= s;
+    if (lu && lw) {
+      vf += M.D[e][sl];
+    } else if (lu != lw) {
+      const double pi = lu ? pu : pv, pj = lu ? pv : pu;
+      const double lam = qdiv(s - pi, pj - pi);
+      M.fr[e][sl] = lam;
+      vf += lam * M.D[e][sl];
+      const int f1 = M.ef1[e][sl], f2 = M.ef2[e][sl];
+      const int fo = lu ? f1 : f2, fi = lu ? f2 : f1;   // face f1 runs u -> v
+      M.fx[fo][sl] = (uint8_t)e;
+      M.fn[fi][sl] = (uint8_t)e;
+      atomicAdd(&M.cnt[fo][sl], 1);
+      atomicAdd(&M.cnt[fi][sl], 1);
+    }
+  }
+  wave_sync();
+  ChordAcc acc{0, 0, 0, 0, 0, 0, 0};
+  int nch = 0, estart = 0xff;
+  bool err = false;
+  for (int f = q; f < nf; f += G) chords_of_face(M, sl, f, s, 0, 0, r, vf, acc, nch, estart, err);
+  vf = tsum<G>(vf);
+  reduce_acc<G>(acc);
+  nch = tsum_i<G>(nch);
+  estart = tmin_i<G>(estart);
+  int bad = tsum_i<G>(err ? 1 : 0);
+  wave_sync();
+  double Vi = 0, S0 = 0, S1 = 0, S2 = 0, A = 0, cw0 = 0, cw1 = 0, cw2 = 0;
+  if (nch > 0 && bad == 0) {
+    // follow the chord links once from one cut edge: a single loop returns
+    // after nch chords
+    int e = estart, len = 0;
+    do {
+      e = M.link[e][sl];
+      ++len;
+    } while (e != estart && e != 0xff && len <= nch);
+    if (e == 0xff) {
+      bad = 1;
+    } else if (e == estart && len == nch) {
+      finish_loop(acc, r, Vi, S0, S1, S2, A, cw0, cw1, cw2);
+    } else {
+      // several loops: label the cut edges, then gather each loop's chords
+      for (int t = 0; t < ne; ++t) M.lab[t][sl] = 0xff;
+      int nloop = 0;
+      for (int t = 0; t < ne && bad == 0; ++t) {
+        if (M.link[t][sl] == 0xff || M.lab[t][sl] != 0xff) continue;
+        int u = t, steps = 0;
+        do {
+          M.lab[u][sl] = (uint8_t)nloop;
+          u = M.link[u][sl];
+          ++steps;
+        } while (u != t && u != 0xff && steps <= nch);
+        if (u != t) bad = 1;
+        ++nloop;
+      }
+      wave_sync();
+      for (int lp = 0; lp < nloop && bad == 0; ++lp) {
+        ChordAcc la{0, 0, 0, 0, 0, 0, 0};
+        double dv = 0.0;
+        int dn = 0, ds = 0;
+        bool derr = false;
+        for (int f = q; f < nf; f += G) chords_of_face(M, sl, f, s, 1, lp, r, dv, la, dn, ds, derr);
+        reduce_acc<G>(la);
+        finish_loop(la, r, Vi, S0, S1, S2, A, cw0, cw1, cw2);
+      }
+    }
+  }
+  wave_sync();
+  CutRes R;
+  R.err = bad != 0;
+  R.nch = nch;
+  R.V = (vf + Vi) * (1.0 / 6.0);
+  R.S0 = S0; R.S1 = S1; R.S2 = S2;
+  R.A = A;
+  if (A > 0) {
+    const double ia = qdiv(1.0, A);
+    R.c0 = cw0 * ia; R.c1 = cw1 * ia; R.c2 = cw2 * ia;
+  } else {
+    R.c0 = R.c1 = R.c2 = 0.0;
+  }
+  return R;
+}
+
+
+// Network scratch of a wavefront (learned form): one BF16 input row per cell
+// slot (16 rows at least: a tile), one 16-row tile of hidden activations and
+// the first output per slot.
+template <int C>
+struct ThinNet {
+  static constexpr int R = C < 16 ? 16 : C;
+  alignas(16) uint16_t x[R][net::kIn];
+  alignas(16) uint16_t h[16][net::kHid];
+  float u[R];
+};
+struct ThinNoNet {
+  int unused;
+};
+
+// Forward pass of the wavefront's rows on v_mfma_f32_16x16x16_bf16 tiles, all
+// 64 lanes, 16 rows per tile (BF16 weights and activations, FP32
+// accumulation, tanh hidden layers); u[r] = output 0 of row r.  Lane l holds
+// A[l%16][4(l/16)+j], B[4(l/16)+j][l%16] and D[4(l/16)+j][l%16].
+template <int C>
+__device__ void net_tiles(ThinNet<C> &T, const uint16_t *wb, const float *master, int lane) {
+  using namespace net;
+  const int col = lane & 15, rq = 4 * (lane >> 4);
+  for (int t0 = 0; t0 < ThinNet<C>::R; t0 += 16) {
+    for (int nt = 0; nt < kHid / 16; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int kt = 0; kt < kIn / 16; ++kt)
+        acc = mfma16(*reinterpret_cast<const bf16x4 *>(&T.x[t0 + col][kt * 16 + rq]),
+                     b_weightT(wb + oW1, kIn, lane, nt * 16, kt * 16, kHid), acc);
+      const float b = master[oB1 + nt * 16 + col];
+      for (int j = 0; j < 4; ++j) T.h[rq + j][nt * 16 + col] = to_bf16(tanhf(acc[j] + b));
+    }
+    wave_sync();
+    f32x4 acc2[kHid / 16];
+    for (int nt = 0; nt < kHid / 16; ++nt) {
+      acc2[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int kt = 0; kt < kHid / 16; ++kt)
+        acc2[nt] = mfma16(*reinterpret_cast<const bf16x4 *>(&T.h[col][kt * 16 + rq]),
+                          b_weightT(wb + oW2, kHid, lane, nt * 16, kt * 16, kHid), acc2[nt]);
+    }
+    wave_sync();
+    for (int nt = 0; nt < kHid / 16; ++nt) {
+      const float b = master[oB2 + nt * 16 + col];
+      for (int j = 0; j < 4; ++j) T.h[rq + j][nt * 16 + col] = to_bf16(tanhf(acc2[nt][j] + b));
+    }
+    wave_sync();
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kt = 0; kt < kHid / 16; ++kt)
+      acc = mfma16(*reinterpret_cast<const bf16x4 *>(&T.h[col][kt * 16 + rq]),
+                   b_weightT(wb + oW3, kHid, lane, 0, kt * 16, kOut), acc);
+    if (col == 0) {
+      const float b = master[oB3];
+      for (int j = 0; j < 4; ++j) T.u[t0 + rq + j] = acc[j] + b;
+    }
+    wave_sync();
+  }
+}
+
+// The 32 network inputs of the cell in slot sl (the definitions of the
+// features entry point) into its BF16 row: face sums over the group's faces,
+// the vertex values ordered by rank (ties by index) through M.link.
+template <int G, class TM, int C>
+__device__ void cell_features(TM &M, ThinNet<C> &T, int sl, int q, const ReconParams &p, int P, double a, int nv,
+                              int nf, int64_t f0, double pmin, double Wd) {
+  double t[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) t[i] = 0.0;
+  double amin = __builtin_inf(), amax = -__builtin_inf();
+  for (int f = q; f < nf; f += G) {
+    const NetFace g = load_net_face(p, P, a, f0 + f);
+    const double A = sqrt(g.S0 * g.S0 + g.S1 * g.S1 + g.S2 * g.S2);
+    const double n0 = g.S0 / A, n1 = g.S1 / A, n2 = g.S2 / A;
+    const double da = A * (g.aQ - a);
+    const double o[6] = {n0 * n0, n1 * n1, n2 * n2, n0 * n1, n0 * n2, n1 * n2};
+    t[0] += A;
+    t[1] += da * n0; t[2] += da * n1; t[3] += da * n2;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      t[4 + c] += da * o[c];
+      t[10 + c] += A * o[c];
+    }
+    if (g.inner) {
+      t[16] += g.aQ;
+      t[17] += 1.0;
+      amin = fmin(amin, g.aQ);
+      amax = fmax(amax, g.aQ);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 18; ++i) t[i] = tsum<G>(t[i]);
+  amin = tmin<G>(amin);
+  amax = tmax<G>(amax);
+  double lsum = 0.0;
+  for (int i = q; i < nv; i += G) {
+    const double v = M.phi[i][sl];
+    int r = 0;
+    for (int jv = 0; jv < nv; ++jv) {
+      const double u = M.phi[jv][sl];
+      r += (u < v) || (u == v && jv < i);
+    }
+    M.link[r][sl] = (uint8_t)i;
+    lsum += v;
+  }
+  lsum = tsum<G>(lsum);
+  wave_sync();
+  auto sorted = [&](int r) { return M.phi[M.link[r][sl]][sl]; };
+  for (int i = q; i < net::kIn; i += G)
+    T.x[sl][i] = net::to_bf16(net::feature(i, a, sorted, nv, lsum, pmin, Wd, t, amin, amax, nf));
+}
+
+template <int G, int NV, int NF, int NL, int NE, bool NET>
+using NetMem = typename std::conditional<NET, ThinNet<64 / G>, ThinNoNet>::type;
+
+// Waves per SIMD a build's register budget is sized for: what its LDS
+// allows, at most 3 (about 168 VGPRs, the size of the search state and one
+// face walk without spills; a 4-wave budget of 128 VGPRs spills).
+constexpr int thin_occupancy(int bytes) {
+  return (160 * 1024) / bytes >= 12 ? 3 : ((160 * 1024) / bytes >= 4 ? (160 * 1024) / bytes / 4 : 1);
+}
+
+template <int G, int NV, int NF, int NL, int NE, bool NET>
+__global__ __launch_bounds__(64, (thin_occupancy((int)(sizeof(ThinMem<64 / G, NV, NF, NL, NE>) +
+                                                       (NET ? sizeof(ThinNet<64 / G>) : 0)))))
+void recon_thin_kernel(ReconParams p) {
+  constexpr int C = 64 / G;
+  __shared__ ThinMem<C, NV, NF, NL, NE> M;
+  __shared__ NetMem<G, NV, NF, NL, NE, NET> T;
+  const int lane = threadIdx.x, sl = lane / G, q = lane % G;
+  const DevMesh &m = p.m;
+  const int64_t N = m.n_cells;
+  const int64_t cap = p.out.cap;
+  int64_t count = p.entries ? (int64_t)*p.entry_count : (int64_t)p.counts[0];
+  if (count > cap) count = cap;
+  const int64_t nbatch = (count + C - 1) / C;
+  if constexpr (NET) {
+    // rows of a tile beyond the wavefront's cells stay zero
+    for (int i = lane; i < (ThinNet<C>::R - C) * net::kIn; i += 64) T.x[C + i / net::kIn][i % net::kIn] = 0;
+  }
+  for (int64_t bt = blockIdx.x; bt < nbatch;) {
+    const int64_t j = bt * C + sl;
+    const bool active = j < count;
+    // ---- phase 1, per cell: checks and staging
+    int64_t k = 0, f0 = 0;
+    int P = 0, nf = 0, nv = 0, nl = 0, ne = 0, st = VOFPC_CELL_OK, it = 0;
+    double a = 0.0, VP = 1.0, pmin = 0.0, pmax = 0.0;
+    bool have_field = false;
+    double s_out = __builtin_nan(""), A_out = 0, d_out = 0, n0 = 0, n1 = 0, n2 = 0, ag = 0.0;
+    if (active) {
+      k = p.entries ? (int64_t)p.entries[j] : j;
+      P = p.mixed[k];
+      a = p.alpha[P];
+      ag = a;
+      f0 = m.cell_face_off[P];
+      nf = (int)(m.cell_face_off[P + 1] - f0);
+      const int64_t v0 = m.cv_off[P];
+      nv = (int)(m.cv_off[P + 1] - v0);
+      const int64_t l0 = m.cl_off[P];
+      nl = (int)(m.cl_off[P + 1] - l0);
+      ne = nl / 2;   // a closed surface uses every edge twice
+      if (!(a >= 0.0 && a <= 1.0)) {
+        st = VOFPC_CELL_BAD_INPUT;
+      } else if (!(a > p.eps && a < 1.0 - p.eps)) {
+        st = VOFPC_CELL_NOT_MIXED;
+      } else if (nv > NV || nf > NF || nl > NL || ne > NE) {
+        st = VOFPC_CELL_BAD_INPUT;   // cannot happen: the launcher sizes the build by the class
+      } else {
+        const double xP0 = m.xc[P], xP1 = m.xc[N + P], xP2 = m.xc[2 * N + P];
+        VP = m.V[P];
+        // ---- stage the polyhedron: vertices (inverse-distance vertex field,
+        // incidences read four at a time and summed in order), loop positions
+        // and face offsets
+        double lo_phi = __builtin_inf(), hi_phi = -__builtin_inf();
+        for (int i = q; i < nv; i += G) {
+          const int gv = m.cv_gid[v0 + i];
+          M.X[0][i][sl] = m.xyz[gv] - xP0;
+          M.X[1][i][sl] = m.xyz[m.n_verts + gv] - xP1;
+          M.X[2][i][sl] = m.xyz[2 * m.n_verts + gv] - xP2;
+          double ph;
+          if (p.phi_override) {
+            ph = p.phi_override[gv];
+          } else {
+            const double *w = p.vertex_mode ? m.vc_wmean : m.vc_w;
+            ph = 0.0;
+            const int64_t j1 = m.vc_off[gv + 1];
+            for (int64_t jj = m.vc_off[gv]; jj < j1; jj += 4) {
+              int cc[4];
+              double ww[4], aa[4];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                const bool in = jj + t < j1;
+                cc[t] = in ? m.vc_cell[jj + t] : 0;
+                ww[t] = in ? w[jj + t] : 0.0;
+              }
+#pragma unroll
+              for (int t = 0; t < 4; ++t) aa[t] = (jj + t < j1) ? p.alpha[cc[t]] : 0.0;
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                if (jj + t < j1) ph += ww[t] * aa[t];
+            }
+          }
+          M.phi[i][sl] = ph;
+          lo_phi = fmin(lo_phi, ph);
+          hi_phi = fmax(hi_phi, ph);
+        }
+        for (int i = q; i < nl; i += G) {
+          M.lv[i][sl] = m.cl_lv[l0 + i];
+          M.eid[i][sl] = (uint8_t)m.cl_eid[l0 + i];
+        }
+        for (int f = q; f < nf; f += G) {
+          M.foff[f][sl] = (uint8_t)m.cf_loff[f0 + f];
+          M.fsz[f][sl] = m.cf_lsz[f0 + f];
+        }
+        for (int e = q; e < ne; e += G) {
+          const uint32_t w = m.ce[(l0 >> 1) + e];
+          M.eu[e][sl] = (uint8_t)(w & 0xffu);
+          M.ev[e][sl] = (uint8_t)((w >> 8) & 0xffu);
+          M.ef1[e][sl] = (uint8_t)((w >> 16) & 0xffu);
+          M.ef2[e][sl] = (uint8_t)(w >> 24);
+        }
+        wave_sync();
+        // the whole-edge volume term of each edge: its two faces' fan terms,
+        // det(c1, u, v) + det(c2, v, u) with c = the face's first vertex
+        for (int e = q; e < ne; e += G) {
+          const int u = M.eu[e][sl], v = M.ev[e][sl];
+          const int a1 = M.lv[M.foff[M.ef1[e][sl]][sl]][sl], a2 = M.lv[M.foff[M.ef2[e][sl]][sl]][sl];
+          const double d0 = M.X[0][a1][sl] - M.X[0][a2][sl], d1 = M.X[1][a1][sl] - M.X[1][a2][sl],
+                       d2 = M.X[2][a1][sl] - M.X[2][a2][sl];
+          M.D[e][sl] = det3(d0, d1, d2, M.X[0][u][sl], M.X[1][u][sl], M.X[2][u][sl], M.X[0][v][sl], M.X[1][v][sl],
+                            M.X[2][v][sl]);
+        }
+        pmin = tmin<G>(lo_phi);
+        pmax = tmax<G>(hi_phi);
+        have_field = true;
+        wave_sync();
+        if (pmax - pmin <= 1e-12) {
+          // degenerate vertex field: linear alpha from the plain least-squares
+          // gradient over the interior face neighbours
+          st = VOFPC_CELL_DEGENERATE;
+          double gxx = 0, gyy = 0, gzz = 0, gxy = 0, gxz = 0, gyz = 0, b0 = 0, b1 = 0, b2 = 0;
+          for (int f = q; f < nf; f += G) {
+            const int qq = m.cf_nbr[f0 + f];
+            if (qq < 0) continue;
+            const double r0 = m.xc[qq] - xP0, r1 = m.xc[N + qq] - xP1, r2 = m.xc[2 * N + qq] - xP2;
+            const double dv = p.alpha[qq] - a;
+            gxx += r0 * r0; gyy += r1 * r1; gzz += r2 * r2; gxy += r0 * r1; gxz += r0 * r2; gyz += r1 * r2;
+            b0 += r0 * dv; b1 += r1 * dv; b2 += r2 * dv;
+          }
+          gxx = tsum<G>(gxx); gyy = tsum<G>(gyy); gzz = tsum<G>(gzz);
+          gxy = tsum<G>(gxy); gxz = tsum<G>(gxz); gyz = tsum<G>(gyz);
+          b0 = tsum<G>(b0); b1 = tsum<G>(b1); b2 = tsum<G>(b2);
+          const double c00 = gyy * gzz - gyz * gyz, c01 = gxz * gyz - gxy * gzz, c02 = gxy * gyz - gxz * gyy;
+          const double c11 = gxx * gzz - gxz * gxz, c12 = gxy * gxz - gxx * gyz, c22 = gxx * gyy - gxy * gxy;
+          const double det = gxx * c00 + gxy * c01 + gxz * c02;
+          const double tr = (gxx + gyy + gzz) / 3.0;
+          double g0 = 0, g1 = 0, g2 = 0;
+          if (det > 1e-12 * tr * tr * tr) {
+            g0 = (c00 * b0 + c01 * b1 + c02 * b2) / det;
+            g1 = (c01 * b0 + c11 * b1 + c12 * b2) / det;
+            g2 = (c02 * b0 + c12 * b1 + c22 * b2) / det;
+          }
+          lo_phi = __builtin_inf();
+          hi_phi = -__builtin_inf();
+          for (int i = q; i < nv; i += G) {
+            const double ph = a + (g0 * M.X[0][i][sl] + g1 * M.X[1][i][sl] + g2 * M.X[2][i][sl]);
+            M.phi[i][sl] = ph;
+            lo_phi = fmin(lo_phi, ph);
+            hi_phi = fmax(hi_phi, ph);
+          }
+          pmin = tmin<G>(lo_phi);
+          pmax = tmax<G>(hi_phi);
+          if (pmax - pmin <= 1e-12) have_field = false;
+          wave_sync();
+        }
+      }
+    }
+    // ---- phase 2: the narrowed bracket of every cell with a vertex field,
+    // from the network (run on the wavefront's cells together) or the caller
+    double hl = 0.0, hh = 0.0;
+    bool hint = false;
+    if constexpr (NET) {
+      const bool row = active && have_field && st == VOFPC_CELL_OK;   // degenerate fields skip the network
+      if (row) {
+        cell_features<G>(M, T, sl, q, p, P, a, nv, nf, f0, pmin, pmax - pmin);
+      } else {
+        for (int i = q; i < net::kIn; i += G) T.x[sl][i] = 0;
+      }
+      wave_sync();
+      net_tiles<C>(T, p.net_wb, p.net_master, lane);
+      if (row) {
+        const float u = T.u[sl];
+        if (!isnan(u)) {
+          const double Wd = pmax - pmin;
+          const double uc = u < 0.f ? 0.0 : (u > 1.f ? 1.0 : (double)u);
+          const double sh = pmin + uc * Wd, dl = p.net_delta * Wd;
+          hl = sh - dl;
+          hh = sh + dl;
+          if (q == 0 && p.net_lo) {
+            p.net_lo[k] = hl;
+            p.net_hi[k] = hh;
+          }
+          hl = hl > pmin ? hl : pmin;
+          hh = hh < pmax ? hh : pmax;
+          if (hl > hh) { hl = pmin; hh = pmax; }
+          hint = true;
+        } else if (q == 0 && p.net_lo) {
+          p.net_lo[k] = __builtin_nan("");
+          p.net_hi[k] = __builtin_nan("");
+        }
+      } else if (active && q == 0 && p.net_lo) {
+        p.net_lo[k] = __builtin_nan("");
+        p.net_hi[k] = __builtin_nan("");
+      }
+      wave_sync();
+    } else {
+      if (active && have_field && p.use_hint) {
+        hl = p.hint_lo[k];
+        hh = p.hint_hi[k];
+        if (!isnan(hl) && !isnan(hh)) {
+          hl = hl > pmin ? hl : pmin;
+          hh = hh < pmax ? hh : pmax;
+          if (hl > hh) { hl = pmin; hh = pmax; }
+          hint = true;
+        }
+      }
+    }
+    // ---- phase 3, per cell: the search and the outputs
+    if (active) {
+        if (have_field) {
+          // reference point of the loop sums: the vertex of largest value when
+          // the cell is mostly vapour (a small liquid piece sits at it), else
+          // the vertex of smallest value (the smallest index among ties)
+          double ref[3];
+          {
+            const bool top = a < 0.5;
+            const double want = top ? pmax : pmin;
+            int cand = 0x7fffffff;
+            for (int i = q; i < nv; i += G)
+              if (M.phi[i][sl] == want && i < cand) cand = i;
+            cand = tmin_i<G>(cand);
+            ref[0] = M.X[0][cand][sl];
+            ref[1] = M.X[1][cand][sl];
+            ref[2] = M.X[2][cand][sl];
+          }
+          // One evaluation site; the phase decides where the next one is:
+          // the fixed isovalue, the two ends of a narrowed bracket, the search
+          // estimate, or the bracket end kept when the search cannot stop.
+          enum { kFixed, kHintLo, kHintHi, kSearch, kFinal };
+          CutRes c;
+          c.err = false;
+          double s = __builtin_nan("");
+          double lo = pmin, hi = pmax, rlo = 1.0 - a, rhi = -a, rl = 0.0;
+          const double iVP = 1.0 / VP;
+          const double tol = p.tol_rel * (a < 1.0 - a ? a : 1.0 - a);
+          double s3 = 0, r3 = 0;   // third point for inverse quadratic interpolation
+          bool have3 = false, collapsed = false, take_lo = false;
+          int kept = 0;            // > 0: lo kept that many updates in a row, < 0: hi
+          bool slow = false;       // the last update did not halve the bracket
+          int ph = p.fixed_iso ? kFixed : (hint ? kHintLo : kSearch);
+          while (true) {
+            double se = 0.0;
+            if (ph == kSearch) {
+              const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
+              if (hi - lo <= 2.0 * ulp_of(big)) {
+                collapsed = true;
+                ph = kFinal;
+              } else if (it >= p.max_iter) {
+                st = VOFPC_CELL_MAX_ITER;
+                ph = kFinal;
+              } else {
+                const double w0 = hi - lo;
+                const double fl = kept >= 2 ? 0.5 * rlo : rlo, fh = kept <= -2 ? 0.5 * rhi : rhi;
+                se = lo + w0 * qdiv(fl, fl - fh);
+                if (have3 && kept > -2 && kept < 2) {
+                  const double qv = iqi1(lo, rlo, hi, rhi, s3, r3);
+                  if (qv > lo && qv < hi) se = qv;
+                }
+                if (slow || !(se > lo && se < hi)) se = lo + w0 / 2.0;
+                if (!(se > lo && se < hi)) {
+                  collapsed = true;
+                  ph = kFinal;
+                }
+              }
+            }
+            if (ph == kFinal) {
+              take_lo = fabs(rlo) <= fabs(rhi);
+              se = take_lo ? lo : hi;
+            } else if (ph == kFixed) {
+              se = p.iso;
+            } else if (ph == kHintLo) {
+              se = hl;
+            } else if (ph == kHintHi) {
+              se = hh;
+            }
+            const CutRes cf = thin_eval<G>(M, sl, q, nf, ne, se, ref);
+            ++it;
+            const double r = cf.V * iVP - a;
+            if (ph == kFixed || ph == kFinal || fabs(r) <= tol) {
+              s = se;
+              c = cf;
+              if (ph == kFinal && collapsed && fabs(take_lo ? rlo : rhi) > 1e-10) st = VOFPC_CELL_NO_ROOT;
+              break;
+            }
+            if (ph == kHintLo) {
+              rl = r;
+              ph = kHintHi;
+              continue;
+            }
+            if (ph == kHintHi) {
+              // the narrowed bracket holds when its ends straddle the root;
+              // otherwise the root lies beyond the end that failed
+              if (rl > 0 && r < 0) {
+                lo = hl; rlo = rl; hi = hh; rhi = r;
+              } else if (rl <= 0) {
+                hi = hl; rhi = rl;
+                if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+              } else {
+                lo = hh; rlo = r;
+                if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+              }
+              ph = kSearch;
+              continue;
+            }
+            const double w0 = hi - lo;
+            if (r > 0) {
+              s3 = lo; r3 = rlo;
+              lo = se; rlo = r;
+              kept = kept <= 0 ? kept - 1 : -1;
+            } else {
+              s3 = hi; r3 = rhi;
+              hi = se; rhi = r;
+              kept = kept >= 0 ? kept + 1 : 1;
+            }
+            have3 = true;
+            slow = (hi - lo) > 0.5 * w0;
+          }
+          const bool cut_ok = true;
+          if (cut_ok && c.err) {
+            st = VOFPC_CELL_BAD_INPUT;
+          } else if (cut_ok) {
+            s_out = s;
+            ag = c.V / VP;
+            A_out = c.A;
+            const double Sm = sqrt(c.S0 * c.S0 + c.S1 * c.S1 + c.S2 * c.S2);
+            if (Sm > 0) {
+              n0 = c.S0 / Sm; n1 = c.S1 / Sm; n2 = c.S2 / Sm;
+              d_out = -(n0 * c.c0 + n1 * c.c1 + n2 * c.c2);
+            }
+          }
+        }
+      if (q == 0) {
+        if (p.mf.gradT) {
+          // mass transfer of the entry (one-sided form, as vofpc_mass_transfer)
+          double md = 0.0;
+          if (A_out > 0.0) {
+            const double gn = p.mf.gradT[P] * n0 + p.mf.gradT[N + P] * n1 + p.mf.gradT[2 * N + P] * n2;
+            const double gl = (a >= 0.5) ? gn : 0.0, gv = (a >= 0.5) ? 0.0 : gn;
+            const double ql = p.mf.k_l * gl * A_out;
+            const double qv = -p.mf.k_v * gv * A_out;
+            md = (ql + qv) / (p.mf.h_lv * m.V[P]);
+          }
+          p.mf.mdot[k] = md;
+          p.mf.Qdot[k] = -md * p.mf.h_lv;
+        }
+        p.out.s[k] = s_out;
+        p.out.n[k] = n0; p.out.n[cap + k] = n1; p.out.n[2 * cap + k] = n2;
+        p.out.A[k] = A_out;
+        p.out.d[k] = d_out;
+        p.out.alpha_got[k] = ag;
+        p.out.status[k] = st;
+        p.out.iters[k] = it;
+      }
+    }
+    // next batch: a wrapping increment, so a launch's nbatch claims (one per
+    // batch done) bring the counter back to zero
+    int nb = 0;
+    if (lane == 0) nb = (int)atomicInc((unsigned int *)p.queue, (unsigned int)(nbatch - 1));
+    bt = (int64_t)gridDim.x + __builtin_amdgcn_readfirstlane(nb);
+    wave_sync();
+  }
+}
+
+template <int G, int NV, int NF, int NL, int NE, bool NET>
+vofpc_status launch_net(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries) {
+  constexpr int C = 64 / G;
+  int blocks_per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu,
+                                                              recon_thin_kernel<G, NV, NF, NL, NE, NET>, 64, 0);
+  if (e != hipSuccess || blocks_per_cu <= 0) blocks_per_cu = 1;
+  int64_t grid = (int64_t)ctx->n_cu * blocks_per_cu;
+  const int64_t need = (n_entries + C - 1) / C;
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  recon_thin_kernel<G, NV, NF, NL, NE, NET><<<(unsigned)grid, 64, 0, ctx->stream>>>(p);
+  VOFPC_HIP(hipGetLastError());
+  return VOFPC_OK;
+}
+
+// the plain build, or the build that runs the network (learned form)
+template <int G, int NV, int NF, int NL, int NE>
+vofpc_status launch_t(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries) {
+  if (p.net_wb) return launch_net<G, NV, NF, NL, NE, true>(ctx, p, n_entries);
+  return launch_net<G, NV, NF, NL, NE, false>(ctx, p, n_entries);
+}
+
+// The builds: class 0 in two sizes (hexahedra and smaller: G = 1, 2, 4; the
+// class caps: G = 2, 4), class 1 at its caps (G = 4, 8, 16).
+struct ThinCaps {
+  int nv, nf, nl, ne;
+};
+constexpr ThinCaps kHex{8, 6, 24, 12}, kC0{16, 8, 48, 24}, kC1{48, 32, 128, 64};
+
+__host__ bool fits(const ThinCaps &t, const int64_t cmax[4]) {
+  return cmax[0] <= t.nv && cmax[1] <= t.nf && cmax[2] <= t.nl && cmax[3] <= t.ne;
+}
+
+}  // namespace
+
+bool thin_available(int c, int G, const int64_t cmax[4]) {
+  if (c == 0) return fits(kHex, cmax) ? (G == 1 || G == 2 || G == 4) : ((G == 2 || G == 4) && fits(kC0, cmax));
+  if (c == 1) return (G == 4 || G == 8 || G == 16) && fits(kC1, cmax);
+  return false;
+}
+
+vofpc_status launch_thin(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries, int c, int G,
+                         const int64_t cmax[4]) {
+  VOFPC_REQUIRE(thin_available(c, G, cmax), VOFPC_E_INVALID_ARG, "reconstruct: no group build for this class");
+  if (c == 0) {
+    if (fits(kHex, cmax)) {
+      if (G == 1) return launch_t<1, kHex.nv, kHex.nf, kHex.nl, kHex.ne>(ctx, p, n_entries);
+      if (G == 2) return launch_t<2, kHex.nv, kHex.nf, kHex.nl, kHex.ne>(ctx, p, n_entries);
+      return launch_t<4, kHex.nv, kHex.nf, kHex.nl, kHex.ne>(ctx, p, n_entries);
+    }
+    if (G == 2) return launch_t<2, kC0.nv, kC0.nf, kC0.nl, kC0.ne>(ctx, p, n_entries);
+    return launch_t<4, kC0.nv, kC0.nf, kC0.nl, kC0.ne>(ctx, p, n_entries);
+  }
+  if (G == 4) return launch_t<4, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
+  if (G == 8) return launch_t<8, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
+  return launch_t<16, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
+}
+
+}  // namespace vofpc

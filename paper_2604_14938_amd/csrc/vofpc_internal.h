@@ -59,6 +59,9 @@ struct DevMesh {
   const uint16_t *cl_eid;  // local undirected edge id of each loop position
   const uint32_t *cl_info; // face within the cell (bits 0-7), index within the face
                            // (8-15) and cell-local next loop position (16-31)
+  const uint32_t *ce;      // per cell-local edge (cell P's edges from cl_off[P]/2, in
+                           // local edge id order): vertices u (bits 0-7), v (8-15),
+                           // the face whose loop runs u -> v (16-23) and the other (24-31)
   // vertex -> cell incidence with normalised inverse-distance weights
   const int64_t *vc_off;
   const int32_t *vc_cell;
@@ -114,11 +117,14 @@ struct vofpc_mesh_s {
   // (cells spread over several classes) launch one variant per class over
   // per-class entry lists [kClasses][n_cells] with device counts
   int64_t class_cells[vofpc::kClasses];
+  int64_t class_max[vofpc::kClasses][4];   // largest vertices, faces, loop positions, edges per class
   int max_class;
   bool bucketed;
   int32_t *bucket_lists;
   int32_t *bucket_counts;
-  // occupancy flavour chosen per class (3 or 4 waves per SIMD; autotuned)
+  // kernel flavour chosen per class (autotuned): 3 or 4 = one cell per
+  // wavefront with the register budget of 3 or 4 waves per SIMD; 10 + G =
+  // G lanes per cell (G = 1, 2, 4, 8)
   int tune[vofpc::kClasses];
   // smallest centre distance of two face neighbours (extrapolation step)
   double min_centre_dist;

@@ -101,6 +101,7 @@ def _load():
         "vofpc_reconstruct_learned": ([P, P, P, P, P, P, P, D, P, P, P], ctypes.c_int),
         "vofpc_mesh_concat": ([P, P, ctypes.c_int32, P], ctypes.c_int),
         "vofpc_mesh_classes": ([P, P, P, P], ctypes.c_int),
+        "vofpc_mesh_set_tune": ([P, P], ctypes.c_int),
         "vofpc_extrap_opts_default": ([P], ctypes.c_int),
         "vofpc_extrapolate": ([P, P, P, P, P, D, P, P, P, P, P, P, P], ctypes.c_int),
         "vofpc_autotune": ([P, P, P, P, ctypes.c_char_p, P, P], ctypes.c_int),
@@ -212,6 +213,12 @@ class Mesh:
         b = ctypes.c_int32()
         _check(lib.vofpc_mesh_classes(self.h, cells, tune, ctypes.byref(b)), "vofpc_mesh_classes")
         return {"cells": list(cells), "tune": list(tune), "bucketed": bool(b.value)}
+
+    def set_tune(self, tune) -> None:
+        """Reconstruction kernel flavour per class (vofpc_mesh_set_tune):
+        3 or 4 (one cell per wavefront), 10 + G (G lanes per cell)."""
+        t = (ctypes.c_int32 * 4)(*[int(x) for x in tune])
+        _check(lib.vofpc_mesh_set_tune(self.h, t), "vofpc_mesh_set_tune")
 
     def info(self) -> dict:
         a = (ctypes.c_int64 * 8)()
