@@ -56,8 +56,10 @@ class _COpts(ctypes.Structure):
 
 @lru_cache(maxsize=1)
 def _lib():
-    build()
-    lib = ctypes.CDLL(_SO)
+    # ORACLE_SO names another build of vof_oracle.c to load (the sanitizer
+    # test's instrumented one); else the in-place build
+    so = os.environ.get("ORACLE_SO") or build()
+    lib = ctypes.CDLL(so)
     P = ctypes.c_void_p
     lib.orc_face_geometry.argtypes = [P, P, P]
     lib.orc_cell_geometry.argtypes = [P, P, P]

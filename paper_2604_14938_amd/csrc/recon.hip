@@ -1253,7 +1253,27 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   const int64_t N = M->d.n_cells;
   p.entries = nullptr;
   p.entry_count = nullptr;
-  if (!M->bucketed) return launch_class(ctx, M, p, N, M->max_class, M->tune[M->max_class]);
+  // event pairs around the class kernels when the context times them (not
+  // while the stream is being captured)
+  bool timed = false;
+  if (ctx->time_classes) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    VOFPC_HIP(hipStreamIsCapturing(ctx->stream, &cs));
+    timed = cs == hipStreamCaptureStatusNone;
+    if (timed)
+      for (int c = 0; c < kClasses; ++c) ctx->cls_rec[c] = false;
+  }
+  auto run_class = [&](int64_t n_cells, int c) -> vofpc_status {
+    if (timed) VOFPC_HIP(hipEventRecord(ctx->cls_ev[c][0], ctx->stream));
+    vofpc_status st = launch_class(ctx, M, p, n_cells, c, M->tune[c]);
+    if (st) return st;
+    if (timed) {
+      VOFPC_HIP(hipEventRecord(ctx->cls_ev[c][1], ctx->stream));
+      ctx->cls_rec[c] = true;
+    }
+    return VOFPC_OK;
+  };
+  if (!M->bucketed) return run_class(N, M->max_class);
   // one launch per class present in the mesh, each over its own entries
   bucket_zero_kernel<<<1, 64, 0, ctx->stream>>>(M->bucket_counts);
   const int64_t span = std::min<int64_t>(out->cap, N);
@@ -1264,8 +1284,44 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
     if (M->class_cells[c] == 0) continue;
     p.entries = M->bucket_lists + (int64_t)c * N;
     p.entry_count = M->bucket_counts + c;
-    vofpc_status st = launch_class(ctx, M, p, M->class_cells[c], c, M->tune[c]);
+    vofpc_status st = run_class(M->class_cells[c], c);
     if (st) return st;
+  }
+  return VOFPC_OK;
+}
+
+extern "C" vofpc_status vofpc_ctx_time_classes(vofpc_ctx ctx, int32_t enable) {
+  using namespace vofpc;
+  clear_error();
+  VOFPC_REQUIRE(ctx, VOFPC_E_INVALID_ARG, "ctx_time_classes: null context");
+  VOFPC_HIP(hipSetDevice(ctx->device));
+  if (enable && !ctx->time_classes) {
+    for (int c = 0; c < kClasses; ++c)
+      for (int j = 0; j < 2; ++j) VOFPC_HIP(hipEventCreate(&ctx->cls_ev[c][j]));
+  } else if (!enable && ctx->time_classes) {
+    for (int c = 0; c < kClasses; ++c)
+      for (int j = 0; j < 2; ++j) {
+        (void)hipEventDestroy(ctx->cls_ev[c][j]);
+        ctx->cls_ev[c][j] = nullptr;
+      }
+  }
+  ctx->time_classes = enable != 0;
+  for (int c = 0; c < kClasses; ++c) ctx->cls_rec[c] = false;
+  return VOFPC_OK;
+}
+
+extern "C" vofpc_status vofpc_ctx_class_ms(vofpc_ctx ctx, float ms[4]) {
+  using namespace vofpc;
+  clear_error();
+  VOFPC_REQUIRE(ctx && ms, VOFPC_E_INVALID_ARG, "ctx_class_ms: null argument");
+  VOFPC_REQUIRE(ctx->time_classes, VOFPC_E_STATE, "ctx_class_ms: class timing is not enabled on this context");
+  VOFPC_HIP(hipSetDevice(ctx->device));
+  for (int c = 0; c < kClasses; ++c) {
+    ms[c] = -1.0f;
+    if (!ctx->cls_rec[c]) continue;
+    VOFPC_HIP(hipEventSynchronize(ctx->cls_ev[c][1]));
+    VOFPC_HIP(hipEventElapsedTime(&ms[c], ctx->cls_ev[c][0], ctx->cls_ev[c][1]));
+    ctx->cls_rec[c] = false;
   }
   return VOFPC_OK;
 }

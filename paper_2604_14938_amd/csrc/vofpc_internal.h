@@ -98,6 +98,11 @@ struct vofpc_ctx_s {
   // launches (each launch wraps it back), so calls on one context must not
   // overlap
   int *queue = nullptr;
+  // per-class kernel timing of the reconstruction (eager launches only):
+  // an event pair around each class kernel of the latest call
+  bool time_classes = false;
+  hipEvent_t cls_ev[vofpc::kClasses][2] = {};
+  bool cls_rec[vofpc::kClasses] = {};
 };
 
 struct vofpc_mesh_s {

@@ -2,7 +2,8 @@
 
 Training data: seeded synthetic fields (random bubbles with radii in
 [2h, 12h] and planar interfaces with random normals, on uniform hexahedral
-and jittered-BCC Voronoi meshes).  Inputs are the library's own features;
+and jittered-BCC Voronoi meshes, and wavy liquid films of random thickness,
+wave count and amplitude on Voronoi pipe meshes).  Inputs are the library's own features;
 labels are its plain (full-bracket) reconstructions: u* = (s* - phi_min)/W and
 the interface normal, for cells whose reconstruction ended OK.  10 % of the
 cells are held out; their RMS error of u gives sigma, stored with the weights
@@ -52,12 +53,19 @@ def xavier(seed: int, n_params: int) -> np.ndarray:
 
 
 def field_list(seed: int, n_fields: int):
-    """(mesh kind, field kind, parameters) for each training field."""
+    """(mesh kind, field kind, parameters) for each training field: of every
+    six, three bubble fields on Voronoi boxes, one on hexahedra, one film on
+    a pipe and one plane (alternately on the two box meshes)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n_fields):
-        mesh_kind = "voronoi" if i % 3 != 2 else "hex"
-        field_kind = "plane" if i % 5 == 4 else "bubbles"
+        k = i % 6
+        if k == 4:
+            mesh_kind, field_kind = "pipe", "film"
+        elif k == 5:
+            mesh_kind, field_kind = ("voronoi" if (i // 6) % 2 == 0 else "hex"), "plane"
+        else:
+            mesh_kind, field_kind = ("hex" if k == 2 else "voronoi"), "bubbles"
         out.append((mesh_kind, field_kind, int(rng.integers(1 << 30))))
     return out
 
@@ -85,62 +93,98 @@ def labelled_cells(ctx, vmesh, mesh, alpha, buf):
     return X[ok].clone(), T[ok].clone()
 
 
-def make_dataset(ctx, n_target: int, seed: int, max_fields: int = 600):
-    from synth import fields, meshes, workloads
+def _field_alpha(m, fk: str, s: int) -> np.ndarray:
+    """The alpha field of one training field on mesh m (host work only)."""
+    from synth import fields, workloads
+    frng = np.random.default_rng(s)
+    if fk == "bubbles":
+        wl = workloads.random_bubbles(m, seed=s, n_max=int(frng.integers(50, 600)), K=12, r_lo_h=2.0,
+                                      r_hi_h=min(float(frng.uniform(4.0, 12.0)), 0.3 / m.h))
+        return wl.alpha
+    if fk == "film":
+        L = 52.0 / 9.5
+        return fields.film_alpha(m, 1.0, float(frng.uniform(0.05, 0.2)), float(frng.uniform(0.0, 0.5)),
+                                 float(frng.integers(1, 9)), L, K=12)
+    nrm = frng.normal(size=3)
+    nrm /= np.linalg.norm(nrm)
+    c = float(nrm @ np.full(3, 0.5) + frng.uniform(-0.25, 0.25))
+    return fields.plane_alpha(m, nrm, c, K=12)
+
+
+def make_dataset(ctx, n_target: int, seed: int, max_fields: int = 1200, threads: int = 8):
+    """Features and labels of the fields of `field_list`, in order, until
+    n_target cells are labelled.  The alpha fields are built on a thread pool
+    (their C and array work releases the interpreter lock), a window at a
+    time, and labelled on the device in field order."""
+    from concurrent.futures import ThreadPoolExecutor
+    from synth import fields, meshes
+    fields._lib()       # load the sub-sampling helper once, before the threads
+    lst = field_list(seed, max_fields)
+    # meshes at the first use of each (kind, size slot), in field order
+    rng = np.random.default_rng(seed)
+    mesh_of = {}
+    for i, (mk, fk, s) in enumerate(lst):
+        key = (mk, (i // 6) % 3)
+        if key in mesh_of:
+            continue
+        if mk == "voronoi":
+            mesh_of[key] = meshes.voronoi_box_mesh(int(rng.choice([24, 32, 40])), seed=s)
+        elif mk == "pipe":
+            mesh_of[key] = meshes.voronoi_pipe_mesh(int(rng.choice([24, 30, 36])), 1.0, 52.0 / 9.5, s)
+        else:
+            mesh_of[key] = meshes.hex_mesh(int(rng.choice([40, 56, 72])))
+    dev_of = {}
     X_parts, T_parts = [], []
     n = 0
-    mesh_cache = {}
-    rng = np.random.default_rng(seed)
-    for i, (mk, fk, s) in enumerate(field_list(seed, max_fields)):
-        if n >= n_target:
-            break
-        key = (mk, i % 4)
-        if key not in mesh_cache:
-            if mk == "voronoi":
-                m = meshes.voronoi_box_mesh(int(rng.choice([16, 20, 24])), seed=s)
-            else:
-                m = meshes.hex_mesh(int(rng.choice([24, 32, 40])))
-            vm = V.Mesh(ctx, m)
-            N = m.n_cells
-            dev = ctx.device
-            buf = dict(mixed=torch.zeros(N, dtype=torch.int32, device=dev),
-                       band=torch.zeros(N, dtype=torch.int32, device=dev),
-                       counts=torch.zeros(2, dtype=torch.int32, device=dev),
-                       feat=torch.zeros(N, 32, dtype=torch.float32, device=dev),
-                       prange=torch.zeros(N, 2, dtype=torch.float64, device=dev),
-                       itf=V.Interface.empty(N, dev))
-            mesh_cache[key] = (m, vm, buf)
-        m, vm, buf = mesh_cache[key]
-        frng = np.random.default_rng(s)
-        if fk == "bubbles":
-            wl = workloads.random_bubbles(m, seed=s, n_max=int(frng.integers(20, 200)), K=12,
-                                          r_lo_h=2.0,
-                                          r_hi_h=min(float(frng.uniform(4.0, 12.0)), 0.3 / m.h))
-            alpha = wl.alpha
-        else:
-            nrm = frng.normal(size=3)
-            nrm /= np.linalg.norm(nrm)
-            c = float(nrm @ np.full(3, 0.5) + frng.uniform(-0.25, 0.25))
-            alpha = fields.plane_alpha(m, nrm, c, K=12)
-        res = labelled_cells(ctx, vm, m, alpha, buf)
-        if res is None:
-            continue
-        X, T = res
-        X_parts.append(X)
-        T_parts.append(T)
-        n += X.shape[0]
-        if i % 10 == 0:
-            log(f"field {i}: {mk}/{fk}, {X.shape[0]} cells, total {n}")
+    kinds = {}
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        for w0 in range(0, len(lst), threads):
+            if n >= n_target:
+                break
+            win = list(enumerate(lst))[w0:w0 + threads]
+            alphas = list(pool.map(lambda t: _field_alpha(mesh_of[(t[1][0], (t[0] // 6) % 3)], t[1][1], t[1][2]),
+                                   win))
+            for (i, (mk, fk, s)), alpha in zip(win, alphas):
+                if n >= n_target:
+                    break
+                key = (mk, (i // 6) % 3)
+                m = mesh_of[key]
+                if key not in dev_of:
+                    N = m.n_cells
+                    dev = ctx.device
+                    buf = dict(mixed=torch.zeros(N, dtype=torch.int32, device=dev),
+                               band=torch.zeros(N, dtype=torch.int32, device=dev),
+                               counts=torch.zeros(2, dtype=torch.int32, device=dev),
+                               feat=torch.zeros(N, 32, dtype=torch.float32, device=dev),
+                               prange=torch.zeros(N, 2, dtype=torch.float64, device=dev),
+                               itf=V.Interface.empty(N, dev))
+                    dev_of[key] = (V.Mesh(ctx, m), buf)
+                vm, buf = dev_of[key]
+                res = labelled_cells(ctx, vm, m, alpha, buf)
+                if res is None:
+                    continue
+                X, T = res
+                X_parts.append(X)
+                T_parts.append(T)
+                n += X.shape[0]
+                kinds[f"{mk}/{fk}"] = kinds.get(f"{mk}/{fk}", 0) + int(X.shape[0])
+                if i % 10 == 0:
+                    log(f"field {i}: {mk}/{fk} on {m.n_cells} cells, {X.shape[0]} labelled, total {n}")
+    for vm, _ in dev_of.values():
+        vm.close()
     X = torch.cat(X_parts)
     T = torch.cat(T_parts)
-    return X, T
+    return X, T, kinds
 
 
 def train(samples: int, steps: int, seed: int, out: str, batch: int = 4096, lr: float = 3e-3) -> dict:
+    """Build the dataset, train with Adam on a cosine schedule and save the
+    weights with the held-out sigma; returns the run's summary."""
     ctx = V.Context(0, stream=torch.cuda.Stream())
     t0 = time.time()
-    X, T = make_dataset(ctx, samples, seed)
-    log(f"dataset: {X.shape[0]} labelled cells in {time.time() - t0:.1f} s")
+    X, T, kinds = make_dataset(ctx, samples, seed)
+    t_data = time.time() - t0
+    log(f"dataset: {X.shape[0]} labelled cells in {t_data:.1f} s: {kinds}")
     g = torch.Generator(device="cpu").manual_seed(seed)
     perm = torch.randperm(X.shape[0], generator=g).to(X.device)
     X, T = X[perm].contiguous(), T[perm].contiguous()
@@ -173,6 +217,7 @@ def train(samples: int, steps: int, seed: int, out: str, batch: int = 4096, lr: 
     q99 = float(err.abs().quantile(0.99)) if nval > 10 else float("nan")
     params = mlp.get_params()
     info = dict(samples=int(X.shape[0]), train=int(ntr), val=int(nval), steps=steps, batch=batch, lr=lr, seed=seed,
+                labels_by_kind=kinds, dataset_seconds=t_data,
                 sigma_val=sigma, abs_err_q99=q99, delta_scale=3.0 * sigma, final_loss=hist[-1][1],
                 train_seconds=time.time() - t1, loss_history=hist)
     os.makedirs(os.path.dirname(out), exist_ok=True)
@@ -190,8 +235,8 @@ def load(path: str = DEFAULT_WEIGHTS) -> tuple[np.ndarray, float, dict]:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--samples", type=int, default=600_000)
-    ap.add_argument("--steps", type=int, default=120000)
+    ap.add_argument("--samples", type=int, default=2_200_000)
+    ap.add_argument("--steps", type=int, default=200000)
     ap.add_argument("--seed", type=int, default=2604)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     a = ap.parse_args()

@@ -102,6 +102,8 @@ def _load():
         "vofpc_mesh_concat": ([P, P, ctypes.c_int32, P], ctypes.c_int),
         "vofpc_mesh_classes": ([P, P, P, P], ctypes.c_int),
         "vofpc_mesh_set_tune": ([P, P], ctypes.c_int),
+        "vofpc_ctx_time_classes": ([P, ctypes.c_int32], ctypes.c_int),
+        "vofpc_ctx_class_ms": ([P, P], ctypes.c_int),
         "vofpc_extrap_opts_default": ([P], ctypes.c_int),
         "vofpc_extrapolate": ([P, P, P, P, P, D, P, P, P, P, P, P, P], ctypes.c_int),
         "vofpc_autotune": ([P, P, P, P, ctypes.c_char_p, P, P], ctypes.c_int),
@@ -160,6 +162,18 @@ class Context:
     def set_stream(self, stream: torch.cuda.Stream) -> None:
         self.stream = stream
         _check(lib.vofpc_ctx_set_stream(self.h, stream.cuda_stream), "vofpc_ctx_set_stream")
+
+    def time_classes(self, enable: bool = True) -> None:
+        """Record an event pair around each class kernel of later eager
+        reconstructions on this context (vofpc_ctx_time_classes)."""
+        _check(lib.vofpc_ctx_time_classes(self.h, int(bool(enable))), "vofpc_ctx_time_classes")
+
+    def class_ms(self) -> list:
+        """Durations (ms) of the class kernels of the latest reconstruction,
+        -1 for classes not launched (vofpc_ctx_class_ms)."""
+        a = (ctypes.c_float * 4)()
+        _check(lib.vofpc_ctx_class_ms(self.h, a), "vofpc_ctx_class_ms")
+        return [float(x) for x in a]
 
     def close(self) -> None:
         if getattr(self, "h", None):

@@ -33,8 +33,9 @@ def build_helper(force: bool = False) -> str:
 
 @lru_cache(maxsize=1)
 def _lib():
-    build_helper()
-    lib = ctypes.CDLL(_SO)
+    # SYNTH_SUBSAMPLE_SO names another build of _subsample.c to load (the
+    # sanitizer test's instrumented one); else the in-place build
+    lib = ctypes.CDLL(os.environ.get("SYNTH_SUBSAMPLE_SO") or build_helper())
     P = ctypes.c_void_p
     lib.synth_subsample.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_int, P, ctypes.c_int, P]
     lib.synth_subsample.restype = None
@@ -109,9 +110,16 @@ def sphere_alpha(mesh: Mesh, spheres: np.ndarray, K: int = 64) -> np.ndarray:
     X = mesh.vert_xyz
     touch_cells, touch_sph = [], []
     inside_any = np.zeros(N, bool)
+    # cells whose box meets the sphere's box have their box centre within
+    # r + (largest box half-diagonal) of the sphere's centre
+    from scipy.spatial import cKDTree
+    bc = 0.5 * (bbox[:, :3] + bbox[:, 3:])
+    ext = 0.5 * float(np.sqrt(((bbox[:, 3:] - bbox[:, :3]) ** 2).sum(1)).max())
+    tree = cKDTree(bc)
     for s, (cx, cy, cz, r) in enumerate(spheres):
         c = np.array([cx, cy, cz])
-        cand = np.nonzero(np.all(bbox[:, :3] <= c + r, 1) & np.all(bbox[:, 3:] >= c - r, 1))[0]
+        near = np.sort(np.asarray(tree.query_ball_point(c, r * np.sqrt(3.0) + ext + 1e-12), np.int64))
+        cand = near[np.all(bbox[near, :3] <= c + r, 1) & np.all(bbox[near, 3:] >= c - r, 1)]
         if len(cand) == 0:
             continue
         q = np.clip(c, bbox[cand, :3], bbox[cand, 3:])
@@ -180,10 +188,9 @@ def plane_alpha(mesh: Mesh, normal, c: float, K: int = 16) -> np.ndarray:
     N = mesh.n_cells
     cells_v, verts_v = _cell_vertices(mesh)
     d = n @ mesh.vert_xyz[:, verts_v] - c
-    lo = np.full(N, np.inf)
-    hi = np.full(N, -np.inf)
-    np.minimum.at(lo, cells_v, d)
-    np.maximum.at(hi, cells_v, d)
+    seg = np.r_[0, np.cumsum(np.bincount(cells_v, minlength=N))[:-1]]   # incidences run cell by cell
+    lo = np.minimum.reduceat(d, seg)
+    hi = np.maximum.reduceat(d, seg)
     alpha = (lo >= 0).astype(float)
     cut = np.nonzero((lo < 0) & (hi > 0))[0]
     if len(cut):

@@ -95,22 +95,19 @@ class Mesh:
         """Axis-aligned bounding box of each cell, [N, 6] = (lo xyz, hi xyz)."""
         N = self.n_cells
         cf_cnt = np.diff(self.cell_face_off)
-        cell_of_slot = np.repeat(np.arange(N), cf_cnt)
         faces = self.cell_face.astype(np.int64)
         rep = np.diff(self.face_vert_off)[faces]
-        cells = np.repeat(cell_of_slot, rep)
         starts = self.face_vert_off[faces]
         idx = np.repeat(starts - np.cumsum(np.r_[0, rep[:-1]]), rep) + np.arange(rep.sum())
         verts = self.face_vert[idx]
+        # the incidences run cell by cell: one segment reduction per axis
+        per_cell = np.bincount(np.repeat(np.arange(N), cf_cnt), weights=rep, minlength=N).astype(np.int64)
+        seg = np.r_[0, np.cumsum(per_cell)[:-1]]
         out = np.empty((N, 6))
         for a in range(3):
             x = self.vert_xyz[a, verts]
-            lo = np.full(N, np.inf)
-            hi = np.full(N, -np.inf)
-            np.minimum.at(lo, cells, x)
-            np.maximum.at(hi, cells, x)
-            out[:, a] = lo
-            out[:, 3 + a] = hi
+            out[:, a] = np.minimum.reduceat(x, seg)
+            out[:, 3 + a] = np.maximum.reduceat(x, seg)
         return out
 
     def face_neighbours(self) -> tuple[np.ndarray, np.ndarray]:
@@ -430,8 +427,9 @@ class _VGResult(ctypes.Structure):
 
 @lru_cache(maxsize=1)
 def _vlib():
-    build_voronoi_helper()
-    lib = ctypes.CDLL(_VSO)
+    # SYNTH_VORONOI_SO names another build of _voronoi.c to load (the
+    # sanitizer test's instrumented one); else the in-place build
+    lib = ctypes.CDLL(os.environ.get("SYNTH_VORONOI_SO") or build_voronoi_helper())
     P = ctypes.c_void_p
     lib.vg_build.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int, P, P]
     lib.vg_build.restype = ctypes.c_int

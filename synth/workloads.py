@@ -14,6 +14,8 @@
 * ``pipe_film``      Voronoi cells of a pipe with a wavy liquid film on the wall.
 * ``batched``        several meshes with many bubbles each (a hexahedral and a
   Voronoi mesh by default), stepped as one disjoint union.
+* ``learned_full``   the batched pair plus a Voronoi pipe of about 4M cells
+  with the wavy film: the learned-bracket configuration at full size.
 * ``static_sphere``  one vapour sphere at rest with the Scriven-like erf
   temperature profile on a hexahedral (n^3) or Voronoi (2 n^3) mesh: the
   static analogue of the gradient-anisotropy study (Sec. 3.3, gradient
@@ -142,6 +144,61 @@ def batched(hex_n: int = 128, vor_n: int = 79, seed: int = 3, n_max: int = 1000,
     out = []
     for i, m in enumerate((hex_mesh(hex_n), voronoi_box_mesh(vor_n, seed))):
         out.append(random_bubbles(m, seed=seed + 17 * i, n_max=n_max, K=K, r_hi_h=r_hi_h))
+    return out
+
+
+def learned_full(hex_n: int = 128, vor_n: int = 79, pipe_radial: int = 98, seed: int = 3, log=None) -> list:
+    """The batched pair (hex_n^3 hexahedra and 2 vor_n^3 Voronoi cells, random
+    bubbles) and a Voronoi pipe with `pipe_radial` seeds across its diameter
+    (98 gives 4,043,057 cells) carrying the wavy film; returns the three
+    workloads, stepped as one disjoint union."""
+    out = batched(hex_n=hex_n, vor_n=vor_n, seed=seed)
+    if log:
+        log(f"batched pair: {[w.mesh.n_cells for w in out]} cells, {[w.n_mixed for w in out]} mixed")
+    out.append(pipe_film(n_radial=pipe_radial, seed=4))
+    if log:
+        log(f"pipe: {out[-1].mesh.n_cells} cells, {out[-1].n_mixed} mixed")
+    return out
+
+
+_MESH_ARRAYS = ("cell_face_off", "cell_face", "face_vert_off", "face_vert", "face_owner", "face_neigh", "face_bc",
+                "vert_xyz")
+
+
+def save_parts(path: str, wls: list) -> None:
+    """Write workloads (meshes, fields, constants; not `meta`) to one .npz
+    file, no pickled objects."""
+    arr = {"n_parts": np.array(len(wls))}
+    for i, w in enumerate(wls):
+        m = w.mesh
+        for k in _MESH_ARRAYS:
+            arr[f"p{i}_{k}"] = getattr(m, k)
+        arr[f"p{i}_sizes"] = np.array([m.n_cells, m.n_faces, m.n_verts], np.int64)
+        arr[f"p{i}_h"] = np.array(m.h)
+        arr[f"p{i}_kind"] = np.array(m.kind)
+        arr[f"p{i}_name"] = np.array(w.name)
+        arr[f"p{i}_alpha"], arr[f"p{i}_T"], arr[f"p{i}_Tb"] = w.alpha, w.T, w.T_bface
+        arr[f"p{i}_const"] = np.array([w.T_sat, w.k_l, w.k_v, w.h_lv])
+        if "n_bubbles" in w.meta:
+            arr[f"p{i}_n_bubbles"] = np.array(w.meta["n_bubbles"])
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **arr)
+    import os
+    os.replace(tmp, path)
+
+
+def load_parts(path: str) -> list:
+    """Read workloads written by `save_parts`."""
+    z = np.load(path, allow_pickle=False)
+    out = []
+    for i in range(int(z["n_parts"])):
+        N, NF, NV = (int(x) for x in z[f"p{i}_sizes"])
+        m = Mesh(N, NF, NV, *[z[f"p{i}_{k}"] for k in _MESH_ARRAYS], kind=str(z[f"p{i}_kind"]),
+                 h=float(z[f"p{i}_h"]))
+        c = z[f"p{i}_const"]
+        meta = {"n_bubbles": int(z[f"p{i}_n_bubbles"])} if f"p{i}_n_bubbles" in z else {}
+        out.append(Workload(str(z[f"p{i}_name"]), m, z[f"p{i}_alpha"], z[f"p{i}_T"], z[f"p{i}_Tb"],
+                            float(c[0]), float(c[1]), float(c[2]), float(c[3]), meta=meta))
     return out
 
 

@@ -28,3 +28,28 @@ def test_algorithmic_flops_by_cell_kind():
     assert bench.recon_flops(hexm, np.arange(5)) == 5 * bench.FLOPS_HEX_CELL
     assert bench.recon_flops(vor, np.arange(3)) == 3 * bench.FLOPS_VORONOI_CELL
     assert abs(bench.FP64_PEAK_TFLOPS - 78.6432) < 1e-9
+
+
+def test_kernel_classes_and_footprint():
+    sys.path.insert(0, ROOT)
+    import bench
+    from synth import meshes, workloads
+    hexm = meshes.hex_mesh(4)
+    cells = np.arange(hexm.n_cells)
+    assert np.all(bench.cell_classes(hexm, cells) == 0)
+    row, verts, nf, nl = bench.cell_incidence(hexm, cells[:3])
+    assert np.all(np.bincount(row) == 8) and np.all(nf == 6) and np.all(nl == 24)
+    vor = meshes.voronoi_box_mesh(6, seed=1)
+    c = bench.cell_classes(vor, np.arange(vor.n_cells))
+    row, _, nf, nl = bench.cell_incidence(vor, np.arange(vor.n_cells))
+    nv = np.bincount(row)
+    # every cell in the first class whose caps hold it
+    for k in range(len(bench.CLASS_CAPS)):
+        v, f, l, e = bench.CLASS_CAPS[k]
+        fits = (nv <= v) & (nf <= f) & (nl <= l) & (nl // 2 <= e)
+        assert np.all(c[fits] <= k) and np.all(c[~fits] > k)
+    # the footprint grows with the cells and counts each shared vertex once
+    b1 = bench.recon_bytes(hexm, cells[:1])
+    b2 = bench.recon_bytes(hexm, cells[:2])
+    assert 0 < b1 < b2 < 2 * b1
+    assert bench.recon_bytes(hexm, cells[:2], learned=True) > b2
