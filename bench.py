@@ -51,7 +51,7 @@ FLOPS_VORONOI_CELL = 40.0e3
 FLOPS_HEX_CELL = 18.5e3
 # kernel classes by cell size: largest vertices, faces, loop positions and
 # edges of a cell each class's kernels are built for (class 3: larger)
-CLASS_CAPS = ((16, 8, 48, 24), (48, 32, 128, 64), (64, 64, 256, 128))
+CLASS_CAPS = ((16, 8, 48, 24), (32, 20, 96, 48), (48, 32, 128, 64))
 STATUS_NAMES = ("ok", "not_mixed", "learned_fallback", "degenerate", "max_iter", "g_singular", "bad_input",
                 "no_root")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "recon_kernel_traffic.json")

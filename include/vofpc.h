@@ -134,21 +134,22 @@ vofpc_status vofpc_mesh_free(vofpc_mesh mesh);
 vofpc_status vofpc_mesh_info(vofpc_mesh mesh, int64_t info[8]);
 /* Kernel classes of the mesh's cells (HOST outputs, any may be NULL): cells[c]
  * = number of cells whose size (vertices, faces, loop positions, edges) fits
- * class c = 0 (<= 16, 8, 48, 24), 1 (<= 48, 32, 128, 64), 2 (<= 64, 64, 256,
- * 128) or 3 (larger); tune[c] = the reconstruction kernel flavour used for
- * class c (see vofpc_mesh_set_tune); *bucketed = 1 when the cells spread over
- * several classes (each with >= 1 % of the cells): then the reconstruction
- * splits the mixed entries by class and launches each class's kernel on its
- * own entries (face-count buckets), else one kernel sized for the largest
- * cell runs. */
+ * class c = 0 (<= 16, 8, 48, 24: hexahedra and smaller), 1 (<= 32, 20, 96,
+ * 48: the usual Voronoi cells), 2 (<= 48, 32, 128, 64) or 3 (larger); tune[c]
+ * = the reconstruction kernel flavour used for class c (see
+ * vofpc_mesh_set_tune); *bucketed = 1 when the cells spread over several
+ * classes: then the reconstruction splits the mixed entries by class and
+ * launches each class's kernel on its own entries (size buckets), else the
+ * one class's kernel runs. */
 vofpc_status vofpc_mesh_classes(vofpc_mesh mesh, int64_t cells[4], int32_t tune[4], int32_t *bucketed);
 /* Reconstruction kernel flavours (tile shapes) per class:
  *   3, 4   one cell per wavefront (64 lanes over its loop positions), with
- *          the register budget of 3 or 4 waves per SIMD; every class;
+ *          the register budget of 3 or 4 waves per SIMD; 3 for every
+ *          class, 4 for classes 0 to 2;
  *   10+G   a group of G lanes per cell (the lanes share the cell's edges and
  *          faces), 64/G cells per wavefront: G = 1, 2, 4 for class 0 when
  *          its cells are at most hexahedra (8 vertices, 6 faces), else
- *          G = 2, 4; G = 4, 8, 16 for class 1.
+ *          G = 2, 4; G = 4, 8, 16 for classes 1 and 2.
  * The learned form runs the network inside the reconstruction for every
  * flavour.  Results of all flavours agree within the parity tolerances. */
 #define VOFPC_FLAVOUR_WAVE3 3
@@ -235,17 +236,25 @@ typedef struct {
  * at once.  Any isovalue in the stopping window is a valid result; the
  * oracle's bisection may stop at another one of the same window.
  * hint_lo/hint_hi: DEVICE [cap] per mixed entry, read only when
- * opts->bracket is VOFPC_BRACKET_HINT: the midpoint is the first guess and
- * a cell whose result falls outside [hint_lo, hint_hi] is flagged
- * VOFPC_CELL_LEARNED_FALLBACK (NaN entries: plain search, no flag). */
+ * opts->bracket is VOFPC_BRACKET_HINT (NaN entries: plain search, no flag):
+ * the bracket, clipped to [phi_min, phi_max], is checked with two cuts, at
+ * its centre and at its end on the side of the root that the centre's
+ * residual gives.  When that end is past the root the search goes on in
+ * the half between them; otherwise it goes on beyond that end and the cell
+ * is flagged VOFPC_CELL_LEARNED_FALLBACK.  The flag therefore marks exactly
+ * the cells whose root lies outside the clipped bracket (V(s) decreasing),
+ * as a cut at both ends would. */
 vofpc_status vofpc_reconstruct(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, const int32_t *mixed_idx,
                                const int32_t *counts, const vofpc_recon_opts *opts, const double *hint_lo,
                                const double *hint_hi, const vofpc_interface *out);
 
 /* Reconstruction with the bracket network run inside the same kernel: each
  * mixed cell's 32 inputs (as vofpc_features defines them) and the forward
- * pass on MFMA give the bracket phi_min + clamp(u,0,1) W +- delta_scale W,
- * used as with VOFPC_BRACKET_HINT.  opts->bracket must be
+ * pass (BF16 MFMA tiles of 16 cells in the group flavours, one FP32 row per
+ * wavefront in the wavefront flavours) give the predicted isovalue
+ * phi_min + clamp(u,0,1) W and the bracket around it of half-width
+ * delta_scale W, checked as with VOFPC_BRACKET_HINT with the first cut at the
+ * predicted isovalue.  opts->bracket must be
  * VOFPC_BRACKET_PLAIN.  hint_lo/hint_hi: optional DEVICE double[cap]
  * receiving the network's brackets (both or neither; NaN where the network
  * gives none).  Cells whose vertex field is degenerate skip the network. */

@@ -25,10 +25,14 @@ FLAGS = [
     "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
 ]
 SOURCES = ["api.hip", "mesh.hip", "compact.hip", "recon.hip", "recon_thin.hip", "grad.hip", "mlp.hip", "extrap.hip", "robin.hip", "csf.hip"]
+# per-source extra flags: the group reconstruction kernels keep the network's
+# MFMA accumulators in VGPRs (accumulation registers would push the learned
+# builds below the register budget of their plain twins)
+EXTRA = {"recon_thin.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {os.path.basename(src)}:\n{r.stderr[-6000:]}")

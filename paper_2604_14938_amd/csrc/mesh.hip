@@ -237,7 +237,7 @@ static vofpc_status setup_classes(vofpc_mesh M, const int64_t *class_cnt, const 
     for (int t = 0; t < 4; ++t) M->class_max[c][t] = cmax[c][t];
     M->tune[c] = 3;
     if (class_cnt[c] > 0) M->max_class = c;
-    if (class_cnt[c] > 0 && class_cnt[c] * 100 >= N) ++big;
+    if (class_cnt[c] > 0) ++big;
   }
   M->bucketed = big >= 2;
   M->bucket_lists = nullptr;

@@ -61,7 +61,7 @@ __device__ void tile_forward(TileMem &T, const float *X, int64_t row0, int nrows
     for (int kt = 0; kt < kIn / 16; ++kt)
       acc = mfma16(a_rows<kIn>(T.x, lane, kt * 16), b_weightT(wb + oW1, kIn, lane, nt * 16, kt * 16, kHid), acc);
     const float b = master[oB1 + nt * 16 + col];
-    for (int j = 0; j < 4; ++j) T.h1[rq + j][nt * 16 + col] = to_bf16(tanhf(acc[j] + b));
+    for (int j = 0; j < 4; ++j) T.h1[rq + j][nt * 16 + col] = to_bf16(act_tanh(acc[j] + b));
   }
   wsync();
   // layer 2
@@ -70,7 +70,7 @@ __device__ void tile_forward(TileMem &T, const float *X, int64_t row0, int nrows
     for (int kt = 0; kt < kHid / 16; ++kt)
       acc = mfma16(a_rows<kHid>(T.h1, lane, kt * 16), b_weightT(wb + oW2, kHid, lane, nt * 16, kt * 16, kHid), acc);
     const float b = master[oB2 + nt * 16 + col];
-    for (int j = 0; j < 4; ++j) T.h2[rq + j][nt * 16 + col] = to_bf16(tanhf(acc[j] + b));
+    for (int j = 0; j < 4; ++j) T.h2[rq + j][nt * 16 + col] = to_bf16(act_tanh(acc[j] + b));
   }
   wsync();
   // layer 3 (4 outputs, padded to a 16-wide tile)

@@ -846,10 +846,10 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
           int kept = 0;            // > 0: lo kept that many updates in a row, < 0: hi
           bool slow = false;       // the last update did not halve the bracket
           int lru = 0, probe = -1;
-          // learned bracket: its centre is the first isovalue tried; the
-          // status records whether the root fell outside it
+          // learned bracket [sh - dl, sh + dl]; the status records whether
+          // the root fell outside it
           bool hint = false;
-          double hl = 0, hh = 0;
+          double hl = 0, hh = 0, hm = 0;
           if (p.net_wb && st == VOFPC_CELL_OK) {
             const double Wd = pmax - pmin;
             const float u = net_guess<NF>(L, lane, p, k, P, a, nv, nf, f0, pmin, Wd, pf);
@@ -865,6 +865,7 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
               hl = hl > pmin ? hl : pmin;
               hh = hh < pmax ? hh : pmax;
               hint = hl <= hh;
+              hm = sh < hl ? hl : (sh > hh ? hh : sh);
             } else if (lane == 0 && p.net_lo) {
               p.net_lo[k] = __builtin_nan("");
               p.net_hi[k] = __builtin_nan("");
@@ -881,29 +882,52 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
               hl = hl > pmin ? hl : pmin;
               hh = hh < pmax ? hh : pmax;
               hint = hl <= hh;
+              hm = hl + (hh - hl) / 2.0;
             }
           }
           if (hint) {
-            // check the narrowed bracket with a cut at each end: it is kept
-            // when the ends straddle the root; otherwise the root lies beyond
-            // the end that failed (LEARNED_FALLBACK)
-            const CutRes cl = full_step(L, lane, nv, nf, nl, hl, lru);
-            const CutRes ch = full_step(L, lane, nv, nf, nl, hh, lru);
-            it += 2;
-            const double rl = cl.V / VP - a, rh = ch.V / VP - a;
-            if (fabs(rl) <= tol) {
-              s = hl; c = cl; cut_ok = true;
-            } else if (fabs(rh) <= tol) {
-              s = hh; c = ch; cut_ok = true;
-            } else if (rl > 0 && rh < 0) {
-              lo = hl; rlo = rl; have_lo = true; store_end(L, lane, 0, cl);
-              hi = hh; rhi = rh; have_hi = true; store_end(L, lane, 1, ch);
-            } else if (rl <= 0) {
-              hi = hl; rhi = rl; have_hi = true; store_end(L, lane, 1, cl);
-              if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+            // check the narrowed bracket with two cuts: at its centre (the
+            // predicted isovalue), whose residual tells the side of the root,
+            // and at the bracket end on that side.  The bracket holds when
+            // that end is past the root (the half on the root's side is
+            // kept); otherwise the root lies beyond it (LEARNED_FALLBACK).
+            const CutRes cm = full_step(L, lane, nv, nf, nl, hm, lru);
+            ++it;
+            const double rm = cm.V / VP - a;
+            if (fabs(rm) <= tol) {
+              s = hm; c = cm; cut_ok = true;
             } else {
-              lo = hh; rlo = rh; have_lo = true; store_end(L, lane, 0, ch);
-              if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+              const bool up = rm > 0;          // the root lies above hm
+              const double he = up ? hh : hl;
+              if (up) {
+                s3 = hi; r3 = rhi;
+                lo = hm; rlo = rm; have_lo = true; store_end(L, lane, 0, cm);
+              } else {
+                s3 = lo; r3 = rlo;
+                hi = hm; rhi = rm; have_hi = true; store_end(L, lane, 1, cm);
+              }
+              have3 = true;
+              bool holds = false;
+              if (he != hm) {
+                wave_sync();
+                const CutRes ce = full_step(L, lane, nv, nf, nl, he, lru);
+                ++it;
+                const double re = ce.V / VP - a;
+                if (fabs(re) <= tol) {
+                  s = he; c = ce; cut_ok = true;
+                  holds = true;
+                } else if (up ? re < 0 : re > 0) {
+                  holds = true;
+                  s3 = up ? hi : lo; r3 = up ? rhi : rlo;
+                  if (up) { hi = he; rhi = re; have_hi = true; store_end(L, lane, 1, ce); }
+                  else { lo = he; rlo = re; have_lo = true; store_end(L, lane, 0, ce); }
+                } else {
+                  s3 = hm; r3 = rm;
+                  if (up) { lo = he; rlo = re; store_end(L, lane, 0, ce); }
+                  else { hi = he; rhi = re; store_end(L, lane, 1, ce); }
+                }
+              }
+              if (!holds && st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
             }
             wave_sync();
           }
@@ -1194,9 +1218,9 @@ vofpc_status launch_class(vofpc_ctx ctx, vofpc_mesh M, const ReconParams &p, int
     case 0:
       return occ == 4 ? launch_t<16, 8, 48, 24, 4>(ctx, p, n_cells) : launch_t<16, 8, 48, 24, 3>(ctx, p, n_cells);
     case 1:
-      return occ == 4 ? launch_t<48, 32, 128, 64, 4>(ctx, p, n_cells) : launch_t<48, 32, 128, 64, 3>(ctx, p, n_cells);
+      return occ == 4 ? launch_t<32, 20, 96, 48, 4>(ctx, p, n_cells) : launch_t<32, 20, 96, 48, 3>(ctx, p, n_cells);
     case 2:
-      return launch_t<64, 64, 256, 128, 3>(ctx, p, n_cells);
+      return occ == 4 ? launch_t<48, 32, 128, 64, 4>(ctx, p, n_cells) : launch_t<48, 32, 128, 64, 3>(ctx, p, n_cells);
     default:
       return launch_t<255, 255, 1536, 768, 3>(ctx, p, n_cells);
   }
@@ -1341,7 +1365,7 @@ struct TuneBuffers {
 // Whether class c of mesh M has a build of flavour f.
 bool flavour_ok(vofpc_mesh M, int c, int f) {
   if (f == VOFPC_FLAVOUR_WAVE3) return true;
-  if (f == VOFPC_FLAVOUR_WAVE4) return c <= 1;
+  if (f == VOFPC_FLAVOUR_WAVE4) return c <= 2;
   if (f >= 10 && f <= 26) return thin_available(c, f - 10, M->class_max[c]);
   return false;
 }

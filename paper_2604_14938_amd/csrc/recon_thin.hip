@@ -33,13 +33,17 @@
 //     through LDS and their sums gathered loop by loop in a second pass over
 //     the faces.
 //
-// Search: the same bracket invariant, estimates (regula falsi with the
-// Illinois weight, inverse quadratic interpolation, bisection after a slow
-// update) and stopping rule as the wavefront kernel, one evaluation per
-// step; a narrowed bracket [h_lo, h_hi] is first checked with two
-// evaluations at its ends, kept when they straddle the root and otherwise
-// replaced by the part of the full bracket beyond the failed end (status
-// LEARNED_FALLBACK).
+// Search: Brent's method (Brent 1973, ch. 4) on r(s) = V(s)/V_P - alpha
+// over a bracket of [phi_min, phi_max] whose ends straddle the root: inverse
+// quadratic interpolation or the secant, the midpoint when the estimate
+// leaves the quarter of the bracket next to its better end or does not
+// shrink fast enough; one evaluation per step, the stopping rule of the
+// wavefront kernel.  A narrowed bracket [h_lo, h_hi] is first checked with
+// two evaluations: at its centre (the network's predicted isovalue), whose
+// residual gives the side of the root, and at its end on that side.  The
+// half on the root's side starts the method when that end is past the root;
+// otherwise the part of the full bracket beyond that end does (status
+// LEARNED_FALLBACK: the root is outside the bracket).
 //
 // Scheduling: a wavefront takes 64/G consecutive mixed entries (a batch),
 // stages them together, runs their searches side by side until the last one
@@ -132,14 +136,32 @@ __device__ __forceinline__ double iqi1(double x0, double f0, double x1, double f
 // The staged cells of one wavefront, item-major and cell-slot-minor; the
 // 4- and 8-byte arrays have an odd slot stride CP, so the lanes of a group,
 // which read different items of one cell, spread over the LDS banks.
+// Network scratch of a wavefront (learned form): one BF16 input row per cell
+// slot (16 rows at least: a tile), one 16-row tile of hidden activations and
+// the first output per slot.
+template <int C>
+struct ThinNet {
+  static constexpr int R = C < 16 ? 16 : C;
+  alignas(16) uint16_t x[R][net::kIn];
+  alignas(16) uint16_t h[16][net::kHid];
+  float u[R];
+};
+
 template <int C, int NV, int NF, int NL, int NE>
 struct ThinMem {
   static constexpr int CP = C | 1;
   double X[3][NV][CP];  // vertex positions relative to the cell centroid
   double phi[NV][CP];   // vertex field
   double D[NE][CP];     // volume term of an edge taken whole by both of its faces
-  double fr[NE][CP];    // liquid fraction of each cut edge (this evaluation)
-  int32_t cnt[NF][CP];  // crossings of each face (this evaluation)
+  // scratch of one evaluation; outside evaluations (the network phase of the
+  // learned form) the same bytes hold the network's rows
+  union {
+    struct {
+      double fr[NE][CP];    // liquid fraction of each cut edge (this evaluation)
+      int32_t cnt[NF][CP];  // crossings of each face (this evaluation)
+    };
+    ThinNet<C> net;
+  };
   uint8_t eu[NE][C], ev[NE][C];    // end vertices of each edge
   uint8_t ef1[NE][C], ef2[NE][C];  // face whose loop runs eu -> ev, and the other face
   uint8_t fx[NF][C], fn[NF][C];    // exit and entry edge of a face with two crossings
@@ -374,19 +396,6 @@ __device__ CutRes thin_eval(TM &M, int sl, int q, int nf, int ne, double s, cons
 }
 
 
-// Network scratch of a wavefront (learned form): one BF16 input row per cell
-// slot (16 rows at least: a tile), one 16-row tile of hidden activations and
-// the first output per slot.
-template <int C>
-struct ThinNet {
-  static constexpr int R = C < 16 ? 16 : C;
-  alignas(16) uint16_t x[R][net::kIn];
-  alignas(16) uint16_t h[16][net::kHid];
-  float u[R];
-};
-struct ThinNoNet {
-  int unused;
-};
 
 // Forward pass of the wavefront's rows on v_mfma_f32_16x16x16_bf16 tiles, all
 // 64 lanes, 16 rows per tile (BF16 weights and activations, FP32
@@ -403,7 +412,7 @@ __device__ void net_tiles(ThinNet<C> &T, const uint16_t *wb, const float *master
         acc = mfma16(*reinterpret_cast<const bf16x4 *>(&T.x[t0 + col][kt * 16 + rq]),
                      b_weightT(wb + oW1, kIn, lane, nt * 16, kt * 16, kHid), acc);
       const float b = master[oB1 + nt * 16 + col];
-      for (int j = 0; j < 4; ++j) T.h[rq + j][nt * 16 + col] = to_bf16(tanhf(acc[j] + b));
+      for (int j = 0; j < 4; ++j) T.h[rq + j][nt * 16 + col] = to_bf16(act_tanh(acc[j] + b));
     }
     wave_sync();
     f32x4 acc2[kHid / 16];
@@ -416,7 +425,7 @@ __device__ void net_tiles(ThinNet<C> &T, const uint16_t *wb, const float *master
     wave_sync();
     for (int nt = 0; nt < kHid / 16; ++nt) {
       const float b = master[oB2 + nt * 16 + col];
-      for (int j = 0; j < 4; ++j) T.h[rq + j][nt * 16 + col] = to_bf16(tanhf(acc2[nt][j] + b));
+      for (int j = 0; j < 4; ++j) T.h[rq + j][nt * 16 + col] = to_bf16(act_tanh(acc2[nt][j] + b));
     }
     wave_sync();
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -479,27 +488,29 @@ __device__ void cell_features(TM &M, ThinNet<C> &T, int sl, int q, const ReconPa
   lsum = tsum<G>(lsum);
   wave_sync();
   auto sorted = [&](int r) { return M.phi[M.link[r][sl]][sl]; };
-  for (int i = q; i < net::kIn; i += G)
-    T.x[sl][i] = net::to_bf16(net::feature(i, a, sorted, nv, lsum, pmin, Wd, t, amin, amax, nf));
+  // every feature index unrolled, each taken by the lane it falls to: the
+  // sums t stay in registers (a runtime index would put them in scratch)
+#pragma unroll
+  for (int i = 0; i < net::kIn; ++i)
+    if (i % G == q) T.x[sl][i] = net::to_bf16(net::feature(i, a, sorted, nv, lsum, pmin, Wd, t, amin, amax, nf));
 }
 
-template <int G, int NV, int NF, int NL, int NE, bool NET>
-using NetMem = typename std::conditional<NET, ThinNet<64 / G>, ThinNoNet>::type;
-
-// Waves per SIMD a build's register budget is sized for: what its LDS
-// allows, at most 3 (about 168 VGPRs, the size of the search state and one
-// face walk without spills; a 4-wave budget of 128 VGPRs spills).
+// Waves per SIMD a build's register budget is sized for: enough for every
+// wave its LDS lets a CU hold (rounded up over the four SIMDs), at most 3
+// (168 VGPRs: the search state and one face walk fit without spills; a
+// 4-wave budget of 128 VGPRs spills).  The learned builds are held to the
+// same budget: what does not fit spills in the staging and network phases,
+// once per batch, not in the search.
 constexpr int thin_occupancy(int bytes) {
-  return (160 * 1024) / bytes >= 12 ? 3 : ((160 * 1024) / bytes >= 4 ? (160 * 1024) / bytes / 4 : 1);
+  return (160 * 1024) / bytes >= 9 ? 3 : ((160 * 1024) / bytes + 3) / 4;
 }
 
 template <int G, int NV, int NF, int NL, int NE, bool NET>
-__global__ __launch_bounds__(64, (thin_occupancy((int)(sizeof(ThinMem<64 / G, NV, NF, NL, NE>) +
-                                                       (NET ? sizeof(ThinNet<64 / G>) : 0)))))
+__global__ __launch_bounds__(64, (thin_occupancy((int)sizeof(ThinMem<64 / G, NV, NF, NL, NE>))))
 void recon_thin_kernel(ReconParams p) {
   constexpr int C = 64 / G;
   __shared__ ThinMem<C, NV, NF, NL, NE> M;
-  __shared__ NetMem<G, NV, NF, NL, NE, NET> T;
+  ThinNet<C> &T = M.net;
   const int lane = threadIdx.x, sl = lane / G, q = lane % G;
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells;
@@ -507,10 +518,6 @@ void recon_thin_kernel(ReconParams p) {
   int64_t count = p.entries ? (int64_t)*p.entry_count : (int64_t)p.counts[0];
   if (count > cap) count = cap;
   const int64_t nbatch = (count + C - 1) / C;
-  if constexpr (NET) {
-    // rows of a tile beyond the wavefront's cells stay zero
-    for (int i = lane; i < (ThinNet<C>::R - C) * net::kIn; i += 64) T.x[C + i / net::kIn][i % net::kIn] = 0;
-  }
   for (int64_t bt = blockIdx.x; bt < nbatch;) {
     const int64_t j = bt * C + sl;
     const bool active = j < count;
@@ -541,56 +548,149 @@ void recon_thin_kernel(ReconParams p) {
       } else {
         const double xP0 = m.xc[P], xP1 = m.xc[N + P], xP2 = m.xc[2 * N + P];
         VP = m.V[P];
-        // ---- stage the polyhedron: vertices (inverse-distance vertex field,
-        // incidences read four at a time and summed in order), loop positions
-        // and face offsets
+        // ---- stage the polyhedron: loop positions, face offsets and edges,
+        // and the vertices with the inverse-distance vertex field.  The
+        // loads of each part are issued together (topology into registers
+        // first, then the vertices level by level: ids, positions and
+        // incidence ranges, incidences, neighbour alphas), so their
+        // latencies overlap instead of adding up.
+        // (builds whose topology takes more than 40 registers per lane store
+        // it straight to LDS after the vertices instead)
+        constexpr int KL = (NL + G - 1) / G, KF = (NF + G - 1) / G, KE = (NE + G - 1) / G;
+        constexpr bool kPre = 2 * KL + 2 * KF + KE <= 40;
+        constexpr int KV = (NV + G - 1) / G < 2 ? (NV + G - 1) / G : 2;   // vertices per lane per round
+        uint8_t tl[kPre ? KL : 1], te[kPre ? KL : 1], tfo[kPre ? KF : 1], tfs[kPre ? KF : 1];
+        uint32_t tw[kPre ? KE : 1];
+        if constexpr (kPre) {
+#pragma unroll
+        for (int t = 0; t < KL; ++t) {
+          const int i = q + t * G;
+          tl[t] = i < nl ? m.cl_lv[l0 + i] : (uint8_t)0;
+          te[t] = i < nl ? (uint8_t)m.cl_eid[l0 + i] : (uint8_t)0;
+        }
+#pragma unroll
+        for (int t = 0; t < KF; ++t) {
+          const int f = q + t * G;
+          tfo[t] = f < nf ? (uint8_t)m.cf_loff[f0 + f] : (uint8_t)0;
+          tfs[t] = f < nf ? m.cf_lsz[f0 + f] : (uint8_t)0;
+        }
+#pragma unroll
+        for (int t = 0; t < KE; ++t) {
+          const int e = q + t * G;
+          tw[t] = e < ne ? m.ce[(l0 >> 1) + e] : 0u;
+        }
+        }
         double lo_phi = __builtin_inf(), hi_phi = -__builtin_inf();
-        for (int i = q; i < nv; i += G) {
-          const int gv = m.cv_gid[v0 + i];
-          M.X[0][i][sl] = m.xyz[gv] - xP0;
-          M.X[1][i][sl] = m.xyz[m.n_verts + gv] - xP1;
-          M.X[2][i][sl] = m.xyz[2 * m.n_verts + gv] - xP2;
-          double ph;
-          if (p.phi_override) {
-            ph = p.phi_override[gv];
-          } else {
-            const double *w = p.vertex_mode ? m.vc_wmean : m.vc_w;
-            ph = 0.0;
-            const int64_t j1 = m.vc_off[gv + 1];
-            for (int64_t jj = m.vc_off[gv]; jj < j1; jj += 4) {
-              int cc[4];
-              double ww[4], aa[4];
+        const double *w = p.vertex_mode ? m.vc_wmean : m.vc_w;
+        for (int i0 = q; i0 < nv; i0 += KV * G) {
+          int gv[KV];
+          int64_t jb[KV], je[KV];
+          double px[KV], py[KV], pz[KV], ph[KV];
 #pragma unroll
-              for (int t = 0; t < 4; ++t) {
-                const bool in = jj + t < j1;
-                cc[t] = in ? m.vc_cell[jj + t] : 0;
-                ww[t] = in ? w[jj + t] : 0.0;
-              }
+          for (int t = 0; t < KV; ++t) {
+            const int i = i0 + t * G;
+            gv[t] = i < nv ? m.cv_gid[v0 + i] : -1;
+          }
 #pragma unroll
-              for (int t = 0; t < 4; ++t) aa[t] = (jj + t < j1) ? p.alpha[cc[t]] : 0.0;
-#pragma unroll
-              for (int t = 0; t < 4; ++t)
-                if (jj + t < j1) ph += ww[t] * aa[t];
+          for (int t = 0; t < KV; ++t) {
+            const bool in = gv[t] >= 0;
+            px[t] = in ? m.xyz[gv[t]] : 0.0;
+            py[t] = in ? m.xyz[m.n_verts + gv[t]] : 0.0;
+            pz[t] = in ? m.xyz[2 * m.n_verts + gv[t]] : 0.0;
+            ph[t] = 0.0;
+            if (p.phi_override) {
+              ph[t] = in ? p.phi_override[gv[t]] : 0.0;
+              jb[t] = je[t] = 0;
+            } else {
+              jb[t] = in ? m.vc_off[gv[t]] : 0;
+              je[t] = in ? m.vc_off[gv[t] + 1] : 0;
             }
           }
-          M.phi[i][sl] = ph;
-          lo_phi = fmin(lo_phi, ph);
-          hi_phi = fmax(hi_phi, ph);
+          // incidences four at a time for every vertex of the round, summed
+          // in order
+          bool more = true;
+          for (int c4 = 0; more; c4 += 4) {
+            int cc[KV][4];
+            double ww[KV][4], aa[KV][4];
+#pragma unroll
+            for (int t = 0; t < KV; ++t)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int64_t jj = jb[t] + c4 + u;
+                const bool in = jj < je[t];
+                cc[t][u] = in ? m.vc_cell[jj] : 0;
+                ww[t][u] = in ? w[jj] : 0.0;
+              }
+#pragma unroll
+            for (int t = 0; t < KV; ++t)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) aa[t][u] = (jb[t] + c4 + u < je[t]) ? p.alpha[cc[t][u]] : 0.0;
+            more = false;
+#pragma unroll
+            for (int t = 0; t < KV; ++t) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (jb[t] + c4 + u < je[t]) ph[t] += ww[t][u] * aa[t][u];
+              more = more || jb[t] + c4 + 4 < je[t];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < KV; ++t) {
+            const int i = i0 + t * G;
+            if (i < nv) {
+              M.X[0][i][sl] = px[t] - xP0;
+              M.X[1][i][sl] = py[t] - xP1;
+              M.X[2][i][sl] = pz[t] - xP2;
+              M.phi[i][sl] = ph[t];
+              lo_phi = fmin(lo_phi, ph[t]);
+              hi_phi = fmax(hi_phi, ph[t]);
+            }
+          }
         }
-        for (int i = q; i < nl; i += G) {
-          M.lv[i][sl] = m.cl_lv[l0 + i];
-          M.eid[i][sl] = (uint8_t)m.cl_eid[l0 + i];
-        }
-        for (int f = q; f < nf; f += G) {
-          M.foff[f][sl] = (uint8_t)m.cf_loff[f0 + f];
-          M.fsz[f][sl] = m.cf_lsz[f0 + f];
-        }
-        for (int e = q; e < ne; e += G) {
-          const uint32_t w = m.ce[(l0 >> 1) + e];
-          M.eu[e][sl] = (uint8_t)(w & 0xffu);
-          M.ev[e][sl] = (uint8_t)((w >> 8) & 0xffu);
-          M.ef1[e][sl] = (uint8_t)((w >> 16) & 0xffu);
-          M.ef2[e][sl] = (uint8_t)(w >> 24);
+        if constexpr (kPre) {
+#pragma unroll
+          for (int t = 0; t < KL; ++t) {
+            const int i = q + t * G;
+            if (i < nl) {
+              M.lv[i][sl] = tl[t];
+              M.eid[i][sl] = te[t];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < KF; ++t) {
+            const int f = q + t * G;
+            if (f < nf) {
+              M.foff[f][sl] = tfo[t];
+              M.fsz[f][sl] = tfs[t];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < KE; ++t) {
+            const int e = q + t * G;
+            if (e < ne) {
+              const uint32_t wv = tw[t];
+              M.eu[e][sl] = (uint8_t)(wv & 0xffu);
+              M.ev[e][sl] = (uint8_t)((wv >> 8) & 0xffu);
+              M.ef1[e][sl] = (uint8_t)((wv >> 16) & 0xffu);
+              M.ef2[e][sl] = (uint8_t)(wv >> 24);
+            }
+          }
+        } else {
+          for (int i = q; i < nl; i += G) {
+            M.lv[i][sl] = m.cl_lv[l0 + i];
+            M.eid[i][sl] = (uint8_t)m.cl_eid[l0 + i];
+          }
+          for (int f = q; f < nf; f += G) {
+            M.foff[f][sl] = (uint8_t)m.cf_loff[f0 + f];
+            M.fsz[f][sl] = m.cf_lsz[f0 + f];
+          }
+          for (int e = q; e < ne; e += G) {
+            const uint32_t wv = m.ce[(l0 >> 1) + e];
+            M.eu[e][sl] = (uint8_t)(wv & 0xffu);
+            M.ev[e][sl] = (uint8_t)((wv >> 8) & 0xffu);
+            M.ef1[e][sl] = (uint8_t)((wv >> 16) & 0xffu);
+            M.ef2[e][sl] = (uint8_t)(wv >> 24);
+          }
         }
         wave_sync();
         // the whole-edge volume term of each edge: its two faces' fan terms,
@@ -650,10 +750,13 @@ void recon_thin_kernel(ReconParams p) {
     }
     // ---- phase 2: the narrowed bracket of every cell with a vertex field,
     // from the network (run on the wavefront's cells together) or the caller
-    double hl = 0.0, hh = 0.0;
+    double hl = 0.0, hh = 0.0, hm = 0.0;
     bool hint = false;
     if constexpr (NET) {
       const bool row = active && have_field && st == VOFPC_CELL_OK;   // degenerate fields skip the network
+      // rows of a tile beyond the wavefront's cells are zero (the bytes are
+      // the evaluations' scratch in between)
+      for (int i = lane; i < (ThinNet<C>::R - C) * net::kIn; i += 64) T.x[C + i / net::kIn][i % net::kIn] = 0;
       if (row) {
         cell_features<G>(M, T, sl, q, p, P, a, nv, nf, f0, pmin, pmax - pmin);
       } else {
@@ -676,6 +779,7 @@ void recon_thin_kernel(ReconParams p) {
           hl = hl > pmin ? hl : pmin;
           hh = hh < pmax ? hh : pmax;
           if (hl > hh) { hl = pmin; hh = pmax; }
+          hm = sh < hl ? hl : (sh > hh ? hh : sh);
           hint = true;
         } else if (q == 0 && p.net_lo) {
           p.net_lo[k] = __builtin_nan("");
@@ -694,6 +798,7 @@ void recon_thin_kernel(ReconParams p) {
           hl = hl > pmin ? hl : pmin;
           hh = hh < pmax ? hh : pmax;
           if (hl > hh) { hl = pmin; hh = pmax; }
+          hm = hl + (hh - hl) / 2.0;
           hint = true;
         }
       }
@@ -717,54 +822,130 @@ void recon_thin_kernel(ReconParams p) {
             ref[2] = M.X[2][cand][sl];
           }
           // One evaluation site; the phase decides where the next one is:
-          // the fixed isovalue, the two ends of a narrowed bracket, the search
-          // estimate, or the bracket end kept when the search cannot stop.
-          enum { kFixed, kHintLo, kHintHi, kSearch, kFinal };
+          // the fixed isovalue, the centre of a narrowed bracket and then its
+          // end on the root's side, the search estimate, or the bracket end
+          // kept when the search cannot stop.
+          enum { kFixed, kHintMid, kHintEnd, kSearch, kFinal };
           CutRes c;
           c.err = false;
           double s = __builtin_nan("");
-          double lo = pmin, hi = pmax, rlo = 1.0 - a, rhi = -a, rl = 0.0;
+          double lo = pmin, hi = pmax, rlo = 1.0 - a, rhi = -a, rm = 0.0;
           const double iVP = 1.0 / VP;
           const double tol = p.tol_rel * (a < 1.0 - a ? a : 1.0 - a);
-          double s3 = 0, r3 = 0;   // third point for inverse quadratic interpolation
-          bool have3 = false, collapsed = false, take_lo = false;
-          int kept = 0;            // > 0: lo kept that many updates in a row, < 0: hi
-          bool slow = false;       // the last update did not halve the bracket
-          int ph = p.fixed_iso ? kFixed : (hint ? kHintLo : kSearch);
+          // Brent's method (Brent 1973, ch. 4) on the residual r(s) = V(s)/V_P - alpha:
+          // xb is the bracket end of smaller |r|, xa the other end, xc the
+          // previous xb, xd the one before; the estimate is inverse quadratic
+          // interpolation through (xa, xb, xc) when the three residuals differ,
+          // else the secant through xa and xb, replaced by the midpoint when it
+          // falls outside the quarter of the bracket next to xb or does not
+          // shrink fast enough against the previous steps.
+          double xa = 0, fa = 0, xb = 0, fb = 0, xc = 0, fc = 0, xd = 0;
+          bool bis = true, started = false, collapsed = false;
+          // a jump of V: where a face with four or more crossings switches its
+          // pairing (at its vertex-value mean) or a loop pinches at a vertex
+          // (at that vertex's value), V may step over alpha V_P and the search
+          // bisects down to two ulps.  From the second bisection step in a row
+          // on a bracket narrower than a hundredth of [phi_min, phi_max], such
+          // a value inside the bracket (the one nearest the bisection point)
+          // is cut instead, then the adjacent double on the root's side: a
+          // sign change between the two pins the bracket to one ulp (at most
+          // four tries per cell).
+          double xj = 0.0, rlast = 0.0;
+          int jtries = 0, nbis = 0;
+          bool jnext = false;
+          int ph = p.fixed_iso ? kFixed : (hint ? kHintMid : kSearch);
           while (true) {
             double se = 0.0;
             if (ph == kSearch) {
-              const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
-              if (hi - lo <= 2.0 * ulp_of(big)) {
+              if (!started) {
+                // the bracket [lo, hi] (full, or what the narrowed bracket's
+                // check left) starts the method
+                xa = lo; fa = rlo; xb = hi; fb = rhi;
+                if (fabs(fa) < fabs(fb)) {
+                  xa = hi; fa = rhi; xb = lo; fb = rlo;
+                }
+                xc = xa; fc = fa; xd = xa;
+                bis = true;
+                started = true;
+              }
+              const double big = fabs(xa) > fabs(xb) ? fabs(xa) : fabs(xb);
+              if (fabs(xb - xa) <= 2.0 * ulp_of(big)) {
                 collapsed = true;
                 ph = kFinal;
               } else if (it >= p.max_iter) {
                 st = VOFPC_CELL_MAX_ITER;
                 ph = kFinal;
               } else {
-                const double w0 = hi - lo;
-                const double fl = kept >= 2 ? 0.5 * rlo : rlo, fh = kept <= -2 ? 0.5 * rhi : rhi;
-                se = lo + w0 * qdiv(fl, fl - fh);
-                if (have3 && kept > -2 && kept < 2) {
-                  const double qv = iqi1(lo, rlo, hi, rhi, s3, r3);
-                  if (qv > lo && qv < hi) se = qv;
+                const double blo = xa < xb ? xa : xb, bhi = xa < xb ? xb : xa;
+                bool pinned = false;
+                if (jnext) {
+                  // the double next to the tried face mean, on the root's side
+                  jnext = false;
+                  const double nb = rlast > 0 ? nextafter(xj, __builtin_inf()) : nextafter(xj, -__builtin_inf());
+                  if (nb > blo && nb < bhi) {
+                    se = nb;
+                    pinned = true;
+                  }
                 }
-                if (slow || !(se > lo && se < hi)) se = lo + w0 / 2.0;
-                if (!(se > lo && se < hi)) {
-                  collapsed = true;
-                  ph = kFinal;
+                if (!pinned) {
+                  if (fa != fc && fb != fc) se = iqi1(xa, fa, xb, fb, xc, fc);
+                  else se = xb - fb * qdiv(xb - xa, fb - fa);
+                  const double q0 = (3.0 * xa + xb) * 0.25;
+                  const bool inside = q0 < xb ? (se > q0 && se < xb) : (se > xb && se < q0);
+                  const double du = 4.0 * ulp_of(xb);
+                  const double lastd = bis ? fabs(xb - xc) : fabs(xc - xd);
+                  if (!inside || fabs(se - xb) >= 0.5 * lastd || lastd < du) {
+                    se = xa + (xb - xa) * 0.5;
+                    bis = true;
+                  } else {
+                    bis = false;
+                  }
+                  nbis = bis ? nbis + 1 : 0;
+                  if (nbis >= 2 && it > 0 && jtries < 4 && bhi - blo <= 0.01 * (pmax - pmin)) {
+                    // candidates: the means of the faces with four or more
+                    // crossings at the last evaluation, and the vertex values
+                    const double mid = se;
+                    double bd = __builtin_inf(), bv = __builtin_inf();
+                    for (int f = q; f < nf; f += G) {
+                      if (M.cnt[f][sl] < 4) continue;
+                      const int o = M.foff[f][sl], n = M.fsz[f][sl];
+                      double fm = 0.0;
+                      for (int k2 = 0; k2 < n; ++k2) fm += M.phi[M.lv[o + k2][sl]][sl];
+                      const double sj = fm / (double)n;
+                      const double d = fabs(sj - mid);
+                      if (sj > blo && sj < bhi && sj != xj && (d < bd || (d == bd && sj < bv))) {
+                        bd = d;
+                        bv = sj;
+                      }
+                    }
+                    for (int i = q; i < nv; i += G) {
+                      const double sj = M.phi[i][sl];
+                      const double d = fabs(sj - mid);
+                      if (sj > blo && sj < bhi && sj != xj && (d < bd || (d == bd && sj < bv))) {
+                        bd = d;
+                        bv = sj;
+                      }
+                    }
+                    const double bdm = tmin<G>(bd);
+                    const double cj = tmin<G>(bd == bdm ? bv : __builtin_inf());
+                    if (cj < __builtin_inf()) {
+                      se = cj;
+                      xj = cj;
+                      jnext = true;
+                      ++jtries;
+                    }
+                  }
                 }
               }
             }
             if (ph == kFinal) {
-              take_lo = fabs(rlo) <= fabs(rhi);
-              se = take_lo ? lo : hi;
+              se = xb;
             } else if (ph == kFixed) {
               se = p.iso;
-            } else if (ph == kHintLo) {
-              se = hl;
-            } else if (ph == kHintHi) {
-              se = hh;
+            } else if (ph == kHintMid) {
+              se = hm;
+            } else if (ph == kHintEnd) {
+              se = rm > 0 ? hh : hl;
             }
             const CutRes cf = thin_eval<G>(M, sl, q, nf, ne, se, ref);
             ++it;
@@ -772,41 +953,54 @@ void recon_thin_kernel(ReconParams p) {
             if (ph == kFixed || ph == kFinal || fabs(r) <= tol) {
               s = se;
               c = cf;
-              if (ph == kFinal && collapsed && fabs(take_lo ? rlo : rhi) > 1e-10) st = VOFPC_CELL_NO_ROOT;
+              if (ph == kFinal && collapsed && fabs(fb) > 1e-10) st = VOFPC_CELL_NO_ROOT;
               break;
             }
-            if (ph == kHintLo) {
-              rl = r;
-              ph = kHintHi;
+            if (ph == kHintMid) {
+              // the residual at the centre tells the side of the root: that
+              // half of the bracket is checked by a cut at its end
+              rm = r;
+              if (r > 0) {
+                lo = se; rlo = r;
+              } else {
+                hi = se; rhi = r;
+              }
+              if ((r > 0 ? hh : hl) == se) {
+                // the centre is the end: the root lies beyond it
+                if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+                ph = kSearch;
+              } else {
+                ph = kHintEnd;
+              }
               continue;
             }
-            if (ph == kHintHi) {
-              // the narrowed bracket holds when its ends straddle the root;
-              // otherwise the root lies beyond the end that failed
-              if (rl > 0 && r < 0) {
-                lo = hl; rlo = rl; hi = hh; rhi = r;
-              } else if (rl <= 0) {
-                hi = hl; rhi = rl;
-                if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
+            if (ph == kHintEnd) {
+              // the bracket holds when its end is past the root; otherwise the
+              // root lies beyond that end
+              const bool up = rm > 0;
+              if (up ? r < 0 : r > 0) {
+                if (up) { hi = se; rhi = r; } else { lo = se; rlo = r; }
               } else {
-                lo = hh; rlo = r;
+                if (up) { lo = se; rlo = r; } else { hi = se; rhi = r; }
                 if (st == VOFPC_CELL_OK) st = VOFPC_CELL_LEARNED_FALLBACK;
               }
               ph = kSearch;
               continue;
             }
-            const double w0 = hi - lo;
-            if (r > 0) {
-              s3 = lo; r3 = rlo;
-              lo = se; rlo = r;
-              kept = kept <= 0 ? kept - 1 : -1;
+            // keep the end across the root from the estimate; xb the end of
+            // smaller residual
+            rlast = r;
+            xd = xc;
+            xc = xb; fc = fb;
+            if ((fa > 0) != (r > 0)) {
+              xb = se; fb = r;
             } else {
-              s3 = hi; r3 = rhi;
-              hi = se; rhi = r;
-              kept = kept >= 0 ? kept + 1 : 1;
+              xa = se; fa = r;
             }
-            have3 = true;
-            slow = (hi - lo) > 0.5 * w0;
+            if (fabs(fa) < fabs(fb)) {
+              const double tx = xa, tf = fa;
+              xa = xb; fa = fb; xb = tx; fb = tf;
+            }
           }
           const bool cut_ok = true;
           if (cut_ok && c.err) {
@@ -882,7 +1076,7 @@ vofpc_status launch_t(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries) {
 struct ThinCaps {
   int nv, nf, nl, ne;
 };
-constexpr ThinCaps kHex{8, 6, 24, 12}, kC0{16, 8, 48, 24}, kC1{48, 32, 128, 64};
+constexpr ThinCaps kHex{8, 6, 24, 12}, kC0{16, 8, 48, 24}, kC1{32, 20, 96, 48}, kC2{48, 32, 128, 64};
 
 __host__ bool fits(const ThinCaps &t, const int64_t cmax[4]) {
   return cmax[0] <= t.nv && cmax[1] <= t.nf && cmax[2] <= t.nl && cmax[3] <= t.ne;
@@ -893,6 +1087,7 @@ __host__ bool fits(const ThinCaps &t, const int64_t cmax[4]) {
 bool thin_available(int c, int G, const int64_t cmax[4]) {
   if (c == 0) return fits(kHex, cmax) ? (G == 1 || G == 2 || G == 4) : ((G == 2 || G == 4) && fits(kC0, cmax));
   if (c == 1) return (G == 4 || G == 8 || G == 16) && fits(kC1, cmax);
+  if (c == 2) return (G == 4 || G == 8 || G == 16) && fits(kC2, cmax);
   return false;
 }
 
@@ -908,9 +1103,14 @@ vofpc_status launch_thin(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries,
     if (G == 2) return launch_t<2, kC0.nv, kC0.nf, kC0.nl, kC0.ne>(ctx, p, n_entries);
     return launch_t<4, kC0.nv, kC0.nf, kC0.nl, kC0.ne>(ctx, p, n_entries);
   }
-  if (G == 4) return launch_t<4, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
-  if (G == 8) return launch_t<8, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
-  return launch_t<16, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
+  if (c == 1) {
+    if (G == 4) return launch_t<4, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
+    if (G == 8) return launch_t<8, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
+    return launch_t<16, kC1.nv, kC1.nf, kC1.nl, kC1.ne>(ctx, p, n_entries);
+  }
+  if (G == 4) return launch_t<4, kC2.nv, kC2.nf, kC2.nl, kC2.ne>(ctx, p, n_entries);
+  if (G == 8) return launch_t<8, kC2.nv, kC2.nf, kC2.nl, kC2.ne>(ctx, p, n_entries);
+  return launch_t<16, kC2.nv, kC2.nf, kC2.nl, kC2.ne>(ctx, p, n_entries);
 }
 
 }  // namespace vofpc

@@ -1,7 +1,8 @@
 """GPU parity of every reconstruction kernel flavour (tile shape) the tuner
 can pick: one cell per wavefront (3 or 4 waves per SIMD) and G lanes per cell
-(G = 1, 2, 4 for class 0, 4, 8, 16 for class 1), each forced through
-vofpc_mesh_set_tune and compared with the oracle to the parity bar."""
+(G = 1, 2, 4 for class 0, 4, 8, 16 for the Voronoi classes 1 and 2), each
+forced through vofpc_mesh_set_tune and compared with the oracle to the parity
+bar."""
 import sys
 
 import numpy as np
@@ -14,7 +15,7 @@ from tests import parity
 pytestmark = pytest.mark.gpu
 
 C0 = [3, 4, 11, 12, 14]      # class 0 (hexahedra and smaller cells)
-C1 = [3, 4, 14, 18, 26]      # class 1 (Voronoi cells)
+C1 = [3, 4, 14, 18, 26]      # classes 1 and 2 (Voronoi cells)
 
 
 def _say(msg):
@@ -62,10 +63,11 @@ def _wl(name):
 
 
 def _tune_for(run, f0, f1):
+    """Flavour f0 for class 0, f1 for the Voronoi classes 1 and 2."""
     cls = run.mesh.classes()
-    t = [f0 if cls["cells"][0] else 3, f1 if cls["cells"][1] else 3, 3, 3]
+    t = [f0 if cls["cells"][0] else 3, f1 if cls["cells"][1] else 3, f1 if cls["cells"][2] else 3, 3]
     run.mesh.set_tune(t)
-    assert run.mesh.classes()["tune"][:2] == t[:2]
+    assert run.mesh.classes()["tune"][:3] == t[:3]
     return cls
 
 
@@ -110,7 +112,8 @@ def test_class1_flavours_match_the_oracle(runner, name, f):
     _say(f"flavour {f} on {name}: {wl.n_mixed} mixed")
     run = runner.PathRun(wl)
     cls = _tune_for(run, 3, f)
-    assert not cls["bucketed"] and run.mesh.classes()["tune"][1] == f
+    assert cls["cells"][1] > 0.9 * wl.mesh.n_cells and cls["cells"][3] == 0, cls
+    assert run.mesh.classes()["tune"][1] == f
     run.step()
     g = run.results()
     rep = _check_step(wl, g, _ref(name, wl))
@@ -136,10 +139,11 @@ def test_bucketed_batch_with_group_flavours(runner, f0, f1):
 
 
 @pytest.mark.parametrize("f", [14, 18, 26])
-def test_hint_bracket_checked_at_both_ends(V, runner, f):
+def test_hint_bracket_checked_with_two_cuts(V, runner, f):
     """A narrowed bracket per cell (good for most cells, off by 0.02 for every
-    fifth): both ends are cut first; the statuses (LEARNED_FALLBACK where the
-    ends do not straddle the root) and results equal the oracle's hint path."""
+    fifth): its centre and the end on the root's side are cut first; the
+    statuses (LEARNED_FALLBACK where the root is outside the bracket) and
+    results equal the oracle's hint path, which cuts both ends."""
     import torch
     wl = _wl("vor12")
     om = oracle.OMesh(wl.mesh)

@@ -346,7 +346,7 @@ def _prism_workload(sides, layers=12, fan=False, tilt=0.3):
     return wl, parts
 
 
-@pytest.mark.parametrize("sides,fan", [((4, 8, 24, 40, 64), False), ((64,), False), ((80,), True)])
+@pytest.mark.parametrize("sides,fan", [((4, 8, 20, 40, 64), False), ((64,), False), ((80,), True)])
 def test_large_cells_use_the_wide_kernel_variants(V, runner, sides, fan):
     """Cells beyond the Voronoi sizes (n-gon faces up to 64 vertices, up to
     162 vertices and 240 faces per cell) run in the wide kernel variants,
