@@ -1287,9 +1287,46 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
     if (timed)
       for (int c = 0; c < kClasses; ++c) ctx->cls_rec[c] = false;
   }
+  // learned form in a group build whose wavefronts hold fewer than 16 cells
+  // (G = 8, 16: classes 1 and 2): the brackets come from a pass of their own
+  // with full network tiles, and the class kernel checks them as a caller's
+  // brackets (the same check and flag)
+  auto pass_first = [&](int c) {
+    const int f = M->tune[c];
+    return p.net_wb != nullptr && (c == 1 || c == 2) && (f == VOFPC_FLAVOUR_GROUP(8) || f == VOFPC_FLAVOUR_GROUP(16));
+  };
+  bool any_pass = false;
+  for (int c = 0; c < kClasses; ++c)
+    any_pass = any_pass || ((M->bucketed ? M->class_cells[c] > 0 : c == M->max_class) && pass_first(c));
+  if (any_pass && !p.net_lo && !M->hint_buf) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    VOFPC_HIP(hipStreamIsCapturing(ctx->stream, &cs));
+    VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
+                  "reconstruct_learned: the first call on a mesh without hint_lo/hint_hi sets up its bracket "
+                  "buffer and must not be captured");
+    void *b = nullptr;
+    vofpc_status st = mesh_scratch_alloc(M, 2 * sizeof(double) * (size_t)N, &b);
+    if (st) return st;
+    M->hint_buf = (double *)b;
+  }
   auto run_class = [&](int64_t n_cells, int c) -> vofpc_status {
     if (timed) VOFPC_HIP(hipEventRecord(ctx->cls_ev[c][0], ctx->stream));
-    vofpc_status st = launch_class(ctx, M, p, n_cells, c, M->tune[c]);
+    vofpc_status st;
+    if (pass_first(c)) {
+      double *hl = p.net_lo ? p.net_lo : M->hint_buf, *hh = p.net_hi ? p.net_hi : M->hint_buf + N;
+      st = launch_bracket_pass(ctx, p, n_cells, c, hl, hh);
+      if (st) return st;
+      ReconParams q = p;
+      q.net_wb = nullptr;
+      q.net_master = nullptr;
+      q.net_lo = q.net_hi = nullptr;
+      q.use_hint = 1;
+      q.hint_lo = hl;
+      q.hint_hi = hh;
+      st = launch_class(ctx, M, q, n_cells, c, M->tune[c]);
+    } else {
+      st = launch_class(ctx, M, p, n_cells, c, M->tune[c]);
+    }
     if (st) return st;
     if (timed) {
       VOFPC_HIP(hipEventRecord(ctx->cls_ev[c][1], ctx->stream));

@@ -107,5 +107,10 @@ vofpc_status launch_thin(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries,
                          const int64_t cmax[4]);
 // Whether launch_thin has a build for class c with these sizes and G.
 bool thin_available(int c, int G, const int64_t cmax[4]);
+// The learned brackets of the entries of class c (1 or 2) in a pass of their
+// own: 16 cells per wavefront; writes hlo/hhi[k] per mixed entry k (NaN
+// where the cell gets no network).  p carries the network and delta.
+vofpc_status launch_bracket_pass(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries, int c, double *hlo,
+                                 double *hhi);
 
 }  // namespace vofpc

@@ -488,11 +488,108 @@ __device__ void cell_features(TM &M, ThinNet<C> &T, int sl, int q, const ReconPa
   lsum = tsum<G>(lsum);
   wave_sync();
   auto sorted = [&](int r) { return M.phi[M.link[r][sl]][sl]; };
-  // every feature index unrolled, each taken by the lane it falls to: the
-  // sums t stay in registers (a runtime index would put them in scratch)
+  if constexpr (sizeof(T.h) >= sizeof(double) * 18 * C) {
+    // the sums go through LDS (the hidden-layer tile, not yet in use: 18
+    // doubles per cell slot), so each lane computes only its own features
+    // with a runtime index
+    double *ts = reinterpret_cast<double *>(&T.h[0][0]) + 18 * sl;
+    if (q == 0) {
 #pragma unroll
-  for (int i = 0; i < net::kIn; ++i)
-    if (i % G == q) T.x[sl][i] = net::to_bf16(net::feature(i, a, sorted, nv, lsum, pmin, Wd, t, amin, amax, nf));
+      for (int i = 0; i < 18; ++i) ts[i] = t[i];
+    }
+    wave_sync();
+    for (int i = q; i < net::kIn; i += G)
+      T.x[sl][i] = net::to_bf16(net::feature(i, a, sorted, nv, lsum, pmin, Wd, ts, amin, amax, nf));
+    wave_sync();
+  } else {
+    // few lanes per cell: every feature index unrolled, each taken by the
+    // lane it falls to (the sums stay in registers; a runtime index would
+    // put them in scratch)
+#pragma unroll
+    for (int i = 0; i < net::kIn; ++i)
+      if (i % G == q) T.x[sl][i] = net::to_bf16(net::feature(i, a, sorted, nv, lsum, pmin, Wd, t, amin, amax, nf));
+  }
+}
+
+// The cell's vertices (positions relative to xP, when WANT_X) and their
+// inverse-distance vertex field (or the caller's override) into LDS; lane q
+// of a group takes vertices q, q + G, ...  Each lane works KV vertices per
+// round with the loads of a round issued together level by level (vertex
+// ids; positions and incidence ranges; incidences four at a time; neighbour
+// alphas) and sums each vertex's incidences in order.  lo/hi: the lane's
+// smallest and largest vertex value.
+template <int G, int KV, bool WANT_X, class TM>
+__device__ __forceinline__ void stage_vertex_field(TM &M, const DevMesh &m, const ReconParams &p, int sl, int q,
+                                                   int64_t v0, int nv, double xP0, double xP1, double xP2, double &lo,
+                                                   double &hi) {
+  const double *w = p.vertex_mode ? m.vc_wmean : m.vc_w;
+  for (int i0 = q; i0 < nv; i0 += KV * G) {
+    int gv[KV];
+    int64_t jb[KV], je[KV];
+    double px[KV], py[KV], pz[KV], ph[KV];
+#pragma unroll
+    for (int t = 0; t < KV; ++t) {
+      const int i = i0 + t * G;
+      gv[t] = i < nv ? m.cv_gid[v0 + i] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < KV; ++t) {
+      const bool in = gv[t] >= 0;
+      if constexpr (WANT_X) {
+        px[t] = in ? m.xyz[gv[t]] : 0.0;
+        py[t] = in ? m.xyz[m.n_verts + gv[t]] : 0.0;
+        pz[t] = in ? m.xyz[2 * m.n_verts + gv[t]] : 0.0;
+      }
+      ph[t] = 0.0;
+      if (p.phi_override) {
+        ph[t] = in ? p.phi_override[gv[t]] : 0.0;
+        jb[t] = je[t] = 0;
+      } else {
+        jb[t] = in ? m.vc_off[gv[t]] : 0;
+        je[t] = in ? m.vc_off[gv[t] + 1] : 0;
+      }
+    }
+    bool more = true;
+    for (int c4 = 0; more; c4 += 4) {
+      int cc[KV][4];
+      double ww[KV][4], aa[KV][4];
+#pragma unroll
+      for (int t = 0; t < KV; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t jj = jb[t] + c4 + u;
+          const bool in = jj < je[t];
+          cc[t][u] = in ? m.vc_cell[jj] : 0;
+          ww[t][u] = in ? w[jj] : 0.0;
+        }
+#pragma unroll
+      for (int t = 0; t < KV; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) aa[t][u] = (jb[t] + c4 + u < je[t]) ? p.alpha[cc[t][u]] : 0.0;
+      more = false;
+#pragma unroll
+      for (int t = 0; t < KV; ++t) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (jb[t] + c4 + u < je[t]) ph[t] += ww[t][u] * aa[t][u];
+        more = more || jb[t] + c4 + 4 < je[t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KV; ++t) {
+      const int i = i0 + t * G;
+      if (i < nv) {
+        if constexpr (WANT_X) {
+          M.X[0][i][sl] = px[t] - xP0;
+          M.X[1][i][sl] = py[t] - xP1;
+          M.X[2][i][sl] = pz[t] - xP2;
+        }
+        M.phi[i][sl] = ph[t];
+        lo = fmin(lo, ph[t]);
+        hi = fmax(hi, ph[t]);
+      }
+    }
+  }
 }
 
 // Waves per SIMD a build's register budget is sized for: enough for every
@@ -581,72 +678,7 @@ void recon_thin_kernel(ReconParams p) {
         }
         }
         double lo_phi = __builtin_inf(), hi_phi = -__builtin_inf();
-        const double *w = p.vertex_mode ? m.vc_wmean : m.vc_w;
-        for (int i0 = q; i0 < nv; i0 += KV * G) {
-          int gv[KV];
-          int64_t jb[KV], je[KV];
-          double px[KV], py[KV], pz[KV], ph[KV];
-#pragma unroll
-          for (int t = 0; t < KV; ++t) {
-            const int i = i0 + t * G;
-            gv[t] = i < nv ? m.cv_gid[v0 + i] : -1;
-          }
-#pragma unroll
-          for (int t = 0; t < KV; ++t) {
-            const bool in = gv[t] >= 0;
-            px[t] = in ? m.xyz[gv[t]] : 0.0;
-            py[t] = in ? m.xyz[m.n_verts + gv[t]] : 0.0;
-            pz[t] = in ? m.xyz[2 * m.n_verts + gv[t]] : 0.0;
-            ph[t] = 0.0;
-            if (p.phi_override) {
-              ph[t] = in ? p.phi_override[gv[t]] : 0.0;
-              jb[t] = je[t] = 0;
-            } else {
-              jb[t] = in ? m.vc_off[gv[t]] : 0;
-              je[t] = in ? m.vc_off[gv[t] + 1] : 0;
-            }
-          }
-          // incidences four at a time for every vertex of the round, summed
-          // in order
-          bool more = true;
-          for (int c4 = 0; more; c4 += 4) {
-            int cc[KV][4];
-            double ww[KV][4], aa[KV][4];
-#pragma unroll
-            for (int t = 0; t < KV; ++t)
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int64_t jj = jb[t] + c4 + u;
-                const bool in = jj < je[t];
-                cc[t][u] = in ? m.vc_cell[jj] : 0;
-                ww[t][u] = in ? w[jj] : 0.0;
-              }
-#pragma unroll
-            for (int t = 0; t < KV; ++t)
-#pragma unroll
-              for (int u = 0; u < 4; ++u) aa[t][u] = (jb[t] + c4 + u < je[t]) ? p.alpha[cc[t][u]] : 0.0;
-            more = false;
-#pragma unroll
-            for (int t = 0; t < KV; ++t) {
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                if (jb[t] + c4 + u < je[t]) ph[t] += ww[t][u] * aa[t][u];
-              more = more || jb[t] + c4 + 4 < je[t];
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < KV; ++t) {
-            const int i = i0 + t * G;
-            if (i < nv) {
-              M.X[0][i][sl] = px[t] - xP0;
-              M.X[1][i][sl] = py[t] - xP1;
-              M.X[2][i][sl] = pz[t] - xP2;
-              M.phi[i][sl] = ph[t];
-              lo_phi = fmin(lo_phi, ph[t]);
-              hi_phi = fmax(hi_phi, ph[t]);
-            }
-          }
-        }
+        stage_vertex_field<G, KV, true>(M, m, p, sl, q, v0, nv, xP0, xP1, xP2, lo_phi, hi_phi);
         if constexpr (kPre) {
 #pragma unroll
           for (int t = 0; t < KL; ++t) {
@@ -1048,6 +1080,94 @@ void recon_thin_kernel(ReconParams p) {
   }
 }
 
+// ---- the learned bracket in a pass of its own
+// In the builds whose wavefronts hold fewer than 16 cells (G >= 8) the
+// network's 16-row tile would run mostly empty inside the reconstruction.
+// This pass takes 16 cells per wavefront (4 lanes each), stages only their
+// vertex field, computes the features, runs one full tile and writes each
+// entry's bracket [sh - d, sh + d] around the predicted isovalue sh (NaN
+// where the reconstruction would run no network: not mixed, bad input,
+// degenerate field).  The reconstruction then checks it as a caller's
+// bracket.
+template <int NVM>
+struct PassMem {
+  double phi[NVM][17];
+  uint8_t link[NVM][16];
+  ThinNet<16> net;
+};
+
+template <int NVM>
+__global__ __launch_bounds__(64) void bracket_pass_kernel(ReconParams p, double *hlo, double *hhi) {
+  constexpr int G = 4, C = 16;
+  __shared__ PassMem<NVM> M;
+  ThinNet<C> &T = M.net;
+  const int lane = threadIdx.x, sl = lane / G, q = lane % G;
+  const DevMesh &m = p.m;
+  int64_t count = p.entries ? (int64_t)*p.entry_count : (int64_t)p.counts[0];
+  if (count > p.out.cap) count = p.out.cap;
+  const int64_t nbatch = (count + C - 1) / C;
+  for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+    const int64_t j = bt * C + sl;
+    const bool active = j < count;
+    int64_t k = 0, f0 = 0;
+    int P = 0, nf = 0, nv = 0;
+    double a = 0.0, pmin = 0.0, pmax = 0.0;
+    bool row = false;
+    if (active) {
+      k = p.entries ? (int64_t)p.entries[j] : j;
+      P = p.mixed[k];
+      a = p.alpha[P];
+      f0 = m.cell_face_off[P];
+      nf = (int)(m.cell_face_off[P + 1] - f0);
+      const int64_t v0 = m.cv_off[P];
+      nv = (int)(m.cv_off[P + 1] - v0);
+      if (a > p.eps && a < 1.0 - p.eps && nv <= NVM) {   // a NaN alpha fails both tests
+        double lo = __builtin_inf(), hi = -__builtin_inf();
+        stage_vertex_field<G, 2, false>(M, m, p, sl, q, v0, nv, 0.0, 0.0, 0.0, lo, hi);
+        pmin = tmin<G>(lo);
+        pmax = tmax<G>(hi);
+        row = pmax - pmin > 1e-12;
+      }
+    }
+    wave_sync();
+    if (row) {
+      cell_features<G>(M, T, sl, q, p, P, a, nv, nf, f0, pmin, pmax - pmin);
+    } else {
+      for (int i = q; i < net::kIn; i += G) T.x[sl][i] = 0;
+    }
+    wave_sync();
+    net_tiles<C>(T, p.net_wb, p.net_master, lane);
+    if (active && q == 0) {
+      double lo = __builtin_nan(""), hi = __builtin_nan("");
+      const float u = T.u[sl];
+      if (row && !isnan(u)) {
+        const double Wd = pmax - pmin;
+        const double uc = u < 0.f ? 0.0 : (u > 1.f ? 1.0 : (double)u);
+        const double sh = pmin + uc * Wd, dl = p.net_delta * Wd;
+        lo = sh - dl;
+        hi = sh + dl;
+      }
+      hlo[k] = lo;
+      hhi[k] = hi;
+    }
+    wave_sync();
+  }
+}
+
+template <int NVM>
+vofpc_status launch_pass(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries, double *hlo, double *hhi) {
+  int blocks_per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, bracket_pass_kernel<NVM>, 64, 0);
+  if (e != hipSuccess || blocks_per_cu <= 0) blocks_per_cu = 4;
+  int64_t grid = (int64_t)ctx->n_cu * blocks_per_cu;
+  const int64_t need = (n_entries + 15) / 16;
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  bracket_pass_kernel<NVM><<<(unsigned)grid, 64, 0, ctx->stream>>>(p, hlo, hhi);
+  VOFPC_HIP(hipGetLastError());
+  return VOFPC_OK;
+}
+
 template <int G, int NV, int NF, int NL, int NE, bool NET>
 vofpc_status launch_net(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries) {
   constexpr int C = 64 / G;
@@ -1089,6 +1209,12 @@ bool thin_available(int c, int G, const int64_t cmax[4]) {
   if (c == 1) return (G == 4 || G == 8 || G == 16) && fits(kC1, cmax);
   if (c == 2) return (G == 4 || G == 8 || G == 16) && fits(kC2, cmax);
   return false;
+}
+
+vofpc_status launch_bracket_pass(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries, int c, double *hlo,
+                                 double *hhi) {
+  VOFPC_REQUIRE(c == 1 || c == 2, VOFPC_E_INVALID_ARG, "reconstruct: no bracket pass for this class");
+  return c == 1 ? launch_pass<kC1.nv>(ctx, p, n_entries, hlo, hhi) : launch_pass<kC2.nv>(ctx, p, n_entries, hlo, hhi);
 }
 
 vofpc_status launch_thin(vofpc_ctx ctx, const ReconParams &p, int64_t n_entries, int c, int G,

@@ -124,6 +124,9 @@ struct vofpc_mesh_s {
   // (cells spread over several classes) launch one variant per class over
   // per-class entry lists [kClasses][n_cells] with device counts
   int64_t class_cells[vofpc::kClasses];
+  // learned brackets [2][n_cells] of a bracket pass when the caller keeps
+  // none (allocated by the first such call, outside capture)
+  double *hint_buf = nullptr;
   int64_t class_max[vofpc::kClasses][4];   // largest vertices, faces, loop positions, edges per class
   int max_class;
   bool bucketed;
