@@ -355,6 +355,9 @@ def main() -> int:
                     help="which forms to time (profiling runs time one)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default kernel flavours instead of autotuning them on the workload before timing")
+    ap.add_argument("--tune", default=None,
+                    help="kernel flavour per class, e.g. 14,26,4,3 (no autotuning; a profiled run then holds only "
+                         "the timed launches)")
     ap.add_argument("--workload", choices=("full", "voronoi_bubble", "batched", "pipe", "multi"), default="full",
                     help="full (default): the learned-bracket configuration (128^3 hexahedra + 986,078 Voronoi "
                          "cells with random bubbles + a 4M-cell Voronoi pipe with a wavy film); voronoi_bubble: "
@@ -408,7 +411,10 @@ def main() -> int:
                              delta_scale=dscale, parts=parts)
         stream = run.ctx.stream
         tune = None
-        if args.autotune:
+        if args.tune:
+            tune = [int(x) for x in args.tune.split(",")]
+            run.mesh.set_tune(tune)
+        elif args.autotune:
             tune, _ = V.autotune(run.ctx, run.mesh, run.alpha)
             log(f"autotuned flavours per class: {tune}")
         run.step()
@@ -495,11 +501,15 @@ def main() -> int:
         # stream (the library records them), averaged over the launches
         run.ctx.time_classes(True)
         cls_ms = np.zeros(4)
+        pass_ms = np.zeros(4)
         for _ in range(reps):
             rec()
-            cls_ms += np.array(run.ctx.class_ms())
+            km, pm = run.ctx.class_ms()
+            cls_ms += np.array(km)
+            pass_ms += np.array(pm)
         run.ctx.time_classes(False)
         res["class_ms"] = (cls_ms / reps).tolist()
+        res["pass_ms"] = (pass_ms / reps).tolist()
         res["tune"] = tune if tune is not None else res["classes"]["tune"]
         run.close()
         return res, ms, statistics.median(per), wall, recon_ms
@@ -516,7 +526,8 @@ def main() -> int:
         mlp.set_params(params)
         learned, ms_l, med_l, wall_l, rms_l = time_form(mlp, dscale)
         log(f"learned step: {ms_l * 1e3:.1f} us mean, {med_l * 1e3:.1f} us median (wall {wall_l:.3f} s); "
-            f"reconstruction {rms_l * 1e3:.1f} us, class kernels {learned['class_ms']} ms")
+            f"reconstruction {rms_l * 1e3:.1f} us, class kernels {learned['class_ms']} ms, bracket passes "
+            f"{learned['pass_ms']} ms")
     two = follow_on(args, wl, parts, runner, V, torch) if args.workload == "voronoi_bubble" else None
     if plain is None and learned is None:
         print(json.dumps({"error": "no trained weights for the learned form"}))
@@ -538,7 +549,12 @@ def main() -> int:
     else:
         kcells = mixed
     k_ms = float(cms[kc])
-    rb_k = recon_bytes(wl.mesh, kcells, learned=form == "learned")
+    kp_ms = float(head["pass_ms"][kc])
+    # the learned class kernel reads its brackets (16 bytes per cell) when a
+    # bracket pass made them, else its network's inputs
+    rb_k = recon_bytes(wl.mesh, kcells, learned=form == "learned" and kp_ms < 0)
+    if form == "learned" and kp_ms >= 0:
+        rb_k += 16 * len(kcells)
     rf_k = recon_flops(wl.mesh, kcells)
     tflops = rf_k / (k_ms * 1e-3) / 1e12
     achieved = rb_k / (k_ms * 1e-3) / 1e9
@@ -577,6 +593,7 @@ def main() -> int:
     if plain is not None:
         cfg["plain"] = {"cells_per_s": plain["mixed_per_step"] / (ms_p * 1e-3), "ms_per_step": ms_p,
                         "recon_us": rms_p * 1e3, "class_kernel_us": [x * 1e3 for x in plain["class_ms"]],
+                        "kernel_flavours": plain["tune"],
                         "evals_per_cell_mean": float(plain["iters"].mean()),
                         "evals_per_cell_p99": float(np.percentile(plain["iters"], 99)),
                         "outcome_rates": outcome(plain)}
@@ -584,6 +601,8 @@ def main() -> int:
         cfg["learned"] = {
             "cells_per_s": learned["mixed_per_step"] / (ms_l * 1e-3), "ms_per_step": ms_l, "recon_us": rms_l * 1e3,
             "class_kernel_us": [x * 1e3 for x in learned["class_ms"]],
+            "bracket_pass_us": [x * 1e3 for x in learned["pass_ms"]],
+            "kernel_flavours": learned["tune"],
             "evals_per_cell_mean": float(learned["iters"].mean()),
             "evals_per_cell_p99": float(np.percentile(learned["iters"], 99)),
             "outcome_rates": outcome(learned),
@@ -627,6 +646,7 @@ def main() -> int:
             "frac": tflops / FP64_PEAK_TFLOPS,
             "traffic": measured_traffic(args.workload, form, kc),
             "kernel_us": k_ms * 1e3,
+            "bracket_pass_us": kp_ms * 1e3 if kp_ms >= 0 else None,
             "cells": int(len(kcells)),
             "algorithmic_flops": rf_k,
             "algorithmic_bytes": rb_k,

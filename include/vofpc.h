@@ -161,13 +161,15 @@ vofpc_status vofpc_mesh_classes(vofpc_mesh mesh, int64_t cells[4], int32_t tune[
 vofpc_status vofpc_mesh_set_tune(vofpc_mesh mesh, const int32_t tune[4]);
 /* Per-class kernel timing of the reconstruction (a measurement aid).  With
  * enable != 0, every later eager reconstruction on this context records a HIP
- * event pair on the context stream around each class kernel it launches (none
- * while the stream is being captured); enable = 0 destroys the events.
- * vofpc_ctx_class_ms waits for the latest call's events and writes the
- * duration in milliseconds of each class kernel to HOST ms[4] (-1 for classes
- * not launched), then forgets them; VOFPC_E_STATE when timing is off. */
+ * event pair on the context stream around each class kernel it launches, and
+ * around the class's bracket pass when the learned form runs one (none while
+ * the stream is being captured); enable = 0 destroys the events.
+ * vofpc_ctx_class_ms waits for the latest call's events and writes to HOST
+ * ms[8] the duration in milliseconds of each class kernel (ms[0..3]) and of
+ * each bracket pass (ms[4..7]), -1 where none ran, then forgets them;
+ * VOFPC_E_STATE when timing is off. */
 vofpc_status vofpc_ctx_time_classes(vofpc_ctx ctx, int32_t enable);
-vofpc_status vofpc_ctx_class_ms(vofpc_ctx ctx, float ms[4]);
+vofpc_status vofpc_ctx_class_ms(vofpc_ctx ctx, float ms[8]);
 /* Copy the computed geometry into caller DEVICE buffers (any may be NULL):
  * V[n_cells], xc[3][n_cells], Sf[3][n_faces], xf[3][n_faces]. */
 vofpc_status vofpc_mesh_geometry(vofpc_mesh mesh, double *V, double *xc, double *Sf, double *xf);

@@ -68,7 +68,10 @@ extern "C" vofpc_status vofpc_ctx_destroy(vofpc_ctx ctx) {
   }
   if (ctx && ctx->time_classes)
     for (int c = 0; c < vofpc::kClasses; ++c)
-      for (int j = 0; j < 2; ++j) (void)hipEventDestroy(ctx->cls_ev[c][j]);
+      for (int j = 0; j < 2; ++j) {
+        (void)hipEventDestroy(ctx->cls_ev[c][j]);
+        (void)hipEventDestroy(ctx->pass_ev[c][j]);
+      }
   delete ctx;
   return VOFPC_OK;
 }

@@ -1285,7 +1285,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
     VOFPC_HIP(hipStreamIsCapturing(ctx->stream, &cs));
     timed = cs == hipStreamCaptureStatusNone;
     if (timed)
-      for (int c = 0; c < kClasses; ++c) ctx->cls_rec[c] = false;
+      for (int c = 0; c < kClasses; ++c) ctx->cls_rec[c] = ctx->pass_rec[c] = false;
   }
   // learned form in a group build whose wavefronts hold fewer than 16 cells
   // (G = 8, 16: classes 1 and 2): the brackets come from a pass of their own
@@ -1310,12 +1310,17 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
     M->hint_buf = (double *)b;
   }
   auto run_class = [&](int64_t n_cells, int c) -> vofpc_status {
-    if (timed) VOFPC_HIP(hipEventRecord(ctx->cls_ev[c][0], ctx->stream));
     vofpc_status st;
     if (pass_first(c)) {
       double *hl = p.net_lo ? p.net_lo : M->hint_buf, *hh = p.net_hi ? p.net_hi : M->hint_buf + N;
+      if (timed) VOFPC_HIP(hipEventRecord(ctx->pass_ev[c][0], ctx->stream));
       st = launch_bracket_pass(ctx, p, n_cells, c, hl, hh);
       if (st) return st;
+      if (timed) {
+        VOFPC_HIP(hipEventRecord(ctx->pass_ev[c][1], ctx->stream));
+        ctx->pass_rec[c] = true;
+        VOFPC_HIP(hipEventRecord(ctx->cls_ev[c][0], ctx->stream));
+      }
       ReconParams q = p;
       q.net_wb = nullptr;
       q.net_master = nullptr;
@@ -1325,6 +1330,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
       q.hint_hi = hh;
       st = launch_class(ctx, M, q, n_cells, c, M->tune[c]);
     } else {
+      if (timed) VOFPC_HIP(hipEventRecord(ctx->cls_ev[c][0], ctx->stream));
       st = launch_class(ctx, M, p, n_cells, c, M->tune[c]);
     }
     if (st) return st;
@@ -1358,31 +1364,41 @@ extern "C" vofpc_status vofpc_ctx_time_classes(vofpc_ctx ctx, int32_t enable) {
   VOFPC_HIP(hipSetDevice(ctx->device));
   if (enable && !ctx->time_classes) {
     for (int c = 0; c < kClasses; ++c)
-      for (int j = 0; j < 2; ++j) VOFPC_HIP(hipEventCreate(&ctx->cls_ev[c][j]));
+      for (int j = 0; j < 2; ++j) {
+        VOFPC_HIP(hipEventCreate(&ctx->cls_ev[c][j]));
+        VOFPC_HIP(hipEventCreate(&ctx->pass_ev[c][j]));
+      }
   } else if (!enable && ctx->time_classes) {
     for (int c = 0; c < kClasses; ++c)
       for (int j = 0; j < 2; ++j) {
         (void)hipEventDestroy(ctx->cls_ev[c][j]);
-        ctx->cls_ev[c][j] = nullptr;
+        (void)hipEventDestroy(ctx->pass_ev[c][j]);
+        ctx->cls_ev[c][j] = ctx->pass_ev[c][j] = nullptr;
       }
   }
   ctx->time_classes = enable != 0;
-  for (int c = 0; c < kClasses; ++c) ctx->cls_rec[c] = false;
+  for (int c = 0; c < kClasses; ++c) ctx->cls_rec[c] = ctx->pass_rec[c] = false;
   return VOFPC_OK;
 }
 
-extern "C" vofpc_status vofpc_ctx_class_ms(vofpc_ctx ctx, float ms[4]) {
+extern "C" vofpc_status vofpc_ctx_class_ms(vofpc_ctx ctx, float ms[8]) {
   using namespace vofpc;
   clear_error();
   VOFPC_REQUIRE(ctx && ms, VOFPC_E_INVALID_ARG, "ctx_class_ms: null argument");
   VOFPC_REQUIRE(ctx->time_classes, VOFPC_E_STATE, "ctx_class_ms: class timing is not enabled on this context");
   VOFPC_HIP(hipSetDevice(ctx->device));
   for (int c = 0; c < kClasses; ++c) {
-    ms[c] = -1.0f;
-    if (!ctx->cls_rec[c]) continue;
-    VOFPC_HIP(hipEventSynchronize(ctx->cls_ev[c][1]));
-    VOFPC_HIP(hipEventElapsedTime(&ms[c], ctx->cls_ev[c][0], ctx->cls_ev[c][1]));
-    ctx->cls_rec[c] = false;
+    ms[c] = ms[kClasses + c] = -1.0f;
+    if (ctx->cls_rec[c]) {
+      VOFPC_HIP(hipEventSynchronize(ctx->cls_ev[c][1]));
+      VOFPC_HIP(hipEventElapsedTime(&ms[c], ctx->cls_ev[c][0], ctx->cls_ev[c][1]));
+      ctx->cls_rec[c] = false;
+    }
+    if (ctx->pass_rec[c]) {
+      VOFPC_HIP(hipEventSynchronize(ctx->pass_ev[c][1]));
+      VOFPC_HIP(hipEventElapsedTime(&ms[kClasses + c], ctx->pass_ev[c][0], ctx->pass_ev[c][1]));
+      ctx->pass_rec[c] = false;
+    }
   }
   return VOFPC_OK;
 }

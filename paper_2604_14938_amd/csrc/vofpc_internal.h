@@ -101,10 +101,13 @@ struct vofpc_ctx_s {
   // overlap
   int *queue = nullptr;
   // per-class kernel timing of the reconstruction (eager launches only):
-  // an event pair around each class kernel of the latest call
+  // an event pair around each class kernel of the latest call, and around
+  // its bracket pass (learned form) when it has one
   bool time_classes = false;
   hipEvent_t cls_ev[vofpc::kClasses][2] = {};
   bool cls_rec[vofpc::kClasses] = {};
+  hipEvent_t pass_ev[vofpc::kClasses][2] = {};
+  bool pass_rec[vofpc::kClasses] = {};
 };
 
 struct vofpc_mesh_s {

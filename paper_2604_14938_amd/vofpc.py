@@ -168,12 +168,14 @@ class Context:
         reconstructions on this context (vofpc_ctx_time_classes)."""
         _check(lib.vofpc_ctx_time_classes(self.h, int(bool(enable))), "vofpc_ctx_time_classes")
 
-    def class_ms(self) -> list:
-        """Durations (ms) of the class kernels of the latest reconstruction,
-        -1 for classes not launched (vofpc_ctx_class_ms)."""
-        a = (ctypes.c_float * 4)()
+    def class_ms(self) -> tuple:
+        """Durations (ms) of the class kernels of the latest reconstruction
+        and of their bracket passes (learned form), -1 where none ran
+        (vofpc_ctx_class_ms): (kernels[4], passes[4])."""
+        a = (ctypes.c_float * 8)()
         _check(lib.vofpc_ctx_class_ms(self.h, a), "vofpc_ctx_class_ms")
-        return [float(x) for x in a]
+        v = [float(x) for x in a]
+        return v[:4], v[4:]
 
     def close(self) -> None:
         if getattr(self, "h", None):
