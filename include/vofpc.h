@@ -185,6 +185,17 @@ vofpc_status vofpc_mesh_geometry(vofpc_mesh mesh, double *V, double *xc, double 
  * counts: DEVICE int32 [2] receives |M| and |B|.  No host readback. */
 vofpc_status vofpc_compact(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, double eps_mixed,
                            int32_t *mixed_idx, int32_t *band_idx, int32_t *counts);
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): vofpc_compact with
+ * the same arguments and results, its scratch (per-cell flag and band-mark
+ * bytes, per-block totals) taken from a fixed array the library holds on
+ * each GPU until the process ends (about 17 MB) instead of the mesh's; it
+ * allocates nothing.  Meshes of at most 8,388,608 cells; larger ones give
+ * VOFPC_E_INVALID_ARG.  Every call on one GPU shares that array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and give
+ * undefined lists. */
+vofpc_status vofpc_compact_noalloc(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, double eps_mixed,
+                                   int32_t *mixed_idx, int32_t *band_idx, int32_t *counts);
 
 /* --------------------------------------------------------- reconstruction */
 #define VOFPC_BRACKET_PLAIN 0   /* search [phi_min, phi_max] of the cell */

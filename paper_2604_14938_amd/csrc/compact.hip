@@ -8,6 +8,9 @@
 // in the number of blocks.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include "vofpc_internal.h"
 #include "wave_ops.h"
 
@@ -204,26 +207,91 @@ __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t 
   if (band) band_idx[wbase[1][w] + lanes_below(bb)] = (int32_t)P;
 }
 
-vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, double eps, int32_t *mixed,
-                            int32_t *band, int32_t *counts) {
+// The compaction on the given scratch: flags [n_cells] bytes, cross
+// [n_cells] bytes (zero on entry; the cell pass clears what the face pass
+// set) and blk_cnt [2][n_blk].
+static vofpc_status compact_on(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, double eps, int32_t *mixed,
+                               int32_t *band, int32_t *counts, uint8_t *flags, uint8_t *cross, int32_t *blk_cnt) {
   VOFPC_REQUIRE(alpha && mixed && band && counts, VOFPC_E_INVALID_ARG, "compact: null pointer");
   VOFPC_REQUIRE(eps >= 0 && eps < 0.5, VOFPC_E_INVALID_ARG, "compact: eps_mixed must be in [0, 0.5)");
   const int64_t nb = M->n_blk;
   hipStream_t s = ctx->stream;
   if (M->max_nf <= 8) {
-    compact_cells_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->flags, M->blk_cnt, nb);
+    compact_cells_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, flags, blk_cnt, nb);
   } else {
     const int64_t nfb = (M->d.n_faces + kCompactBlock - 1) / kCompactBlock;
-    compact_faces_kernel<<<(unsigned)nfb, kCompactBlock, 0, s>>>(M->d, alpha, M->cross);
-    compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, M->cross, M->flags, M->blk_cnt,
-                                                                 nb);
+    compact_faces_kernel<<<(unsigned)nfb, kCompactBlock, 0, s>>>(M->d, alpha, cross);
+    compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, cross, flags, blk_cnt, nb);
   }
   const int scanned = nb > kScanBlocks ? 1 : 0;
-  if (scanned) compact_scan_kernel<<<1, kScanThreads, 0, s>>>(M->blk_cnt, nb, counts);
-  compact_scatter_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, M->flags, M->blk_cnt, nb, scanned,
-                                                                  mixed, band, counts);
+  if (scanned) compact_scan_kernel<<<1, kScanThreads, 0, s>>>(blk_cnt, nb, counts);
+  compact_scatter_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, flags, blk_cnt, nb, scanned, mixed,
+                                                                  band, counts);
   VOFPC_HIP(hipGetLastError());
   return VOFPC_OK;
 }
 
+vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, double eps, int32_t *mixed,
+                            int32_t *band, int32_t *counts) {
+  return compact_on(ctx, M, alpha, eps, mixed, band, counts, M->flags, M->cross, M->blk_cnt);
+}
+
+// ---------------------------------------------------------------- no allocation
+// The compaction's scratch for callers that cannot allocate: one file-scope
+// device array per GPU, held until the process ends, laid out as flags
+// [kNoAllocMaxCells] bytes, band marks [kNoAllocMaxCells] bytes and block
+// totals [2][kNoAllocMaxBlocks] int32.  In host code the array's name is not
+// a device address: each device's address comes from hipGetSymbolAddress
+// (once per device, with that device current) and only that address is used.
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 23;   // 8,388,608 cells
+constexpr int64_t kNoAllocMaxBlocks = kNoAllocMaxCells / kCompactBlock;
+constexpr int64_t kNoAllocBytes = 2 * kNoAllocMaxCells + 2 * kNoAllocMaxBlocks * (int64_t)sizeof(int32_t);
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+__global__ __launch_bounds__(kCompactBlock) void zero_bytes_kernel(uint8_t *p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace vofpc
+
+extern "C" vofpc_status vofpc_compact_noalloc(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, double eps,
+                                              int32_t *mixed_idx, int32_t *band_idx, int32_t *counts) {
+  using namespace vofpc;
+  clear_error();
+  VOFPC_REQUIRE(ctx && mesh, VOFPC_E_INVALID_ARG, "compact_noalloc: null context or mesh");
+  VOFPC_REQUIRE(mesh->ctx && mesh->ctx->device == ctx->device, VOFPC_E_STATE,
+                "compact_noalloc: mesh on another device");
+  const int64_t N = mesh->d.n_cells;
+  VOFPC_REQUIRE(N <= kNoAllocMaxCells && mesh->n_blk <= kNoAllocMaxBlocks, VOFPC_E_INVALID_ARG,
+                "compact_noalloc: meshes of more than 8,388,608 cells exceed its fixed scratch (use vofpc_compact)");
+  VOFPC_REQUIRE(ctx->device >= 0 && ctx->device < kNoAllocMaxDevices, VOFPC_E_STATE,
+                "compact_noalloc: device index beyond the scratch table");
+  VOFPC_HIP(hipSetDevice(ctx->device));
+  uint8_t *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[ctx->device]) {
+      void *ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        set_error(std::string("compact_noalloc: hipGetSymbolAddress of the scratch array failed: ") +
+                  hipGetErrorString(e));
+        return VOFPC_E_HIP;
+      }
+      g_scratch_ptr[ctx->device] = (uint8_t *)ptr;
+    }
+    base = g_scratch_ptr[ctx->device];
+  }
+  uint8_t *flags = base, *cross = base + kNoAllocMaxCells;
+  int32_t *blk_cnt = reinterpret_cast<int32_t *>(base + 2 * kNoAllocMaxCells);
+  // the band marks must start at zero: the array keeps the last call's
+  // contents (a call that stopped early may have left marks)
+  zero_bytes_kernel<<<(unsigned)((N + kCompactBlock - 1) / kCompactBlock), kCompactBlock, 0, ctx->stream>>>(cross, N);
+  VOFPC_HIP(hipGetLastError());
+  return compact_on(ctx, mesh, alpha, eps, mixed_idx, band_idx, counts, flags, cross, blk_cnt);
+}

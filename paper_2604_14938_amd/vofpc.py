@@ -80,6 +80,7 @@ def _load():
         "vofpc_mesh_info": ([P, P], ctypes.c_int),
         "vofpc_mesh_geometry": ([P, P, P, P, P], ctypes.c_int),
         "vofpc_compact": ([P, P, P, D, P, P, P], ctypes.c_int),
+        "vofpc_compact_noalloc": ([P, P, P, D, P, P, P], ctypes.c_int),
         "vofpc_recon_opts_default": ([P], ctypes.c_int),
         "vofpc_reconstruct": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "vofpc_grad_T": ([P, P, P, P, D, P, P, P, I32, I32, P, P], ctypes.c_int),
@@ -303,6 +304,12 @@ class Interface:
 def compact(ctx: Context, mesh: Mesh, alpha, mixed_idx, band_idx, counts, eps_mixed: float = 1e-8) -> None:
     _check(lib.vofpc_compact(ctx.h, mesh.h, _ptr(alpha), eps_mixed, _ptr(mixed_idx), _ptr(band_idx), _ptr(counts)),
            "vofpc_compact")
+
+
+def compact_noalloc(ctx: Context, mesh: Mesh, alpha, mixed_idx, band_idx, counts, eps_mixed: float = 1e-8) -> None:
+    """vofpc_compact on the library's fixed per-GPU scratch (allocates nothing)."""
+    _check(lib.vofpc_compact_noalloc(ctx.h, mesh.h, _ptr(alpha), eps_mixed, _ptr(mixed_idx), _ptr(band_idx),
+                                     _ptr(counts)), "vofpc_compact_noalloc")
 
 
 def reconstruct(ctx: Context, mesh: Mesh, alpha, mixed_idx, counts, itf: Interface, opts: ReconOpts | None = None,
