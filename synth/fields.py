@@ -82,7 +82,12 @@ def subsample(mesh: Mesh, cells: np.ndarray, bbox: np.ndarray, kind: int,
 
 
 def _cell_vertices(mesh: Mesh):
-    """(cell, vertex) incidence pairs with repeats, for min/max queries."""
+    """(cell, vertex) incidence pairs with repeats, for min/max queries
+    (computed once per mesh)."""
+    return mesh._cached("_cell_vertices", lambda: _cell_vertices_of(mesh))
+
+
+def _cell_vertices_of(mesh: Mesh):
     N = mesh.n_cells
     cf_cnt = np.diff(mesh.cell_face_off)
     faces = mesh.cell_face.astype(np.int64)
@@ -113,9 +118,12 @@ def sphere_alpha(mesh: Mesh, spheres: np.ndarray, K: int = 64) -> np.ndarray:
     # cells whose box meets the sphere's box have their box centre within
     # r + (largest box half-diagonal) of the sphere's centre
     from scipy.spatial import cKDTree
-    bc = 0.5 * (bbox[:, :3] + bbox[:, 3:])
-    ext = 0.5 * float(np.sqrt(((bbox[:, 3:] - bbox[:, :3]) ** 2).sum(1)).max())
-    tree = cKDTree(bc)
+
+    def box_tree():
+        bc = 0.5 * (bbox[:, :3] + bbox[:, 3:])
+        return cKDTree(bc), 0.5 * float(np.sqrt(((bbox[:, 3:] - bbox[:, :3]) ** 2).sum(1)).max())
+
+    tree, ext = mesh._cached("_box_tree", box_tree)
     for s, (cx, cy, cz, r) in enumerate(spheres):
         c = np.array([cx, cy, cz])
         near = np.sort(np.asarray(tree.query_ball_point(c, r * np.sqrt(3.0) + ext + 1e-12), np.int64))

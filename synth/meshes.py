@@ -56,7 +56,23 @@ class Mesh:
     extra: dict = field(default_factory=dict)
 
     # ---- cheap helpers used only to place input fields ----------------
+    # (each is computed once per mesh and kept in `extra` under a "_" key:
+    # meshes are not modified after construction)
+    def _cached(self, key, fn):
+        if key not in self.extra:
+            self.extra[key] = fn()
+        return self.extra[key]
+
     def cell_vertex_mean(self) -> np.ndarray:
+        return self._cached("_cell_vertex_mean", self._cell_vertex_mean)
+
+    def face_vertex_mean(self) -> np.ndarray:
+        return self._cached("_face_vertex_mean", self._face_vertex_mean)
+
+    def cell_bbox(self) -> np.ndarray:
+        return self._cached("_cell_bbox", self._cell_bbox)
+
+    def _cell_vertex_mean(self) -> np.ndarray:
         """Mean of the distinct vertices of each cell, [N, 3].
 
         Used only to evaluate synthetic input profiles (temperature); the
@@ -82,7 +98,7 @@ class Mesh:
             out[:, a] = np.bincount(c, weights=self.vert_xyz[a, v], minlength=N) / cnt
         return out
 
-    def face_vertex_mean(self) -> np.ndarray:
+    def _face_vertex_mean(self) -> np.ndarray:
         """Mean of each face's vertices, [NF, 3] (input-profile placement only)."""
         cnt = np.diff(self.face_vert_off)
         fid = np.repeat(np.arange(self.n_faces), cnt)
@@ -91,7 +107,7 @@ class Mesh:
             out[:, a] = np.bincount(fid, weights=self.vert_xyz[a, self.face_vert], minlength=self.n_faces) / cnt
         return out
 
-    def cell_bbox(self) -> np.ndarray:
+    def _cell_bbox(self) -> np.ndarray:
         """Axis-aligned bounding box of each cell, [N, 6] = (lo xyz, hi xyz)."""
         N = self.n_cells
         cf_cnt = np.diff(self.cell_face_off)
