@@ -107,47 +107,83 @@ __global__ __launch_bounds__(kCompactBlock) void compact_cells_kernel(DevMesh m,
   }
 }
 
-// Exclusive prefix of both rows of block totals, in place, by one block:
-// each thread sums a contiguous chunk, the chunk sums are scanned (within
-// each wavefront by shuffles, then across the wavefronts), then every thread
-// rewrites its chunk.  Writes the list lengths.
+// Exclusive prefix of both rows of block totals, in place, by one block, a
+// tile of kScanTile totals per row at a time: coalesced loads (the next
+// tile's issued before the current one is scanned) staged through LDS, each
+// thread scans kScanPer consecutive totals, the thread sums are scanned
+// within each wavefront by shuffles and then across the wavefronts, and a
+// carry per row runs from tile to tile.  Writes the list lengths.
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
 __global__ __launch_bounds__(kScanThreads) void compact_scan_kernel(int32_t *blk_cnt, int64_t n_blk,
                                                                     int32_t *counts) {
   constexpr int kW = kScanThreads / 64;
+  __shared__ int32_t tile[2][kScanTile];
   __shared__ int32_t wtot[2][kW];
   const int t = threadIdx.x, w = t >> 6, l = lane_id();
-  const int64_t chunk = (n_blk + kScanThreads - 1) / kScanThreads;
-  const int64_t i0 = t * chunk < n_blk ? t * chunk : n_blk, i1 = (i0 + chunk < n_blk) ? i0 + chunk : n_blk;
-  int32_t ex[2];
-  for (int r = 0; r < 2; ++r) {
-    int32_t s = 0;
-    for (int64_t i = i0; i < i1; ++i) s += blk_cnt[r * n_blk + i];
-    int32_t inc = s;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int32_t u = __shfl_up(inc, d);
-      if (l >= d) inc += u;
+  int32_t cur[2][kScanPer];
+  auto load = [&](int64_t t0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < kScanPer; ++j) {
+        const int64_t g = t0 + j * kScanThreads + t;
+        cur[r][j] = g < n_blk ? blk_cnt[r * n_blk + g] : 0;
+      }
+  };
+  int32_t carry[2] = {0, 0};
+  load(0);
+  for (int64_t t0 = 0; t0 < n_blk; t0 += kScanTile) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < kScanPer; ++j) tile[r][j * kScanThreads + t] = cur[r][j];
+    if (t0 + kScanTile < n_blk) load(t0 + kScanTile);
+    __syncthreads();
+    int32_t v[2][kScanPer], ex[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int32_t s = 0;
+#pragma unroll
+      for (int j = 0; j < kScanPer; ++j) {
+        v[r][j] = tile[r][t * kScanPer + j];
+        s += v[r][j];
+      }
+      int32_t inc = s;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int32_t u = __shfl_up(inc, d);
+        if (l >= d) inc += u;
+      }
+      ex[r] = inc - s;
+      if (l == 63) wtot[r][w] = inc;
     }
-    ex[r] = inc - s;
-    if (l == 63) wtot[r][w] = inc;
-  }
-  __syncthreads();
-  for (int r = 0; r < 2; ++r) {
-    int32_t base = 0, all = 0;
-    for (int i = 0; i < kW; ++i) {
-      base += (i < w) ? wtot[r][i] : 0;
-      all += wtot[r][i];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int32_t base = 0, all = 0;
+      for (int i = 0; i < kW; ++i) {
+        base += (i < w) ? wtot[r][i] : 0;
+        all += wtot[r][i];
+      }
+      int32_t run = carry[r] + base + ex[r];
+#pragma unroll
+      for (int j = 0; j < kScanPer; ++j) {
+        tile[r][t * kScanPer + j] = run;
+        run += v[r][j];
+      }
+      carry[r] += all;
     }
-    ex[r] += base;
-    if (t == 0) counts[r] = all;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < kScanPer; ++j) {
+        const int64_t g = t0 + j * kScanThreads + t;
+        if (g < n_blk) blk_cnt[r * n_blk + g] = tile[r][j * kScanThreads + t];
+      }
+    __syncthreads();
   }
-  for (int r = 0; r < 2; ++r) {
-    int32_t run = ex[r];
-    for (int64_t i = i0; i < i1; ++i) {
-      const int32_t v = blk_cnt[r * n_blk + i];
-      blk_cnt[r * n_blk + i] = run;
-      run += v;
-    }
-  }
+  if (t < 2) counts[t] = carry[t];
 }
 
 // Scatter the cell ids into both lists in ascending order.  With `scanned`

@@ -1173,23 +1173,43 @@ __global__ void bucket_zero_kernel(int32_t *c) {
 }
 
 // Split the mixed entries into one list per class (order within a list is
-// the order of the atomic claims; results do not depend on it).
-__global__ __launch_bounds__(256) void bucket_kernel(DevMesh m, const int32_t *mixed, const int32_t *counts,
-                                                     int64_t cap, int32_t *lists, int64_t stride, int32_t *bcount) {
+// the order of the claims; results do not depend on it).  Blocks of 1024
+// stride over the mixed entries; per tile of 1024 entries, one claim per
+// class on the list counter (the waves' counts summed in LDS first).
+constexpr int kBucketBlock = 1024;
+__global__ __launch_bounds__(kBucketBlock) void bucket_kernel(DevMesh m, const int32_t *mixed, const int32_t *counts,
+                                                              int64_t cap, int32_t *lists, int64_t stride,
+                                                              int32_t *bcount) {
+  constexpr int kW = kBucketBlock / 64;
+  __shared__ int32_t wcnt[kW][kClasses];
+  __shared__ int32_t gbase[kClasses];
   int64_t count = counts[0];
   if (count > cap) count = cap;
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int c = (k < count) ? cell_class(m, mixed[k]) : -1;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t k0 = (int64_t)blockIdx.x * kBucketBlock; k0 < count; k0 += (int64_t)gridDim.x * kBucketBlock) {
+    const int64_t k = k0 + threadIdx.x;
+    const int c = (k < count) ? cell_class(m, mixed[k]) : -1;
+    uint64_t mine = 0;
 #pragma unroll
-  for (int q = 0; q < kClasses; ++q) {
-    const uint64_t bm = __ballot(c == q);
-    if (!bm) continue;
-    const int leader = __ffsll((long long)bm) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&bcount[q], __popcll(bm));
-    base = __shfl(base, leader);
-    if (c == q) lists[q * stride + base + lanes_below(bm)] = (int32_t)k;
+    for (int q = 0; q < kClasses; ++q) {
+      const uint64_t bm = __ballot(c == q);
+      if (c == q) mine = bm;
+      if (lane == 0) wcnt[w][q] = __popcll(bm);
+    }
+    __syncthreads();
+    if (threadIdx.x < kClasses) {
+      const int q = threadIdx.x;
+      int tot = 0;
+      for (int i = 0; i < kW; ++i) tot += wcnt[i][q];
+      gbase[q] = tot ? atomicAdd(&bcount[q], tot) : 0;
+    }
+    __syncthreads();
+    if (c >= 0) {
+      int off = gbase[c] + lanes_below(mine);
+      for (int i = 0; i < w; ++i) off += wcnt[i][c];
+      lists[c * stride + off] = (int32_t)k;
+    }
+    __syncthreads();
   }
 }
 
@@ -1344,8 +1364,9 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   // one launch per class present in the mesh, each over its own entries
   bucket_zero_kernel<<<1, 64, 0, ctx->stream>>>(M->bucket_counts);
   const int64_t span = std::min<int64_t>(out->cap, N);
-  bucket_kernel<<<(unsigned)((span + 255) / 256), 256, 0, ctx->stream>>>(M->d, mixed, counts, out->cap,
-                                                                        M->bucket_lists, N, M->bucket_counts);
+  const int64_t bgrid = std::min<int64_t>((span + kBucketBlock - 1) / kBucketBlock, (int64_t)ctx->n_cu * 2);
+  bucket_kernel<<<(unsigned)std::max<int64_t>(bgrid, 1), kBucketBlock, 0, ctx->stream>>>(
+      M->d, mixed, counts, out->cap, M->bucket_lists, N, M->bucket_counts);
   VOFPC_HIP(hipGetLastError());
   for (int c = 0; c < kClasses; ++c) {
     if (M->class_cells[c] == 0) continue;
