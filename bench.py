@@ -660,6 +660,24 @@ def main() -> int:
     return 0
 
 
+def extrap_sweep_bytes(mesh, dom, us) -> dict:
+    """Algorithmic bytes of one busy extrapolation sweep over the domain
+    cells `dom` (boolean per cell): per domain cell its list entry (4), its
+    packed-stencil range (8), theta (8), its advanced components read (24)
+    and written (24), and its record as a neighbour (24); per upwind face
+    slot its weight (8) and neighbour (4).  The upwind slots are taken as half
+    of the face slots between two domain cells (such a face is upwind for
+    exactly one of its cells when their velocities agree)."""
+    nd = int(dom.sum())
+    nb = np.asarray(mesh.face_neigh)
+    inner = nb >= 0
+    slots = int(np.count_nonzero(dom[mesh.face_owner[inner]] & dom[nb[inner]]))   # 2 slots per face, half upwind
+    b = nd * (4 + 8 + 8 + 24 + 24 + 24) + slots * 12
+    gbs = b / (us * 1e-6) / 1e9 if us > 0 else float("nan")
+    return {"domain_cells": nd, "upwind_slots_est": slots, "algorithmic_bytes": b, "GBps": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
 def follow_on(args, wl, parts, runner, V, torch) -> dict:
     """Two-sided mass transfer (Eq. extrapolation + Eq. mass_transfer), the
     interface coupling coefficients (Eq. interface_htc) and the surface-tension
@@ -714,6 +732,27 @@ def follow_on(args, wl, parts, runner, V, torch) -> dict:
         log(f"two-sided mass transfer, {name}: eager {tsm[name]['us_eager']:.1f} us, graph replay "
             f"{tsm[name]['us_graph_replay']:.1f} us ({tsm['sweeps']} sweeps over {dom} cells)")
         del graph
+    # the sweep kernel alone: graph replays with no sweeps (set-up and
+    # finish), with exactly the sweeps convergence needs (all busy) and with
+    # the cap of 120 (the rest idle)
+    sw = tsm["sweeps"]
+    t_cap = {}
+    for cap in (0, sw, 120):
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=run.ctx.stream):
+            two_sided(cap)
+        graph.replay()
+        torch.cuda.synchronize()
+        t_cap[cap] = timed(graph.replay)
+        del graph
+    busy = (t_cap[sw] - t_cap[0]) / max(sw, 1)
+    idle = (t_cap[120] - t_cap[sw]) / max(120 - sw, 1)
+    tsm["sweep_kernel"] = extrap_sweep_bytes(wl.mesh, (~torch.isnan(gl[0])).cpu().numpy(), busy)
+    tsm["sweep_kernel"].update(busy_us=busy, idle_us=idle, setup_and_finish_us=t_cap[0])
+    sk = tsm["sweep_kernel"]
+    log(f"extrapolation sweep: busy {busy:.2f} us, idle {idle:.2f} us, set-up and finish {t_cap[0]:.1f} us; "
+        f"{sk['algorithmic_bytes'] / 1e6:.2f} MB algorithmic per sweep -> {sk['GBps']:.0f} GB/s "
+        f"({100 * sk['hbm_frac']:.1f} % of HBM)")
     nf_cap = wl.mesh.n_faces
     ad = torch.zeros(N, dtype=torch.float64, device=run.dev)
     fi = torch.zeros(nf_cap, dtype=torch.int32, device=run.dev)

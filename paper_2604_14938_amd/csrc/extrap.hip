@@ -78,57 +78,89 @@ struct ExParams {
   DevMesh m;
   const double *alpha;
   const int32_t *list;
-  double *wup;      // per cell-face slot: upwind weight w_f / sum w (0 off the upwind set)
+  double *wup;      // per cell-face slot: upwind weights w_f / sum w, packed at the front of each cell's slots
+  int32_t *upn;     // per cell-face slot: the neighbour of each packed upwind weight
+  int2 *upr;        // per domain entry: first slot and number of its packed upwind weights
   double *theta;    // per domain entry: pseudo-time fraction min(dtau sum w / V, 1), 0 without upwind faces
   int32_t *info;
   double *part;     // [2][grid] per-block largest change of the last two sweeps
   const int8_t *mark;
   const double *nrm;
-  double *buf;   // [2][6][N]
+  double *buf;   // [2][N][kExRec]
   double dtau, tol;
   int max_iter;
   double *gl, *gv;
 };
 
-constexpr int kExLanes = 16;   // lanes per domain cell in the stencil and sweeps (one DPP row)
+constexpr int kExLanes = 8;   // lanes per domain cell in the stencil and sweeps (half a DPP row)
+constexpr int kExBlocksPerCu = 4;   // stencil and sweep blocks per CU
+// The two iterates of both fields: one 64-byte record per cell and iterate,
+// G_l in words 0-2 and G_v in words 3-5, so a neighbour's gathered
+// components share one cache line.
+constexpr int kExRec = 8;
+
+// Upwind weight of cell-face slot i of cell P for velocity c: w_f = -c.S_f
+// (S_f outward from P) when that is positive and the neighbour Q is in the
+// domain, else 0.
+__device__ __forceinline__ double ex_up_weight(const ExParams &p, int P, double c0, double c1, double c2, int64_t i,
+                                               int &Q) {
+  const DevMesh &m = p.m;
+  const int64_t NF = m.n_faces;
+  Q = m.cf_nbr[i];
+  if (Q < 0 || p.mark[Q] < 0) return 0.0;
+  const int f = m.cell_face[i];
+  const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
+  const double cs = c0 * (sg * m.Sf[f]) + c1 * (sg * m.Sf[NF + f]) + c2 * (sg * m.Sf[2 * NF + f]);
+  return cs < 0.0 ? -cs : 0.0;
+}
 
 // The upwind stencil of domain entry j, fixed for the whole iteration (and
 // the start of both fields, the gradient p.gl, written to both iterates): with
 // c = sgn(alpha - 1/2) n, the faces with c.S_f < 0 (S_f outward) whose
-// neighbour is in the domain get w_f = -c.S_f; each such cell-face slot keeps
-// w_f / sum w, every other slot 0, and the entry keeps
+// neighbour is in the domain get w_f = -c.S_f; those faces, in slot order,
+// are packed at the front of the cell's slot range as (w_f / sum w,
+// neighbour), the entry keeps (first slot, count) and
 // theta = min(dtau sum w / V_P, 1) (0 when no face is upwind: no update).
 __device__ __forceinline__ void ex_stencil(const ExParams &p, int64_t j, int lane) {
   const DevMesh &m = p.m;
-  const int64_t N = m.n_cells, NF = m.n_faces;
+  const int64_t N = m.n_cells;
   const int P = p.list[j];
   if (lane < 3) {
     // both fields start from the gradient (each iterate)
     const double g = p.gl[lane * N + P];
-    p.buf[lane * N + P] = g;
-    p.buf[(3 + lane) * N + P] = g;
-    p.buf[(6 + lane) * N + P] = g;
-    p.buf[(9 + lane) * N + P] = g;
+    double *rec0 = p.buf + (int64_t)P * kExRec, *rec1 = p.buf + ((int64_t)N + P) * kExRec;
+    rec0[lane] = g;
+    rec0[3 + lane] = g;
+    rec1[lane] = g;
+    rec1[3 + lane] = g;
   }
   const double sgn = p.alpha[P] >= 0.5 ? 1.0 : -1.0;
   const double c0 = sgn * p.nrm[P], c1 = sgn * p.nrm[N + P], c2 = sgn * p.nrm[2 * N + P];
   const int64_t i0 = m.cell_face_off[P], i1 = m.cell_face_off[P + 1];
   double w = 0.0;
   for (int64_t i = i0 + lane; i < i1; i += kExLanes) {
-    const int Q = m.cf_nbr[i];
-    double wf = 0.0;
-    if (Q >= 0 && p.mark[Q] >= 0) {
-      const int f = m.cell_face[i];
-      const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
-      const double cs = c0 * (sg * m.Sf[f]) + c1 * (sg * m.Sf[NF + f]) + c2 * (sg * m.Sf[2 * NF + f]);
-      if (cs < 0.0) wf = -cs;
-    }
-    p.wup[i] = wf;
-    w += wf;
+    int Q;
+    w += ex_up_weight(p, P, c0, c1, c2, i, Q);
   }
   w = gsum<kExLanes>(w);
-  if (w > 0.0)
-    for (int64_t i = i0 + lane; i < i1; i += kExLanes) p.wup[i] = p.wup[i] / w;
+  // the lanes of a group share the cell, so they run the same rounds; each
+  // round packs its upwind slots after those of the rounds before
+  const int gl0 = (threadIdx.x & 63) & ~(kExLanes - 1);
+  const uint64_t below = (1ull << lane) - 1;
+  int n = 0;
+  for (int64_t k0 = i0; k0 < i1; k0 += kExLanes) {
+    const int64_t i = k0 + lane;
+    int Q = -1;
+    const double wf = (i < i1 && w > 0.0) ? ex_up_weight(p, P, c0, c1, c2, i, Q) : 0.0;
+    const bool up = wf > 0.0;
+    const uint64_t gm = (__ballot(up) >> gl0) & ((1ull << kExLanes) - 1);
+    if (up) {
+      const int64_t o = i0 + n + __popcll(gm & below);
+      p.wup[o] = wf / w;
+      p.upn[o] = Q;
+    }
+    n += __popcll(gm);
+  }
   if (lane == 0) {
     double th = 0.0;
     if (w > 0.0) {
@@ -136,6 +168,7 @@ __device__ __forceinline__ void ex_stencil(const ExParams &p, int64_t j, int lan
       if (th > 1.0) th = 1.0;
     }
     p.theta[j] = th;
+    p.upr[j] = make_int2((int)i0, n);
   }
 }
 
@@ -147,8 +180,8 @@ __global__ __launch_bounds__(kExBlock) void ex_stencil_kernel(ExParams p) {
     ex_stencil(p, j, lane);
 }
 
-// Upwind update of domain entry j from iterate cur by the 16 lanes of one
-// row, one face slot per lane: the new values of its three advanced
+// Upwind update of domain entry j from iterate cur by a group of kExLanes
+// lanes, one packed upwind slot per lane and round: the new values of its three advanced
 // components and their largest change (ex_compute), written into the next
 // iterate by ex_store.  The kept field was written to both iterates at the
 // start and is not touched.
@@ -163,22 +196,23 @@ __device__ __forceinline__ ExNew ex_compute(const ExParams &p, int64_t j, int la
   ExNew r;
   r.P = p.list[j];
   r.adv = p.alpha[r.P] >= 0.5 ? 3 : 0;   // G_v advances in liquid, G_l in vapour
-  const double *ca = cur + (int64_t)r.adv * N;
+  const double *ca = cur + r.adv;
+  const int2 ur = p.upr[j];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int64_t i = m.cell_face_off[r.P] + lane; i < m.cell_face_off[r.P + 1]; i += kExLanes) {
-    const double wf = p.wup[i];
-    if (wf == 0.0) continue;
-    const int Q = m.cf_nbr[i];
-    a0 += wf * ca[Q];
-    a1 += wf * ca[N + Q];
-    a2 += wf * ca[2 * N + Q];
+  for (int k = lane; k < ur.y; k += kExLanes) {
+    const double wf = p.wup[ur.x + k];
+    const double *q = ca + (int64_t)p.upn[ur.x + k] * kExRec;
+    a0 += wf * q[0];
+    a1 += wf * q[1];
+    a2 += wf * q[2];
   }
   a0 = gsum<kExLanes>(a0);
   a1 = gsum<kExLanes>(a1);
   a2 = gsum<kExLanes>(a2);
   const double th = p.theta[j];
   const int P = r.P;
-  const double o0 = ca[P], o1 = ca[N + P], o2 = ca[2 * N + P];
+  const double *o = ca + (int64_t)P * kExRec;
+  const double o0 = o[0], o1 = o[1], o2 = o[2];
   r.n0 = o0 + th * (a0 - o0);
   r.n1 = o1 + th * (a1 - o1);
   r.n2 = o2 + th * (a2 - o2);
@@ -188,10 +222,10 @@ __device__ __forceinline__ ExNew ex_compute(const ExParams &p, int64_t j, int la
 
 __device__ __forceinline__ void ex_store(const ExParams &p, const ExNew &r, double *nxt) {
   const int64_t N = p.m.n_cells;
-  double *na = nxt + (int64_t)r.adv * N;
-  na[r.P] = r.n0;
-  na[N + r.P] = r.n1;
-  na[2 * N + r.P] = r.n2;
+  double *na = nxt + (int64_t)r.P * kExRec + r.adv;
+  na[0] = r.n0;
+  na[1] = r.n1;
+  na[2] = r.n2;
 }
 
 // Sweep `it` (0-based) of the Jacobi iteration.  From the second sweep on it
@@ -204,12 +238,13 @@ __global__ __launch_bounds__(kExBlock) void ex_sweep_kernel(ExParams p, int it) 
   const int64_t nd = p.info[1];
   if (converged) return;
   const int64_t N = p.m.n_cells;
-  const double *cur = p.buf + (int64_t)(it & 1) * 6 * N;
-  double *nxt = p.buf + (int64_t)((it + 1) & 1) * 6 * N;
-  // rows of 16 lanes take the domain cells; every lane of a row sees the
-  // same cells, so the row reductions see all its lanes.  The row's first
-  // cell is computed before the convergence test of the previous sweep (its
-  // gathers and that test's reads are in flight together) and stored after.
+  const double *cur = p.buf + (int64_t)(it & 1) * kExRec * N;
+  double *nxt = p.buf + (int64_t)((it + 1) & 1) * kExRec * N;
+  // groups of kExLanes lanes take the domain cells; every lane of a group
+  // sees the same cells, so the group reductions see all its lanes.  The
+  // group's first cell is computed before the convergence test of the
+  // previous sweep (its gathers and that test's reads are in flight
+  // together) and stored after.
   constexpr int kCells = kExBlock / kExLanes;
   const int lane = threadIdx.x % kExLanes;
   const int64_t j0 = blockIdx.x * (int64_t)kCells + threadIdx.x / kExLanes;
@@ -268,12 +303,13 @@ __global__ __launch_bounds__(kExBlock) void ex_finish_kernel(ExParams p) {
   // converged: the count the first idle sweep kernel recorded; otherwise
   // every sweep ran (the last one counts whether or not it met the tolerance)
   const int sweeps = p.info[4] ? p.info[2] : p.max_iter;
-  const double *fin = p.buf + (int64_t)(sweeps & 1) * 6 * N;
+  const double *fin = p.buf + (int64_t)(sweeps & 1) * kExRec * N;
   for (int64_t j = blockIdx.x * (int64_t)kExBlock + threadIdx.x; j < nd; j += (int64_t)gridDim.x * kExBlock) {
     const int P = p.list[j];
+    const double *rec = fin + (int64_t)P * kExRec;
     for (int d = 0; d < 3; ++d) {
-      p.gl[d * N + P] = fin[d * N + P];
-      p.gv[d * N + P] = fin[(3 + d) * N + P];
+      p.gl[d * N + P] = rec[d];
+      p.gv[d * N + P] = rec[3 + d];
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) p.info[2] = sweeps;
@@ -315,6 +351,7 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   VOFPC_REQUIRE(o.layers >= 0 && o.layers <= 100 && o.max_iter >= 0 && o.max_iter <= 100000 && o.tol >= 0 &&
                     o.eps_mixed >= 0 && o.eps_mixed < 0.5,
                 VOFPC_E_INVALID_ARG, "extrapolate: options out of range");
+  VOFPC_REQUIRE(M->ncf <= INT32_MAX, VOFPC_E_INVALID_ARG, "extrapolate: more than 2^31 - 1 cell-face slots");
   VOFPC_HIP(hipSetDevice(ctx->device));
   const int64_t N = M->d.n_cells, NF = M->d.n_faces;
   hipStream_t s = ctx->stream;
@@ -324,15 +361,17 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
     VOFPC_REQUIRE(cs == hipStreamCaptureStatusNone, VOFPC_E_STATE,
                   "extrapolate: the first call on a mesh sets up its buffers and must not be captured");
     void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr, *e = nullptr, *f = nullptr, *g = nullptr,
-         *h = nullptr;
+         *h = nullptr, *i = nullptr, *j = nullptr;
     vofpc_status st;
     if ((st = mesh_scratch_alloc(M, (size_t)N, &a)) || (st = mesh_scratch_alloc(M, 4 * (size_t)N, &b)) ||
         (st = mesh_scratch_alloc(M, 32, &c)) || (st = mesh_scratch_alloc(M, 16 * kExMaxGrid, &d)) ||
-        (st = mesh_scratch_alloc(M, 24 * (size_t)N, &e)) || (st = mesh_scratch_alloc(M, 96 * (size_t)N, &f)) ||
-        (st = mesh_scratch_alloc(M, 8 * (size_t)M->ncf, &g)) || (st = mesh_scratch_alloc(M, 8 * (size_t)N, &h)))
+        (st = mesh_scratch_alloc(M, 24 * (size_t)N, &e)) || (st = mesh_scratch_alloc(M, 16 * sizeof(double) * (size_t)N, &f)) ||
+        (st = mesh_scratch_alloc(M, 8 * (size_t)M->ncf, &g)) || (st = mesh_scratch_alloc(M, 8 * (size_t)N, &h)) ||
+        (st = mesh_scratch_alloc(M, 4 * (size_t)M->ncf, &i)) || (st = mesh_scratch_alloc(M, 8 * (size_t)N, &j)))
       return st;
     M->ex_mark = (int8_t *)a; M->ex_list = (int32_t *)b; M->ex_info = (int32_t *)c; M->ex_part = (double *)d;
     M->ex_nrm = (double *)e; M->ex_buf = (double *)f; M->ex_wup = (double *)g; M->ex_theta = (double *)h;
+    M->ex_upn = (int32_t *)i; M->ex_upr = (int2 *)j;
   }
   const unsigned gN = (unsigned)((N + kExBlock - 1) / kExBlock), gF = (unsigned)((NF + kExBlock - 1) / kExBlock);
   ex_init_kernel<<<gN, kExBlock, 0, s>>>(N, alpha, o.eps_mixed, M->ex_mark, M->ex_info);
@@ -359,6 +398,8 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   p.nrm = M->ex_nrm;
   p.buf = M->ex_buf;
   p.wup = M->ex_wup;
+  p.upn = M->ex_upn;
+  p.upr = M->ex_upr;
   p.theta = M->ex_theta;
   p.dtau = M->min_centre_dist;
   p.tol = o.tol;
@@ -371,7 +412,7 @@ extern "C" vofpc_status vofpc_extrapolate(vofpc_ctx ctx, vofpc_mesh M, const dou
   const unsigned gS = (unsigned)std::max<int64_t>(1, std::min<int64_t>(gN, (int64_t)ctx->n_cu * 2));
   const unsigned gW = (unsigned)std::max<int64_t>(
       1, std::min<int64_t>((N + kExBlock / kExLanes - 1) / (kExBlock / kExLanes),
-                           std::min<int64_t>((int64_t)ctx->n_cu * 4, kExMaxGrid)));
+                           std::min<int64_t>((int64_t)ctx->n_cu * kExBlocksPerCu, kExMaxGrid)));
   // the upwind stencil once; then one kernel per sweep: the kernel boundary
   // orders the sweeps, and once the tolerance is met the remaining sweep
   // kernels return at once

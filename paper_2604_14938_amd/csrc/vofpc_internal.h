@@ -147,9 +147,11 @@ struct vofpc_mesh_s {
   int32_t *ex_info = nullptr;      // [1] domain size, [2] sweeps done, [3] unused, [4] converged
   double *ex_part = nullptr;       // [2][grid] per-block largest change of the last two sweeps
   double *ex_nrm = nullptr;        // [3][n_cells] advection direction
-  double *ex_buf = nullptr;        // [2][6][n_cells]: G_l and G_v, two iterates
+  double *ex_buf = nullptr;        // [2][n_cells][8]: G_l and G_v per cell, two iterates
   double *ex_wup = nullptr;        // per cell-face slot: normalised upwind weight
   double *ex_theta = nullptr;      // per domain entry: pseudo-time fraction
+  int32_t *ex_upn = nullptr;       // per cell-face slot: neighbour of a packed upwind weight
+  int2 *ex_upr = nullptr;          // per domain entry: first slot and count of its upwind weights
   // interface coupling: mixed entry of each cell (-1 between calls)
   int32_t *rb_entry = nullptr;
   // curvature scratch: [3][n_cells] (smoothing ping-pong, raw and step-1

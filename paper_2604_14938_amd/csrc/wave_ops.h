@@ -59,11 +59,11 @@ __device__ __forceinline__ void pair_d(double v, double &lo, double &hi) {
 
 template <int W>
 __device__ __forceinline__ double gsum(double v) {
-  static_assert(W == 8 || W == 16 || W == 32 || W == 64, "group width");
+  static_assert(W == 4 || W == 8 || W == 16 || W == 32 || W == 64, "group width");
   v += dpp_d<kQuadXor1>(v);
   v += dpp_d<kQuadXor2>(v);
-  v += dpp_d<kHalfMirror>(v);
-  if (W >= 16) v += dpp_d<kRowMirror>(v);
+  if constexpr (W >= 8) v += dpp_d<kHalfMirror>(v);
+  if constexpr (W >= 16) v += dpp_d<kRowMirror>(v);
   if constexpr (W >= 32) { double lo, hi; pair_d<16>(v, lo, hi); v = lo + hi; }
   if constexpr (W >= 64) { double lo, hi; pair_d<32>(v, lo, hi); v = lo + hi; }
   return v;

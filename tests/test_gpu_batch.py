@@ -185,9 +185,12 @@ def test_follow_on_rows_on_a_concatenated_mesh(R):
     run.close()
 
 
-def test_learned_form_in_the_bucketed_launch(R):
-    """The learned bracket inside both kernel classes of a bucketed launch
-    (hexahedral and Voronoi cells together) gives the oracle's results."""
+@pytest.mark.parametrize("tune", [None, (3, 3, 3, 3), (4, 4, 4, 3), (14, 26, 4, 3), (12, 18, 26, 3)])
+def test_learned_form_in_the_bucketed_launch(R, tune):
+    """The learned bracket inside every kernel class of a bucketed launch
+    (hexahedral and Voronoi cells together) gives the oracle's results, with
+    the default flavours and with each flavour the tuner can pick per class
+    (the full workload's pick is 14, 26, 4, 3)."""
     import os
     import torch
     from paper_2604_14938_amd import train, vofpc as V
@@ -202,11 +205,14 @@ def test_learned_form_in_the_bucketed_launch(R):
     mlp.set_params(params)
     run = R.PathRun(wl, ctx=ctx, parts=[w.mesh for w in wls], mlp=mlp, delta_scale=dscale)
     assert run.mesh.classes()["bucketed"]
+    if tune is not None:
+        run.mesh.set_tune(list(tune))
+        assert run.mesh.classes()["tune"] == list(tune)
     run.step()
     g = run.results()
     fb = g["status"] == V.CELL_LEARNED_FALLBACK
     g["status"] = np.where(fb, V.CELL_OK, g["status"])
     rep = _check_step(wl, g)
-    _say(f"learned bucketed ok: {rep}; fallback rate {fb.mean():.3f}, mean evaluations {g['iters'].mean():.1f}")
+    _say(f"learned bucketed {tune} ok: {rep}; fallback rate {fb.mean():.3f}, mean evaluations {g['iters'].mean():.1f}")
     run.close()
     mlp.close()

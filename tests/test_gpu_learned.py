@@ -100,7 +100,7 @@ def _oracle_learned(name, wl, params, dscale):
     return out
 
 
-@pytest.mark.parametrize("f0,f1", [(3, 3), (14, 26), (12, 18), (11, 14)])
+@pytest.mark.parametrize("f0,f1", [(3, 3), (4, 4), (14, 26), (12, 18), (11, 14)])
 @pytest.mark.parametrize("name", ["vor12", "hex_bubbles", "batch"])
 def test_learned_flags_match_the_oracle_hint_path(V, weights, name, f0, f1):
     import torch
