@@ -36,12 +36,12 @@ extern "C" vofpc_status vofpc_ctx_create(int device, void *stream, vofpc_ctx *ou
   c->device = device;
   c->stream = (hipStream_t)stream;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  if (hipMalloc(&c->queue, 2 * sizeof(int)) != hipSuccess) {
+  if (hipMalloc(&c->queue, kQueueInts * sizeof(int)) != hipSuccess) {
     delete c;
     set_error("ctx_create: hipMalloc of the work-queue counters failed");
     return VOFPC_E_OOM;
   }
-  hipError_t e = hipMemset(c->queue, 0, 2 * sizeof(int));
+  hipError_t e = hipMemset(c->queue, 0, kQueueInts * sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     (void)hipFree(c->queue);

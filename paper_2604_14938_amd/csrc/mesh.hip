@@ -16,6 +16,19 @@ namespace vofpc {
 // ------------------------------------------------------------ geometry kernels
 // Face area vector (right-hand rule on the stored loop) and area centroid,
 // from the fan of triangles around the loop's vertex mean.
+// Each cell-face slot's outward area vector (the face's, signed for the
+// slot's cell), a cell's slots side by side.
+__global__ void slot_area_kernel(DevMesh m, double *cf_S) {
+  const int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (P >= m.n_cells) return;
+  const int64_t NF = m.n_faces;
+  for (int64_t i = m.cell_face_off[P]; i < m.cell_face_off[P + 1]; ++i) {
+    const int f = m.cell_face[i];
+    const double sg = (m.face_owner[f] == P) ? 1.0 : -1.0;
+    for (int c = 0; c < 3; ++c) cf_S[3 * i + c] = sg * m.Sf[c * NF + f];
+  }
+}
+
 __global__ void face_geom_kernel(DevMesh m, double *Sf, double *xf) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= m.n_faces) return;
@@ -444,6 +457,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   COPY(Sf, (const double *)nullptr, 3 * NF, double);
   COPY(xf, (const double *)nullptr, 3 * NF, double);
   COPY(ginv, (const double *)nullptr, 6 * N, double);
+  COPY(cf_S, (const double *)nullptr, 3 * ncf, double);
   M->n_blk = (N + kCompactBlockCells - 1) / kCompactBlockCells;
   {
     uint8_t *fl = nullptr;
@@ -481,6 +495,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   face_geom_kernel<<<(unsigned)((NF + B - 1) / B), B, 0, s>>>(m, (double *)m.Sf, (double *)m.xf);
   cell_geom_kernel<<<(unsigned)((N + B - 1) / B), B, 0, s>>>(m, m.Sf, m.xf, (double *)m.V, (double *)m.xc, bad);
   ginv_kernel<<<(unsigned)((N + B - 1) / B), B, 0, s>>>(m, m.xc, m.xf, (double *)m.ginv);
+  slot_area_kernel<<<(unsigned)((N + B - 1) / B), B, 0, s>>>(m, (double *)m.cf_S);
   vertex_weight_kernel<<<(unsigned)((NV + B - 1) / B), B, 0, s>>>(m, m.xc, (double *)m.vc_w, (double *)m.vc_wmean);
   // smallest distance between the centres of two face neighbours (the
   // pseudo-time step of the gradient extrapolation); as ordered bits of a
@@ -591,6 +606,7 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
   ALLOC(Sf, 3 * NF, double);
   ALLOC(xf, 3 * NF, double);
   ALLOC(ginv, 6 * N, double);
+  ALLOC(cf_S, 3 * ncf, double);
 #undef ALLOC
   M->n_blk = (N + kCompactBlockCells - 1) / kCompactBlockCells;
   {
@@ -663,6 +679,7 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
     CC((double *)m.vc_w + bvc, a.vc_w, A.nvc, 0, 0);
     CC((double *)m.vc_wmean + bvc, a.vc_wmean, A.nvc, 0, 0);
     CC((double *)m.V + bN, a.V, n_, 0, 0);
+    CC((double *)m.cf_S + 3 * bcf, a.cf_S, 3 * A.ncf, 0, 0);
     // structure-of-arrays fields, one component at a time
     for (int c = 0; c < 3; ++c) {
       CC((double *)m.xyz + c * NV + bV, a.xyz + c * nv_, nv_, 0, 0);

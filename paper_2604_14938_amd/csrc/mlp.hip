@@ -296,7 +296,6 @@ __global__ __launch_bounds__(64) void features_kernel(DevMesh m, const double *a
   FeatMem &L = F[g];
   int64_t count = counts[0];
   if (count > cap) count = cap;
-  const int64_t N = m.n_cells, NF = m.n_faces;
   for (int64_t k = (int64_t)blockIdx.x * G + g; k < count; k += (int64_t)gridDim.x * G) {
     const int P = mixed[k];
     const double aP = alpha[P];
@@ -344,9 +343,8 @@ __global__ __launch_bounds__(64) void features_kernel(DevMesh m, const double *a
     for (int q = 0; q < 20; ++q) s[q] = 0.0;
     double amin = __builtin_inf(), amax = -__builtin_inf();
     for (int f = lane; f < nf; f += W) {
-      const int fid = m.cell_face[f0 + f];
-      const double sg = (m.face_owner[fid] == P) ? 1.0 : -1.0;
-      const double S0 = sg * m.Sf[fid], S1 = sg * m.Sf[NF + fid], S2 = sg * m.Sf[2 * NF + fid];
+      const double *Sv = m.cf_S + 3 * (f0 + f);
+      const double S0 = Sv[0], S1 = Sv[1], S2 = Sv[2];
       const double A = sqrt(S0 * S0 + S1 * S1 + S2 * S2);
       const double n0 = S0 / A, n1 = S1 / A, n2 = S2 / A;
       const int q = m.cf_nbr[f0 + f];

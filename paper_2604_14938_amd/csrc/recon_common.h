@@ -38,7 +38,8 @@ struct ReconParams {
   const double *hint_lo, *hint_hi;
   double eps, tol_rel, iso;
   int max_iter, vertex_mode, fixed_iso, use_hint;
-  int *queue;   // claim counter of the cells beyond the first grid-size ones
+  int *queue;   // claim counters: the wavefront kernel's (cells beyond the first grid-size ones) at 0, then
+                // one per XCD for the group kernel (kQueueStride ints apart)
   // optional entry list of this launch (a face-count bucket): entries[j] for
   // j < *entry_count instead of every mixed entry
   const int32_t *entries;
@@ -53,6 +54,24 @@ struct ReconParams {
   MdotFuse mf;
   vofpc_interface out;
 };
+
+// The batches of a group-kernel launch in runs of kRun consecutive batches,
+// run r to XCD r % kXcd: consecutive mixed entries are mostly neighbouring
+// cells, which share vertices and faces, so a run is staged through one L2
+// instead of being spread over all of them.  xcd_count: the batches of XCD
+// x; xcd_batch: its i-th batch (runs in order, then batches within a run).
+template <int kRun>
+__device__ __forceinline__ int64_t xcd_count(int64_t nbatch, int x) {
+  const int64_t nrun = nbatch / kRun, rem = nbatch % kRun;
+  const int64_t full = nrun / kXcd + (x < nrun % kXcd ? 1 : 0);
+  return full * kRun + (x == nrun % kXcd ? rem : 0);
+}
+template <int kRun>
+__device__ __forceinline__ int64_t xcd_batch(int64_t i, int x) {
+  return ((i / kRun) * kXcd + x) * kRun + i % kRun;
+}
+// cells per run
+constexpr int kRunCells = 256;
 
 // Spacing of the doubles above |x|: the bit patterns of non-negative
 // doubles are ordered as their values, so the next double up is the pattern
@@ -86,14 +105,11 @@ struct NetFace {
 
 __device__ __forceinline__ NetFace load_net_face(const ReconParams &p, int P, double aP, int64_t slot) {
   const DevMesh &m = p.m;
-  const int64_t NFg = m.n_faces;
-  const int fid = m.cell_face[slot];
   const int q = m.cf_nbr[slot];
-  const double sg = (m.face_owner[fid] == P) ? 1.0 : -1.0;
   NetFace r;
-  r.S0 = sg * m.Sf[fid];
-  r.S1 = sg * m.Sf[NFg + fid];
-  r.S2 = sg * m.Sf[2 * NFg + fid];
+  r.S0 = m.cf_S[3 * slot];
+  r.S1 = m.cf_S[3 * slot + 1];
+  r.S2 = m.cf_S[3 * slot + 2];
   r.inner = q >= 0;
   r.aQ = r.inner ? p.alpha[q] : aP;
   return r;

@@ -47,8 +47,10 @@
 //
 // Scheduling: a wavefront takes 64/G consecutive mixed entries (a batch),
 // stages them together, runs their searches side by side until the last one
-// stops, writes them out and claims the next batch from a counter that
-// wraps back to zero after the launch's last claim.
+// stops, writes them out and claims the next batch.  The batches go to the
+// XCDs in runs of consecutive batches (neighbouring cells share an L2), and
+// each XCD's wavefronts claim its batches from a counter of its own that
+// wraps back to zero after the XCD's last claim.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -615,7 +617,15 @@ void recon_thin_kernel(ReconParams p) {
   int64_t count = p.entries ? (int64_t)*p.entry_count : (int64_t)p.counts[0];
   if (count > cap) count = cap;
   const int64_t nbatch = (count + C - 1) / C;
-  for (int64_t bt = blockIdx.x; bt < nbatch;) {
+  // this XCD's batches (runs of kRunCells cells): the first one per
+  // workgroup by its index, the rest claimed from the XCD's counter
+  constexpr int kRun = kRunCells / C;
+  const int xcd = (int)(blockIdx.x % kXcd);
+  const int64_t nx = xcd_count<kRun>(nbatch, xcd);
+  const int64_t wx = ((int64_t)gridDim.x - xcd + kXcd - 1) / kXcd;
+  unsigned int *claim = reinterpret_cast<unsigned int *>(p.queue + (1 + xcd) * kQueueStride);
+  for (int64_t ix = blockIdx.x / kXcd; ix < nx;) {
+    const int64_t bt = xcd_batch<kRun>(ix, xcd);
     const int64_t j = bt * C + sl;
     const bool active = j < count;
     // ---- phase 1, per cell: checks and staging
@@ -1071,11 +1081,11 @@ void recon_thin_kernel(ReconParams p) {
         p.out.iters[k] = it;
       }
     }
-    // next batch: a wrapping increment, so a launch's nbatch claims (one per
-    // batch done) bring the counter back to zero
+    // next batch: a wrapping increment, so the XCD's nx claims (one per
+    // batch done) bring its counter back to zero
     int nb = 0;
-    if (lane == 0) nb = (int)atomicInc((unsigned int *)p.queue, (unsigned int)(nbatch - 1));
-    bt = (int64_t)gridDim.x + __builtin_amdgcn_readfirstlane(nb);
+    if (lane == 0) nb = (int)atomicInc(claim, (unsigned int)(nx - 1));
+    ix = wx + __builtin_amdgcn_readfirstlane(nb);
     wave_sync();
   }
 }
@@ -1106,7 +1116,13 @@ __global__ __launch_bounds__(64) void bracket_pass_kernel(ReconParams p, double 
   int64_t count = p.entries ? (int64_t)*p.entry_count : (int64_t)p.counts[0];
   if (count > p.out.cap) count = p.out.cap;
   const int64_t nbatch = (count + C - 1) / C;
-  for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+  // this XCD's batches (runs of kRunCells cells), a fixed share per workgroup
+  constexpr int kRun = kRunCells / C;
+  const int xcd = (int)(blockIdx.x % kXcd);
+  const int64_t nx = xcd_count<kRun>(nbatch, xcd);
+  const int64_t wx = ((int64_t)gridDim.x - xcd + kXcd - 1) / kXcd;
+  for (int64_t ix = blockIdx.x / kXcd; ix < nx; ix += wx) {
+    const int64_t bt = xcd_batch<kRun>(ix, xcd);
     const int64_t j = bt * C + sl;
     const bool active = j < count;
     int64_t k = 0, f0 = 0;

@@ -50,6 +50,8 @@ struct DevMesh {
   const int32_t *cf_nbr;
   const uint16_t *cf_loff;
   const uint8_t *cf_lsz;
+  const double *cf_S;  // [slot][3]: the face's area vector pointing out of the slot's cell
+                       // (Sf or -Sf), a cell's slots contiguous
   // packed cell-local polyhedra: distinct vertices (global ids) and the
   // outward face loops as local vertex ids, faces in cell_face order
   const int64_t *cv_off;
@@ -77,6 +79,12 @@ struct DevMesh {
 
 // cells per block of the compaction kernels (sizes a mesh's block arrays)
 constexpr int kCompactBlockCells = 256;
+// XCDs of the chip (the hardware hands workgroup b to XCD b % kXcd; a
+// schedule built on this only gains or loses locality, never correctness)
+// and the spacing of the work-queue counters (one 128-byte line each)
+constexpr int kXcd = 8;
+constexpr int kQueueStride = 32;
+constexpr int kQueueInts = (1 + kXcd) * kQueueStride;
 
 // Reconstruction kernel classes: the template variants by the largest cell
 // they hold (vertices, faces, loop positions, edges): hexahedra and smaller
@@ -96,9 +104,10 @@ struct vofpc_ctx_s {
   int device;
   hipStream_t stream;
   int n_cu;
-  // claim counter of the reconstruction kernel's cell queue; zero between
-  // launches (each launch wraps it back), so calls on one context must not
-  // overlap
+  // claim counters of the reconstruction kernels' work queues (the
+  // wavefront kernel's at 0, the group kernel's one per XCD after it,
+  // kQueueStride ints apart); zero between launches (each launch wraps them
+  // back), so calls on one context must not overlap
   int *queue = nullptr;
   // per-class kernel timing of the reconstruction (eager launches only):
   // an event pair around each class kernel of the latest call, and around
