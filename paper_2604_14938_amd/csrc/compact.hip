@@ -8,6 +8,7 @@
 // in the number of blocks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -26,16 +27,38 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // Faces whose two cells lie on opposite sides of alpha = 1/2 put both cells
 // in the band (interior faces only).  `cross` is a per-cell byte array that
 // the cell pass reads and clears again, so the next step starts from zeros.
+// Each thread takes kFaceRun consecutive faces: their owners and neighbours
+// in two 16-byte loads, then every alpha they need in flight together.
+constexpr int kFaceRun = 4;
 __global__ __launch_bounds__(kCompactBlock) void compact_faces_kernel(DevMesh m, const double *alpha, uint8_t *cross) {
-  const int64_t f = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
-  if (f >= m.n_faces) return;
-  const int q = m.face_neigh[f];
-  if (q < 0) return;
-  const int o = m.face_owner[f];
-  if ((alpha[o] - 0.5) * (alpha[q] - 0.5) < 0.0) {
-    cross[o] = 1;
-    cross[q] = 1;
+  const int64_t f0 = (blockIdx.x * (int64_t)kCompactBlock + threadIdx.x) * kFaceRun;
+  const int64_t nf = m.n_faces;
+  if (f0 >= nf) return;
+  int o[kFaceRun], q[kFaceRun];
+  if (f0 + kFaceRun <= nf) {
+    const int4 ov = *reinterpret_cast<const int4 *>(m.face_owner + f0);
+    const int4 qv = *reinterpret_cast<const int4 *>(m.face_neigh + f0);
+    o[0] = ov.x; o[1] = ov.y; o[2] = ov.z; o[3] = ov.w;
+    q[0] = qv.x; q[1] = qv.y; q[2] = qv.z; q[3] = qv.w;
+  } else {
+#pragma unroll
+    for (int t = 0; t < kFaceRun; ++t) {
+      o[t] = f0 + t < nf ? m.face_owner[f0 + t] : 0;
+      q[t] = f0 + t < nf ? m.face_neigh[f0 + t] : -1;
+    }
   }
+  double ao[kFaceRun], aq[kFaceRun];
+#pragma unroll
+  for (int t = 0; t < kFaceRun; ++t) {
+    ao[t] = alpha[o[t]];
+    aq[t] = q[t] >= 0 ? alpha[q[t]] : 0.5;
+  }
+#pragma unroll
+  for (int t = 0; t < kFaceRun; ++t)
+    if (q[t] >= 0 && (ao[t] - 0.5) * (aq[t] - 0.5) < 0.0) {
+      cross[o[t]] = 1;
+      cross[q[t]] = 1;
+    }
 }
 
 // Per cell: bit 0 mixed (eps < alpha < 1-eps), bit 1 band (mixed, or a face
@@ -255,8 +278,9 @@ static vofpc_status compact_on(vofpc_ctx ctx, vofpc_mesh M, const double *alpha,
   if (M->max_nf <= 8) {
     compact_cells_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, flags, blk_cnt, nb);
   } else {
-    const int64_t nfb = (M->d.n_faces + kCompactBlock - 1) / kCompactBlock;
-    compact_faces_kernel<<<(unsigned)nfb, kCompactBlock, 0, s>>>(M->d, alpha, cross);
+    const int64_t per = (int64_t)kCompactBlock * kFaceRun;
+    const int64_t nfb = (M->d.n_faces + per - 1) / per;
+    compact_faces_kernel<<<(unsigned)std::max<int64_t>(nfb, 1), kCompactBlock, 0, s>>>(M->d, alpha, cross);
     compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, cross, flags, blk_cnt, nb);
   }
   const int scanned = nb > kScanBlocks ? 1 : 0;

@@ -2,7 +2,7 @@
 // modification of Sec. 2.4.4) and the mass transfer rate (Eq. mass_transfer,
 // Eq. latent_source).
 //
-// Sixteen lanes per cell, one face per lane.  The gradient gathers, for every
+// Eight lanes per cell, faces dealt round the lanes.  The gradient gathers, for every
 // face of the cell, the neighbour centroid, alpha and T (or the boundary face
 // centroid and value), so the least-squares matrix is accumulated from data
 // the right-hand side needs anyway; cells without a crossing face may instead
@@ -40,10 +40,10 @@ struct LsqSums {
   }
 };
 
-constexpr int kGradLanes = 16;   // lanes per cell (one DPP row)
+constexpr int kGradLanes = 8;   // lanes per cell (half a DPP row)
 
-// Gradient of cell P by the 16 lanes of one row: lane j takes faces j,
-// j+16, ...; the least-squares sums are reduced over the row.
+// Gradient of cell P by a group of kGradLanes lanes: lane j takes faces j,
+// j + kGradLanes, ...; the least-squares sums are reduced over the group.
 __device__ __forceinline__ void grad_cell(const GradParams &p, int P, int j) {
   const DevMesh &m = p.m;
   const int64_t N = m.n_cells, NF = m.n_faces;
@@ -119,8 +119,9 @@ __device__ __forceinline__ void grad_cell(const GradParams &p, int P, int j) {
   if (p.status) p.status[P] = st;
 }
 
-// A block of 256 lanes serves 16 cells at a time; every lane of a row
-// iterates the same cells, so the row's reductions see all its lanes.
+// A block of 256 lanes serves 256 / kGradLanes cells at a time; every lane
+// of a group iterates the same cells, so the group's reductions see all its
+// lanes.
 __global__ __launch_bounds__(256) void grad_kernel(GradParams p) {
   const int64_t n = (p.scope == VOFPC_SCOPE_ALL) ? p.m.n_cells : (int64_t)p.counts[1];
   constexpr int kCellsPerBlock = 256 / kGradLanes;
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256) void grad_kernel(GradParams p) {
   }
 }
 
-// Two gradients over the same band list in one launch (the row computes
+// Two gradients over the same band list in one launch (the group computes
 // both for its cell; used where a caller needs two fields' gradients on one
 // domain).
 __global__ __launch_bounds__(256) void grad2_kernel(GradParams a, GradParams b) {

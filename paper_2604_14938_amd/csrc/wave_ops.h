@@ -70,40 +70,44 @@ __device__ __forceinline__ double gsum(double v) {
 }
 template <int W>
 __device__ __forceinline__ int gsum_i(int v) {
+  static_assert(W == 4 || W == 8 || W == 16 || W == 32 || W == 64, "group width");
   v += dpp_i<kQuadXor1>(v);
   v += dpp_i<kQuadXor2>(v);
-  v += dpp_i<kHalfMirror>(v);
-  if (W >= 16) v += dpp_i<kRowMirror>(v);
+  if constexpr (W >= 8) v += dpp_i<kHalfMirror>(v);
+  if constexpr (W >= 16) v += dpp_i<kRowMirror>(v);
   if constexpr (W >= 32) { int lo, hi; pair_i<16>(v, lo, hi); v = lo + hi; }
   if constexpr (W >= 64) { int lo, hi; pair_i<32>(v, lo, hi); v = lo + hi; }
   return v;
 }
 template <int W>
 __device__ __forceinline__ int gmin_i(int v) {
+  static_assert(W == 4 || W == 8 || W == 16 || W == 32 || W == 64, "group width");
   v = min(v, dpp_i<kQuadXor1>(v));
   v = min(v, dpp_i<kQuadXor2>(v));
-  v = min(v, dpp_i<kHalfMirror>(v));
-  if (W >= 16) v = min(v, dpp_i<kRowMirror>(v));
+  if constexpr (W >= 8) v = min(v, dpp_i<kHalfMirror>(v));
+  if constexpr (W >= 16) v = min(v, dpp_i<kRowMirror>(v));
   if constexpr (W >= 32) { int lo, hi; pair_i<16>(v, lo, hi); v = min(lo, hi); }
   if constexpr (W >= 64) { int lo, hi; pair_i<32>(v, lo, hi); v = min(lo, hi); }
   return v;
 }
 template <int W>
 __device__ __forceinline__ double gmin(double v) {
+  static_assert(W == 4 || W == 8 || W == 16 || W == 32 || W == 64, "group width");
   v = fmin(v, dpp_d<kQuadXor1>(v));
   v = fmin(v, dpp_d<kQuadXor2>(v));
-  v = fmin(v, dpp_d<kHalfMirror>(v));
-  if (W >= 16) v = fmin(v, dpp_d<kRowMirror>(v));
+  if constexpr (W >= 8) v = fmin(v, dpp_d<kHalfMirror>(v));
+  if constexpr (W >= 16) v = fmin(v, dpp_d<kRowMirror>(v));
   if constexpr (W >= 32) { double lo, hi; pair_d<16>(v, lo, hi); v = fmin(lo, hi); }
   if constexpr (W >= 64) { double lo, hi; pair_d<32>(v, lo, hi); v = fmin(lo, hi); }
   return v;
 }
 template <int W>
 __device__ __forceinline__ double gmax(double v) {
+  static_assert(W == 4 || W == 8 || W == 16 || W == 32 || W == 64, "group width");
   v = fmax(v, dpp_d<kQuadXor1>(v));
   v = fmax(v, dpp_d<kQuadXor2>(v));
-  v = fmax(v, dpp_d<kHalfMirror>(v));
-  if (W >= 16) v = fmax(v, dpp_d<kRowMirror>(v));
+  if constexpr (W >= 8) v = fmax(v, dpp_d<kHalfMirror>(v));
+  if constexpr (W >= 16) v = fmax(v, dpp_d<kRowMirror>(v));
   if constexpr (W >= 32) { double lo, hi; pair_d<16>(v, lo, hi); v = fmax(lo, hi); }
   if constexpr (W >= 64) { double lo, hi; pair_d<32>(v, lo, hi); v = fmax(lo, hi); }
   return v;
