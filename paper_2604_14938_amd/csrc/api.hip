@@ -42,8 +42,13 @@ extern "C" vofpc_status vofpc_ctx_create(int device, void *stream, vofpc_ctx *ou
     return VOFPC_E_OOM;
   }
   hipError_t e = hipMemset(c->queue, 0, kQueueInts * sizeof(int));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->side) (void)hipStreamDestroy(c->side);
     (void)hipFree(c->queue);
     delete c;
     set_error(std::string("ctx_create: ") + hipGetErrorString(e));
@@ -65,6 +70,12 @@ extern "C" vofpc_status vofpc_ctx_destroy(vofpc_ctx ctx) {
   if (ctx && ctx->queue) {
     (void)hipSetDevice(ctx->device);
     (void)hipFree(ctx->queue);
+  }
+  if (ctx) {
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
   }
   if (ctx && ctx->time_classes)
     for (int c = 0; c < vofpc::kClasses; ++c)

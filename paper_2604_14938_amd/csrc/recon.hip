@@ -1247,6 +1247,11 @@ vofpc_status launch_class(vofpc_ctx ctx, vofpc_mesh M, const ReconParams &p, int
 }
 }  // namespace
 
+// The class that stays on the context's stream when a bucketed launch runs
+// the others beside it.
+constexpr int kMainClass = 1;
+constexpr bool kOverlapClasses = true;
+
 vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, const int32_t *mixed,
                                 const int32_t *counts, const vofpc_recon_opts *o, const double *hlo,
                                 const double *hhi, const vofpc_interface *out, vofpc_mlp net, double delta,
@@ -1368,14 +1373,33 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   bucket_kernel<<<(unsigned)std::max<int64_t>(bgrid, 1), kBucketBlock, 0, ctx->stream>>>(
       M->d, mixed, counts, out->cap, M->bucket_lists, N, M->bucket_counts);
   VOFPC_HIP(hipGetLastError());
-  for (int c = 0; c < kClasses; ++c) {
+  // the usual Voronoi class (with its bracket pass) on the context's stream,
+  // the other classes beside it on the side stream, forked after the
+  // bucketing and joined before the call returns (each class claims from
+  // its own counters), so one class's tail overlaps another's work
+  bool others = false;
+  for (int c = 0; c < kClasses; ++c) others = others || (c != kMainClass && M->class_cells[c] > 0);
+  const bool fork = kOverlapClasses && ctx->side && others && M->class_cells[kMainClass] > 0;
+  hipStream_t main_stream = ctx->stream;
+  if (fork) {
+    VOFPC_HIP(hipEventRecord(ctx->fork_ev, main_stream));
+    VOFPC_HIP(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+  }
+  vofpc_status st = VOFPC_OK;
+  for (int c = 0; c < kClasses && st == VOFPC_OK; ++c) {
     if (M->class_cells[c] == 0) continue;
     p.entries = M->bucket_lists + (int64_t)c * N;
     p.entry_count = M->bucket_counts + c;
-    vofpc_status st = run_class(M->class_cells[c], c);
-    if (st) return st;
+    p.queue = ctx->queue + c * kQueueSet;
+    if (fork && c != kMainClass) ctx->stream = ctx->side;
+    st = run_class(M->class_cells[c], c);
+    ctx->stream = main_stream;
   }
-  return VOFPC_OK;
+  if (fork) {
+    VOFPC_HIP(hipEventRecord(ctx->join_ev, ctx->side));
+    VOFPC_HIP(hipStreamWaitEvent(main_stream, ctx->join_ev, 0));
+  }
+  return st;
 }
 
 extern "C" vofpc_status vofpc_ctx_time_classes(vofpc_ctx ctx, int32_t enable) {

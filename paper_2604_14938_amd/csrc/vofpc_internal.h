@@ -84,13 +84,14 @@ constexpr int kCompactBlockCells = 256;
 // and the spacing of the work-queue counters (one 128-byte line each)
 constexpr int kXcd = 8;
 constexpr int kQueueStride = 32;
-constexpr int kQueueInts = (1 + kXcd) * kQueueStride;
+constexpr int kQueueSet = (1 + kXcd) * kQueueStride;   // the counters of one class launch
 
 // Reconstruction kernel classes: the template variants by the largest cell
 // they hold (vertices, faces, loop positions, edges): hexahedra and smaller
 // cells; the usual Voronoi cells (about 99.5 % of a jittered-BCC mesh's);
 // the larger Voronoi cells; anything larger.
 constexpr int kClasses = 4;
+constexpr int kQueueInts = kClasses * kQueueSet;   // one set per class: class launches may overlap
 __host__ __device__ inline int class_of(int64_t nv, int64_t nf, int64_t nl, int64_t ne) {
   if (nv <= 16 && nf <= 8 && nl <= 48 && ne <= 24) return 0;
   if (nv <= 32 && nf <= 20 && nl <= 96 && ne <= 48) return 1;
@@ -104,11 +105,16 @@ struct vofpc_ctx_s {
   int device;
   hipStream_t stream;
   int n_cu;
-  // claim counters of the reconstruction kernels' work queues (the
-  // wavefront kernel's at 0, the group kernel's one per XCD after it,
-  // kQueueStride ints apart); zero between launches (each launch wraps them
-  // back), so calls on one context must not overlap
+  // claim counters of the reconstruction kernels' work queues, one set of
+  // kQueueSet ints per class (the wavefront kernel's at 0, the group
+  // kernel's one per XCD after it, kQueueStride ints apart); zero between
+  // launches (each launch wraps them back), so calls on one context must not
+  // overlap
   int *queue = nullptr;
+  // second stream (default priority) for the class kernels that run beside
+  // the main class of a bucketed launch, with the fork and join events
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // per-class kernel timing of the reconstruction (eager launches only):
   // an event pair around each class kernel of the latest call, and around
   // its bracket pass (learned form) when it has one
