@@ -1,5 +1,6 @@
-// Mixed-cell and gradient-band compaction: a face pass for the band test
-// (meshes with cells of at most eight faces test it in the cell pass), a
+// Mixed-cell and gradient-band compaction: a side-bit pass and a face pass
+// for the band test (meshes with cells of at most eight faces test it in the
+// cell pass), a
 // cell pass with wavefront ballots and block totals, the exclusive prefix of
 // the block totals, and a scatter, giving stable (ascending) index lists and
 // their lengths in device memory.  Up to kScanBlocks blocks each scatter
@@ -24,22 +25,44 @@ constexpr int kScanThreads = 1024;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-// Faces whose two cells lie on opposite sides of alpha = 1/2 put both cells
-// in the band (interior faces only).  `cross` is a per-cell byte array that
-// the cell pass reads and clears again, so the next step starts from zeros.
-// Each thread takes kFaceRun consecutive faces: their owners and neighbours
-// in two 16-byte loads, then every alpha they need in flight together.
-constexpr int kFaceRun = 4;
-__global__ __launch_bounds__(kCompactBlock) void compact_faces_kernel(DevMesh m, const double *alpha, uint8_t *cross) {
+// The side of alpha = 1/2 of every cell as two bits, above (alpha > 1/2)
+// and below (alpha < 1/2; a NaN is neither): side[2w] and side[2w + 1] hold
+// the two bits of cells 64w .. 64w + 63, so the face pass gathers from
+// n_cells / 4 bytes (held in L2) instead of the 8-byte alphas.
+__global__ __launch_bounds__(kCompactBlock) void compact_side_kernel(int64_t n, const double *alpha,
+                                                                     uint64_t *side) {
+  const int64_t P = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
+  const double a = P < n ? alpha[P] : 0.5;
+  const uint64_t above = __ballot(a > 0.5), below = __ballot(a < 0.5);
+  if (lane_id() == 0) {
+    const int64_t w = P >> 6;
+    side[2 * w] = above;
+    side[2 * w + 1] = below;
+  }
+}
+
+// Faces whose two cells lie strictly on opposite sides of alpha = 1/2 (the
+// product of their alpha - 1/2 is negative) put both cells in the band
+// (interior faces only).  `cross` is a per-cell byte array that the cell
+// pass reads and clears again, so the next step starts from zeros.  Each
+// thread takes kFaceRun consecutive faces: their owners and neighbours in
+// two 16-byte loads, then every side word they need in flight together.
+constexpr int kFaceRun = 4;   // a multiple of 4
+static_assert(kFaceRun % 4 == 0, "whole 16-byte loads");
+__global__ __launch_bounds__(kCompactBlock) void compact_faces_kernel(DevMesh m, const uint64_t *side,
+                                                                      uint8_t *cross) {
   const int64_t f0 = (blockIdx.x * (int64_t)kCompactBlock + threadIdx.x) * kFaceRun;
   const int64_t nf = m.n_faces;
   if (f0 >= nf) return;
   int o[kFaceRun], q[kFaceRun];
   if (f0 + kFaceRun <= nf) {
-    const int4 ov = *reinterpret_cast<const int4 *>(m.face_owner + f0);
-    const int4 qv = *reinterpret_cast<const int4 *>(m.face_neigh + f0);
-    o[0] = ov.x; o[1] = ov.y; o[2] = ov.z; o[3] = ov.w;
-    q[0] = qv.x; q[1] = qv.y; q[2] = qv.z; q[3] = qv.w;
+#pragma unroll
+    for (int h = 0; h < kFaceRun; h += 4) {
+      const int4 ov = *reinterpret_cast<const int4 *>(m.face_owner + f0 + h);
+      const int4 qv = *reinterpret_cast<const int4 *>(m.face_neigh + f0 + h);
+      o[h] = ov.x; o[h + 1] = ov.y; o[h + 2] = ov.z; o[h + 3] = ov.w;
+      q[h] = qv.x; q[h + 1] = qv.y; q[h + 2] = qv.z; q[h + 3] = qv.w;
+    }
   } else {
 #pragma unroll
     for (int t = 0; t < kFaceRun; ++t) {
@@ -47,18 +70,23 @@ __global__ __launch_bounds__(kCompactBlock) void compact_faces_kernel(DevMesh m,
       q[t] = f0 + t < nf ? m.face_neigh[f0 + t] : -1;
     }
   }
-  double ao[kFaceRun], aq[kFaceRun];
+  const ulonglong2 *sw = reinterpret_cast<const ulonglong2 *>(side);
+  ulonglong2 so[kFaceRun], sq[kFaceRun];
 #pragma unroll
   for (int t = 0; t < kFaceRun; ++t) {
-    ao[t] = alpha[o[t]];
-    aq[t] = q[t] >= 0 ? alpha[q[t]] : 0.5;
+    so[t] = sw[o[t] >> 6];
+    sq[t] = q[t] >= 0 ? sw[q[t] >> 6] : ulonglong2{0ull, 0ull};
   }
 #pragma unroll
-  for (int t = 0; t < kFaceRun; ++t)
-    if (q[t] >= 0 && (ao[t] - 0.5) * (aq[t] - 0.5) < 0.0) {
+  for (int t = 0; t < kFaceRun; ++t) {
+    if (q[t] < 0) continue;
+    const int bo = o[t] & 63, bq = q[t] & 63;
+    const uint64_t cr = ((so[t].x >> bo) & (sq[t].y >> bq)) | ((so[t].y >> bo) & (sq[t].x >> bq));
+    if (cr & 1ull) {
       cross[o[t]] = 1;
       cross[q[t]] = 1;
     }
+  }
 }
 
 // Per cell: bit 0 mixed (eps < alpha < 1-eps), bit 1 band (mixed, or a face
@@ -268,9 +296,11 @@ __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(int64_t 
 
 // The compaction on the given scratch: flags [n_cells] bytes, cross
 // [n_cells] bytes (zero on entry; the cell pass clears what the face pass
-// set) and blk_cnt [2][n_blk].
+// set), blk_cnt [2][n_blk] and side [2][ceil(n_cells / 64)] words (16-byte
+// aligned; written before it is read).
 static vofpc_status compact_on(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, double eps, int32_t *mixed,
-                               int32_t *band, int32_t *counts, uint8_t *flags, uint8_t *cross, int32_t *blk_cnt) {
+                               int32_t *band, int32_t *counts, uint8_t *flags, uint8_t *cross, int32_t *blk_cnt,
+                               uint64_t *side) {
   VOFPC_REQUIRE(alpha && mixed && band && counts, VOFPC_E_INVALID_ARG, "compact: null pointer");
   VOFPC_REQUIRE(eps >= 0 && eps < 0.5, VOFPC_E_INVALID_ARG, "compact: eps_mixed must be in [0, 0.5)");
   const int64_t nb = M->n_blk;
@@ -278,9 +308,10 @@ static vofpc_status compact_on(vofpc_ctx ctx, vofpc_mesh M, const double *alpha,
   if (M->max_nf <= 8) {
     compact_cells_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, flags, blk_cnt, nb);
   } else {
+    compact_side_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d.n_cells, alpha, side);
     const int64_t per = (int64_t)kCompactBlock * kFaceRun;
     const int64_t nfb = (M->d.n_faces + per - 1) / per;
-    compact_faces_kernel<<<(unsigned)std::max<int64_t>(nfb, 1), kCompactBlock, 0, s>>>(M->d, alpha, cross);
+    compact_faces_kernel<<<(unsigned)std::max<int64_t>(nfb, 1), kCompactBlock, 0, s>>>(M->d, side, cross);
     compact_flags_kernel<<<(unsigned)nb, kCompactBlock, 0, s>>>(M->d, alpha, eps, cross, flags, blk_cnt, nb);
   }
   const int scanned = nb > kScanBlocks ? 1 : 0;
@@ -293,19 +324,22 @@ static vofpc_status compact_on(vofpc_ctx ctx, vofpc_mesh M, const double *alpha,
 
 vofpc_status launch_compact(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, double eps, int32_t *mixed,
                             int32_t *band, int32_t *counts) {
-  return compact_on(ctx, M, alpha, eps, mixed, band, counts, M->flags, M->cross, M->blk_cnt);
+  return compact_on(ctx, M, alpha, eps, mixed, band, counts, M->flags, M->cross, M->blk_cnt, M->side);
 }
 
 // ---------------------------------------------------------------- no allocation
 // The compaction's scratch for callers that cannot allocate: one file-scope
 // device array per GPU, held until the process ends, laid out as flags
-// [kNoAllocMaxCells] bytes, band marks [kNoAllocMaxCells] bytes and block
-// totals [2][kNoAllocMaxBlocks] int32.  In host code the array's name is not
+// [kNoAllocMaxCells] bytes, band marks [kNoAllocMaxCells] bytes, block
+// totals [2][kNoAllocMaxBlocks] int32 and side bits [2][kNoAllocMaxCells /
+// 64] words.  In host code the array's name is not
 // a device address: each device's address comes from hipGetSymbolAddress
 // (once per device, with that device current) and only that address is used.
 constexpr int64_t kNoAllocMaxCells = int64_t(1) << 23;   // 8,388,608 cells
 constexpr int64_t kNoAllocMaxBlocks = kNoAllocMaxCells / kCompactBlock;
-constexpr int64_t kNoAllocBytes = 2 * kNoAllocMaxCells + 2 * kNoAllocMaxBlocks * (int64_t)sizeof(int32_t);
+constexpr int64_t kNoAllocSideOffset = 2 * kNoAllocMaxCells + 2 * kNoAllocMaxBlocks * (int64_t)sizeof(int32_t);
+constexpr int64_t kNoAllocBytes = kNoAllocSideOffset + 2 * (kNoAllocMaxCells / 64) * (int64_t)sizeof(uint64_t);
+static_assert(kNoAllocSideOffset % 16 == 0, "side words 16-byte aligned");
 static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
 
 constexpr int kNoAllocMaxDevices = 64;
@@ -349,9 +383,10 @@ extern "C" vofpc_status vofpc_compact_noalloc(vofpc_ctx ctx, vofpc_mesh mesh, co
   }
   uint8_t *flags = base, *cross = base + kNoAllocMaxCells;
   int32_t *blk_cnt = reinterpret_cast<int32_t *>(base + 2 * kNoAllocMaxCells);
+  uint64_t *side = reinterpret_cast<uint64_t *>(base + kNoAllocSideOffset);
   // the band marks must start at zero: the array keeps the last call's
   // contents (a call that stopped early may have left marks)
   zero_bytes_kernel<<<(unsigned)((N + kCompactBlock - 1) / kCompactBlock), kCompactBlock, 0, ctx->stream>>>(cross, N);
   VOFPC_HIP(hipGetLastError());
-  return compact_on(ctx, mesh, alpha, eps, mixed_idx, band_idx, counts, flags, cross, blk_cnt);
+  return compact_on(ctx, mesh, alpha, eps, mixed_idx, band_idx, counts, flags, cross, blk_cnt, side);
 }

@@ -474,6 +474,12 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
     }
     M->cross = cr;
     VOFPC_HIP(hipMemset(cr, 0, (size_t)std::max<int64_t>(N, 1)));
+    uint64_t *sd = nullptr;
+    if ((st = dev_copy<uint64_t>(M, nullptr, 2 * ((N + 63) / 64), &sd))) {
+      vofpc_mesh_free(M);
+      return st;
+    }
+    M->side = sd;
   }
   int32_t *bad = nullptr;
   if ((st = dev_copy<int32_t>(M, nullptr, 1, &bad))) {
@@ -624,6 +630,12 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
     }
     M->cross = cr;
     VOFPC_HIP(hipMemset(cr, 0, (size_t)std::max<int64_t>(N, 1)));
+    uint64_t *sd = nullptr;
+    if ((st = dev_copy<uint64_t>(M, nullptr, 2 * ((N + 63) / 64), &sd))) {
+      vofpc_mesh_free(M);
+      return st;
+    }
+    M->side = sd;
   }
   M->max_nf = mx[0]; M->max_nv = mx[1]; M->max_fv = mx[2]; M->max_ne = mx[3]; M->max_loop = mx[4];
   M->ncf = ncf; M->nfv = nfv; M->ncv = ncv; M->ncl = ncl; M->nvc = nvc;

@@ -137,6 +137,7 @@ struct vofpc_mesh_s {
   uint8_t *flags;
   uint8_t *cross;     // band marks of the face pass (zero between calls)
   int32_t *blk_cnt;   // [2][n_blocks]
+  uint64_t *side;     // [2][ceil(n_cells / 64)]: the side of alpha = 1/2 of each cell as bits
   int64_t n_blk;
   // cells per kernel class; the class of the largest cell; bucketed meshes
   // (cells spread over several classes) launch one variant per class over
@@ -179,7 +180,7 @@ struct vofpc_mesh_s {
   // vertex-neighbour gradient stencil (built by its first use): CSR over cells
   int64_t *xn_off = nullptr;
   int32_t *xn_cell = nullptr;
-  void *alloc[64];
+  void *alloc[96];
   int n_alloc;
 };
 
