@@ -188,8 +188,9 @@ vofpc_status vofpc_compact(vofpc_ctx ctx, vofpc_mesh mesh, const double *alpha, 
 /* For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid allocation): vofpc_compact with
  * the same arguments and results, its scratch (per-cell flag and band-mark
- * bytes, per-block totals) taken from a fixed array the library holds on
- * each GPU until the process ends (about 17 MB) instead of the mesh's; it
+ * bytes, per-block totals, per-cell side bits) taken from a fixed array the
+ * library holds on each GPU until the process ends (about 19 MB) instead of
+ * the mesh's; it
  * allocates nothing.  Meshes of at most 8,388,608 cells; larger ones give
  * VOFPC_E_INVALID_ARG.  Every call on one GPU shares that array: calls that
  * overlap in time on one GPU (other streams, other threads) race and give
