@@ -159,11 +159,21 @@ vofpc_status vofpc_mesh_classes(vofpc_mesh mesh, int64_t cells[4], int32_t tune[
  * accept any value.  VOFPC_E_INVALID_ARG (nothing changed) when a class with
  * cells is given a flavour that has no build for it. */
 vofpc_status vofpc_mesh_set_tune(vofpc_mesh mesh, const int32_t tune[4]);
+/* Class launches side by side (default on).  A bucketed reconstruction runs
+ * the usual Voronoi class (1) and its bracket pass on the context's stream
+ * and the other classes beside it on a second stream the context owns
+ * (default priority), forked after the bucketing and joined before the call
+ * returns, so one class's idle issue slots and tail are filled by another's
+ * work.  With enable = 0 every class runs in turn on the context's stream
+ * (then each class kernel's time is its own).  Results are the same either
+ * way, bit for bit. */
+vofpc_status vofpc_ctx_overlap_classes(vofpc_ctx ctx, int32_t enable);
 /* Per-class kernel timing of the reconstruction (a measurement aid).  With
  * enable != 0, every later eager reconstruction on this context records a HIP
- * event pair on the context stream around each class kernel it launches, and
- * around the class's bracket pass when the learned form runs one (none while
- * the stream is being captured); enable = 0 destroys the events.
+ * event pair around each class kernel it launches, on the stream the kernel
+ * runs on, and around the class's bracket pass when the learned form runs
+ * one (none while the stream is being captured); enable = 0 destroys the
+ * events.
  * vofpc_ctx_class_ms waits for the latest call's events and writes to HOST
  * ms[8] the duration in milliseconds of each class kernel (ms[0..3]) and of
  * each bracket pass (ms[4..7]), -1 where none ran, then forgets them;

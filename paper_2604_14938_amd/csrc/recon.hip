@@ -1250,7 +1250,6 @@ vofpc_status launch_class(vofpc_ctx ctx, vofpc_mesh M, const ReconParams &p, int
 // The class that stays on the context's stream when a bucketed launch runs
 // the others beside it.
 constexpr int kMainClass = 1;
-constexpr bool kOverlapClasses = true;
 
 vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha, const int32_t *mixed,
                                 const int32_t *counts, const vofpc_recon_opts *o, const double *hlo,
@@ -1379,7 +1378,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   // its own counters), so one class's tail overlaps another's work
   bool others = false;
   for (int c = 0; c < kClasses; ++c) others = others || (c != kMainClass && M->class_cells[c] > 0);
-  const bool fork = kOverlapClasses && ctx->side && others && M->class_cells[kMainClass] > 0;
+  const bool fork = ctx->overlap_classes && ctx->side && others && M->class_cells[kMainClass] > 0;
   hipStream_t main_stream = ctx->stream;
   if (fork) {
     VOFPC_HIP(hipEventRecord(ctx->fork_ev, main_stream));
@@ -1400,6 +1399,14 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
     VOFPC_HIP(hipStreamWaitEvent(main_stream, ctx->join_ev, 0));
   }
   return st;
+}
+
+extern "C" vofpc_status vofpc_ctx_overlap_classes(vofpc_ctx ctx, int32_t enable) {
+  using namespace vofpc;
+  clear_error();
+  VOFPC_REQUIRE(ctx, VOFPC_E_INVALID_ARG, "ctx_overlap_classes: null context");
+  ctx->overlap_classes = enable != 0;
+  return VOFPC_OK;
 }
 
 extern "C" vofpc_status vofpc_ctx_time_classes(vofpc_ctx ctx, int32_t enable) {

@@ -115,6 +115,7 @@ struct vofpc_ctx_s {
   // the main class of a bucketed launch, with the fork and join events
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool overlap_classes = true;   // use the second stream (vofpc_ctx_overlap_classes)
   // per-class kernel timing of the reconstruction (eager launches only):
   // an event pair around each class kernel of the latest call, and around
   // its bracket pass (learned form) when it has one

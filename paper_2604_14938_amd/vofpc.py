@@ -104,6 +104,7 @@ def _load():
         "vofpc_mesh_classes": ([P, P, P, P], ctypes.c_int),
         "vofpc_mesh_set_tune": ([P, P], ctypes.c_int),
         "vofpc_ctx_time_classes": ([P, ctypes.c_int32], ctypes.c_int),
+        "vofpc_ctx_overlap_classes": ([P, ctypes.c_int32], ctypes.c_int),
         "vofpc_ctx_class_ms": ([P, P], ctypes.c_int),
         "vofpc_extrap_opts_default": ([P], ctypes.c_int),
         "vofpc_extrapolate": ([P, P, P, P, P, D, P, P, P, P, P, P, P], ctypes.c_int),
@@ -163,6 +164,11 @@ class Context:
     def set_stream(self, stream: torch.cuda.Stream) -> None:
         self.stream = stream
         _check(lib.vofpc_ctx_set_stream(self.h, stream.cuda_stream), "vofpc_ctx_set_stream")
+
+    def overlap_classes(self, enable: bool = True) -> None:
+        """Run the classes of a bucketed reconstruction side by side on two
+        streams (the default) or in turn (vofpc_ctx_overlap_classes)."""
+        _check(lib.vofpc_ctx_overlap_classes(self.h, int(bool(enable))), "vofpc_ctx_overlap_classes")
 
     def time_classes(self, enable: bool = True) -> None:
         """Record an event pair around each class kernel of later eager

@@ -226,3 +226,37 @@ def test_learned_form_in_the_bucketed_launch(R, tune):
     _say(f"learned bucketed {tune} ok: {rep}; fallback rate {fb.mean():.3f}, mean evaluations {g['iters'].mean():.1f}")
     run.close()
     mlp.close()
+
+
+@pytest.mark.parametrize("form", ["plain", "learned"])
+def test_classes_side_by_side_or_in_turn_give_the_same_bits(R, form):
+    """A bucketed step with the classes on two streams (the default) and
+    with them in turn on one: every output bit for bit the same."""
+    import os
+    import torch
+    from paper_2604_14938_amd import train, vofpc as V
+    wls = workloads.batched(hex_n=24, vor_n=12, seed=11, n_max=200, K=12, r_hi_h=3.0)
+    wl = workloads.concat_workloads(wls)
+    mlp = dscale = None
+    ctx = V.Context(0, stream=torch.cuda.Stream())
+    if form == "learned":
+        if not os.path.exists(train.DEFAULT_WEIGHTS):
+            pytest.skip("no trained weights")
+        params, dscale, _ = train.load()
+        mlp = V.Mlp(ctx)
+        mlp.set_params(params)
+    run = R.PathRun(wl, ctx=ctx, parts=[w.mesh for w in wls], mlp=mlp, delta_scale=dscale or 0.0)
+    cls = run.mesh.classes()
+    assert cls["bucketed"] and cls["cells"][1] > 0 and cls["cells"][0] > 0
+    _say(f"classes side by side / in turn ({form}): {wl.n_mixed} mixed, tune {cls['tune']}")
+    out = []
+    for overlap in (True, False, True):
+        run.ctx.overlap_classes(overlap)
+        run.step()
+        out.append(run.results())
+    for g in out[1:]:
+        for k in ("mixed_idx", "status", "iters", "s", "n", "A", "d", "alpha_got", "mdot", "gradT"):
+            np.testing.assert_array_equal(np.asarray(g[k]).view(np.uint8), np.asarray(out[0][k]).view(np.uint8), k)
+    run.close()
+    if mlp is not None:
+        mlp.close()
