@@ -34,7 +34,9 @@ __global__ __launch_bounds__(kCompactBlock) void compact_side_kernel(int64_t n, 
   const int64_t P = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x;
   const double a = P < n ? alpha[P] : 0.5;
   const uint64_t above = __ballot(a > 0.5), below = __ballot(a < 0.5);
-  if (lane_id() == 0) {
+  // lane 0 holds the wavefront's first cell: only wavefronts that start
+  // inside the mesh have a word (the array holds ceil(n / 64) of them)
+  if (lane_id() == 0 && P < n) {
     const int64_t w = P >> 6;
     side[2 * w] = above;
     side[2 * w + 1] = below;

@@ -54,6 +54,9 @@ def test_null_arguments_are_rejected_without_touching_the_device():
     assert lib.vofpc_ctx_create(0, None, None) == -1
     assert lib.vofpc_mesh_free(None) == 0
     assert lib.vofpc_graph_destroy(None) == 0
+    for name in ("vofpc_ctx_overlap_classes", "vofpc_ctx_time_classes"):
+        assert getattr(lib, name)(None, 1) == -1, name
+        assert b"null context" in lib.vofpc_last_error(), name
 
 
 def test_product_package_does_not_import_the_oracle():
