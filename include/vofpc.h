@@ -79,7 +79,11 @@ int vofpc_version(void);
 /* ------------------------------------------------------------------ context */
 /* Create a context on HIP device `device`, issuing work on `hip_stream` (a
  * hipStream_t; NULL = the device's null stream).  The stream must stay valid
- * while the context uses it.  *out receives the handle. */
+ * while the context uses it.  The context also creates a second stream of
+ * its own (default priority) that a bucketed reconstruction forks to and
+ * joins back before returning (vofpc_ctx_overlap_classes), so synchronising
+ * the context's stream still covers all of a call's work.  *out receives
+ * the handle. */
 vofpc_status vofpc_ctx_create(int device, void *hip_stream, vofpc_ctx *out);
 /* Change the stream later work is issued on. */
 vofpc_status vofpc_ctx_set_stream(vofpc_ctx ctx, void *hip_stream);
