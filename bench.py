@@ -52,6 +52,7 @@ FLOPS_HEX_CELL = 18.5e3
 # kernel classes by cell size: largest vertices, faces, loop positions and
 # edges of a cell each class's kernels are built for (class 3: larger)
 CLASS_CAPS = ((16, 8, 48, 24), (32, 20, 96, 48), (48, 32, 128, 64))
+HEX_CAPS = (8, 6, 24, 12)
 STATUS_NAMES = ("ok", "not_mixed", "learned_fallback", "degenerate", "max_iter", "g_singular", "bad_input",
                 "no_root")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "recon_kernel_traffic.json")
@@ -86,15 +87,36 @@ def cell_incidence(mesh, cells: np.ndarray):
     return key // mesh.n_verts, key % mesh.n_verts, nf, nl
 
 
-def cell_classes(mesh, cells: np.ndarray) -> np.ndarray:
-    """Kernel class of each cell: the first whose caps hold its vertices,
-    faces, loop positions and edges (loop positions / 2)."""
+def _classes_and_hex(mesh, cells: np.ndarray):
     row, _, nf, nl = cell_incidence(mesh, cells)
     nv = np.bincount(row, minlength=len(cells))
     out = np.full(len(cells), len(CLASS_CAPS), np.int64)
     for c in range(len(CLASS_CAPS) - 1, -1, -1):
         v, f, l, e = CLASS_CAPS[c]
         out[(nv <= v) & (nf <= f) & (nl <= l) & (nl // 2 <= e)] = c
+    v, f, l, e = HEX_CAPS
+    return out, (nv <= v) & (nf <= f) & (nl <= l) & (nl // 2 <= e)
+
+
+def mesh_hex0(mesh) -> bool:
+    """Whether the mesh's class 0 is all but at most 1 % hexahedral-sized
+    cells (then the library moves the other class-0 cells to class 1)."""
+    cls, hexfit = _classes_and_hex(mesh, np.arange(mesh.n_cells))
+    c0 = int(np.count_nonzero(cls == 0))
+    rest = c0 - int(np.count_nonzero((cls == 0) & hexfit))
+    return rest > 0 and rest * 100 <= c0
+
+
+def cell_classes(mesh, cells: np.ndarray, hex0: bool | None = None) -> np.ndarray:
+    """Kernel class of each cell as the library assigns it: the first class
+    whose caps hold its vertices, faces, loop positions and edges (loop
+    positions / 2), class-0 cells beyond the hexahedral caps in class 1 when
+    the mesh's class 0 is hexahedral (mesh_hex0)."""
+    out, hexfit = _classes_and_hex(mesh, cells)
+    if hex0 is None:
+        hex0 = mesh_hex0(mesh)
+    if hex0:
+        out[(out == 0) & ~hexfit] = 1
     return out
 
 

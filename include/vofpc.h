@@ -139,7 +139,11 @@ vofpc_status vofpc_mesh_info(vofpc_mesh mesh, int64_t info[8]);
 /* Kernel classes of the mesh's cells (HOST outputs, any may be NULL): cells[c]
  * = number of cells whose size (vertices, faces, loop positions, edges) fits
  * class c = 0 (<= 16, 8, 48, 24: hexahedra and smaller), 1 (<= 32, 20, 96,
- * 48: the usual Voronoi cells), 2 (<= 48, 32, 128, 64) or 3 (larger); tune[c]
+ * 48: the usual Voronoi cells), 2 (<= 48, 32, 128, 64) or 3 (larger), the
+ * smallest that holds it; when all but at most 1 % of a mesh's class-0 cells
+ * are within the hexahedral sizes (8, 6, 24, 12), the other class-0 cells
+ * are counted in class 1 instead, so that class 0 runs the hexahedral
+ * layout (a mixed hexahedral and Voronoi mesh); tune[c]
  * = the reconstruction kernel flavour used for class c (see
  * vofpc_mesh_set_tune); *bucketed = 1 when the cells spread over several
  * classes: then the reconstruction splits the mixed entries by class and

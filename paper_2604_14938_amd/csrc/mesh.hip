@@ -239,10 +239,27 @@ vofpc_status mesh_vertex_stencil(vofpc_mesh M) {
 }
 
 // Kernel classes of a mesh: the class of its largest cell, and whether its
-// cells spread over several classes (each holding at least 1 % of the cells),
-// in which case the reconstruction buckets its mixed entries by class.
-static vofpc_status setup_classes(vofpc_mesh M, const int64_t *class_cnt, const int64_t (*cmax)[4]) {
+// cells spread over several classes, in which case the reconstruction
+// buckets its mixed entries by class.  When all but at most 1 % of class 0
+// are hexahedral-sized cells the others move to class 1 (mesh_class_of).
+static vofpc_status setup_classes(vofpc_mesh M, const ClassStats &cs) {
   const int64_t N = M->d.n_cells;
+  M->class_stats = cs;
+  int64_t class_cnt[kClasses], cmax[kClasses][4];
+  for (int c = 0; c < kClasses; ++c) {
+    class_cnt[c] = cs.cnt[c];
+    for (int t = 0; t < 4; ++t) cmax[c][t] = cs.max[c][t];
+  }
+  const int64_t rest = cs.cnt[0] - cs.hex_cnt;
+  M->hex0 = rest > 0 && rest * 100 <= cs.cnt[0];
+  if (M->hex0) {
+    class_cnt[0] = cs.hex_cnt;
+    class_cnt[1] += rest;
+    for (int t = 0; t < 4; ++t) {
+      cmax[0][t] = cs.hex_max[t];
+      cmax[1][t] = std::max(cmax[1][t], cs.rest_max[t]);
+    }
+  }
   int big = 0;
   M->max_class = 0;
   for (int c = 0; c < kClasses; ++c) {
@@ -320,8 +337,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   cv_gid.reserve(ncf * 2);
   cl_lv.reserve(nfv * 2);
   int64_t max_nf = 0, max_nv = 0, max_fv = 0, max_ne = 0, max_loop = 0;
-  int64_t class_cnt[kClasses] = {0, 0, 0, 0};
-  int64_t class_max[kClasses][4] = {};
+  ClassStats class_stats;
   std::vector<int32_t> loc;
   std::vector<uint16_t> dedge;
   for (int64_t P = 0; P < N; ++P) {
@@ -398,9 +414,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
     {
       const int64_t sz[4] = {(int64_t)loc.size(), cfo[P + 1] - cfo[P], cl_off[P + 1] - cl_off[P],
                              (int64_t)dedge.size() / 2};
-      const int c = class_of(sz[0], sz[1], sz[2], sz[3]);
-      class_cnt[c]++;
-      for (int t = 0; t < 4; ++t) class_max[c][t] = std::max(class_max[c][t], sz[t]);
+      class_stats.add(sz);
     }
   }
   // vertex -> cell incidence (cells ascending)
@@ -490,7 +504,7 @@ vofpc_status mesh_upload(vofpc_ctx ctx, const vofpc_mesh_desc *d, vofpc_mesh *ou
   M->max_nf = max_nf; M->max_nv = max_nv; M->max_fv = max_fv; M->max_ne = max_ne; M->max_loop = max_loop;
   M->ncf = ncf; M->nfv = nfv; M->ncv = (int64_t)cv_gid.size(); M->ncl = (int64_t)cl_lv.size();
   M->nvc = (int64_t)vc_cell.size();
-  if ((st = setup_classes(M, class_cnt, class_max))) {
+  if ((st = setup_classes(M, class_stats))) {
     vofpc_mesh_free(M);
     return st;
   }
@@ -640,17 +654,13 @@ vofpc_status mesh_concat(vofpc_ctx ctx, const vofpc_mesh *ms, int32_t n, vofpc_m
   M->max_nf = mx[0]; M->max_nv = mx[1]; M->max_fv = mx[2]; M->max_ne = mx[3]; M->max_loop = mx[4];
   M->ncf = ncf; M->nfv = nfv; M->ncv = ncv; M->ncl = ncl; M->nvc = nvc;
   {
-    int64_t cc[kClasses] = {0, 0, 0, 0};
-    int64_t cm[kClasses][4] = {};
+    ClassStats cs;
     M->min_centre_dist = ms[0]->min_centre_dist;
     for (int i = 0; i < n; ++i) {
-      for (int c = 0; c < kClasses; ++c) {
-        cc[c] += ms[i]->class_cells[c];
-        for (int t = 0; t < 4; ++t) cm[c][t] = std::max(cm[c][t], ms[i]->class_max[c][t]);
-      }
+      cs.merge(ms[i]->class_stats);
       M->min_centre_dist = std::min(M->min_centre_dist, ms[i]->min_centre_dist);
     }
-    if ((st = setup_classes(M, cc, cm))) {
+    if ((st = setup_classes(M, cs))) {
       vofpc_mesh_free(M);
       return st;
     }

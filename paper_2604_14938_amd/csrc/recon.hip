@@ -1160,12 +1160,13 @@ __global__ __launch_bounds__(64, OCC) void recon_kernel(ReconParams p) {
 }
 
 // ----------------------------------------------------------------- buckets
-// Kernel class of a cell: the smallest template variant that holds it.
-__device__ __forceinline__ int cell_class(const DevMesh &m, int P) {
+// Kernel class of a cell: the smallest template variant that holds it (with
+// the mesh's hexahedral class 0, mesh_class_of).
+__device__ __forceinline__ int cell_class(const DevMesh &m, bool hex0, int P) {
   const int64_t nf = m.cell_face_off[P + 1] - m.cell_face_off[P];
   const int64_t nv = m.cv_off[P + 1] - m.cv_off[P];
   const int64_t nl = m.cl_off[P + 1] - m.cl_off[P];
-  return class_of(nv, nf, nl, nl / 2);
+  return mesh_class_of(hex0, nv, nf, nl, nl / 2);
 }
 
 __global__ void bucket_zero_kernel(int32_t *c) {
@@ -1177,9 +1178,9 @@ __global__ void bucket_zero_kernel(int32_t *c) {
 // stride over the mixed entries; per tile of 1024 entries, one claim per
 // class on the list counter (the waves' counts summed in LDS first).
 constexpr int kBucketBlock = 1024;
-__global__ __launch_bounds__(kBucketBlock) void bucket_kernel(DevMesh m, const int32_t *mixed, const int32_t *counts,
-                                                              int64_t cap, int32_t *lists, int64_t stride,
-                                                              int32_t *bcount) {
+__global__ __launch_bounds__(kBucketBlock) void bucket_kernel(DevMesh m, int hex0, const int32_t *mixed,
+                                                              const int32_t *counts, int64_t cap, int32_t *lists,
+                                                              int64_t stride, int32_t *bcount) {
   constexpr int kW = kBucketBlock / 64;
   __shared__ int32_t wcnt[kW][kClasses];
   __shared__ int32_t gbase[kClasses];
@@ -1188,7 +1189,7 @@ __global__ __launch_bounds__(kBucketBlock) void bucket_kernel(DevMesh m, const i
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t k0 = (int64_t)blockIdx.x * kBucketBlock; k0 < count; k0 += (int64_t)gridDim.x * kBucketBlock) {
     const int64_t k = k0 + threadIdx.x;
-    const int c = (k < count) ? cell_class(m, mixed[k]) : -1;
+    const int c = (k < count) ? cell_class(m, hex0 != 0, mixed[k]) : -1;
     uint64_t mine = 0;
 #pragma unroll
     for (int q = 0; q < kClasses; ++q) {
@@ -1370,7 +1371,7 @@ vofpc_status launch_reconstruct(vofpc_ctx ctx, vofpc_mesh M, const double *alpha
   const int64_t span = std::min<int64_t>(out->cap, N);
   const int64_t bgrid = std::min<int64_t>((span + kBucketBlock - 1) / kBucketBlock, (int64_t)ctx->n_cu * 2);
   bucket_kernel<<<(unsigned)std::max<int64_t>(bgrid, 1), kBucketBlock, 0, ctx->stream>>>(
-      M->d, mixed, counts, out->cap, M->bucket_lists, N, M->bucket_counts);
+      M->d, M->hex0 ? 1 : 0, mixed, counts, out->cap, M->bucket_lists, N, M->bucket_counts);
   VOFPC_HIP(hipGetLastError());
   // the usual Voronoi class (with its bracket pass) on the context's stream,
   // the other classes beside it on the side stream, forked after the

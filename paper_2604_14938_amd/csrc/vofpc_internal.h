@@ -98,6 +98,48 @@ __host__ __device__ inline int class_of(int64_t nv, int64_t nf, int64_t nl, int6
   if (nv <= 48 && nf <= 32 && nl <= 128 && ne <= 64) return 2;
   return 3;
 }
+// Cells within the hexahedral caps (vertices, faces, loop positions, edges).
+__host__ __device__ inline bool fits_hex(int64_t nv, int64_t nf, int64_t nl, int64_t ne) {
+  return nv <= 8 && nf <= 6 && nl <= 24 && ne <= 12;
+}
+// The class a mesh gives a cell: class_of, except that a mesh whose class 0
+// is all but at most 1 % hexahedral-sized cells (hex0) moves the other
+// class-0 cells to class 1, so its class 0 runs the hexahedral layout.
+__host__ __device__ inline int mesh_class_of(bool hex0, int64_t nv, int64_t nf, int64_t nl, int64_t ne) {
+  const int c = class_of(nv, nf, nl, ne);
+  return (hex0 && c == 0 && !fits_hex(nv, nf, nl, ne)) ? 1 : c;
+}
+// Size statistics of a mesh's cells by class_of, kept so that meshes can be
+// concatenated: counts and largest sizes per class, and of the class-0 cells
+// the number within the hexahedral caps, their largest sizes and those of
+// the others.
+struct ClassStats {
+  int64_t cnt[4] = {0, 0, 0, 0};
+  int64_t max[4][4] = {};
+  int64_t hex_cnt = 0;
+  int64_t hex_max[4] = {0, 0, 0, 0};
+  int64_t rest_max[4] = {0, 0, 0, 0};
+  void add(const int64_t sz[4]) {
+    const int c = class_of(sz[0], sz[1], sz[2], sz[3]);
+    ++cnt[c];
+    for (int t = 0; t < 4; ++t) max[c][t] = max[c][t] > sz[t] ? max[c][t] : sz[t];
+    if (c != 0) return;
+    int64_t *m = fits_hex(sz[0], sz[1], sz[2], sz[3]) ? hex_max : rest_max;
+    if (m == hex_max) ++hex_cnt;
+    for (int t = 0; t < 4; ++t) m[t] = m[t] > sz[t] ? m[t] : sz[t];
+  }
+  void merge(const ClassStats &o) {
+    for (int c = 0; c < 4; ++c) {
+      cnt[c] += o.cnt[c];
+      for (int t = 0; t < 4; ++t) max[c][t] = max[c][t] > o.max[c][t] ? max[c][t] : o.max[c][t];
+    }
+    hex_cnt += o.hex_cnt;
+    for (int t = 0; t < 4; ++t) {
+      hex_max[t] = hex_max[t] > o.hex_max[t] ? hex_max[t] : o.hex_max[t];
+      rest_max[t] = rest_max[t] > o.rest_max[t] ? rest_max[t] : o.rest_max[t];
+    }
+  }
+};
 
 }  // namespace vofpc
 
@@ -148,6 +190,8 @@ struct vofpc_mesh_s {
   // none (allocated by the first such call, outside capture)
   double *hint_buf = nullptr;
   int64_t class_max[vofpc::kClasses][4];   // largest vertices, faces, loop positions, edges per class
+  vofpc::ClassStats class_stats;           // by class_of, before the hex0 move
+  bool hex0;                               // class 0 holds only hexahedral-sized cells (mesh_class_of)
   int max_class;
   bool bucketed;
   int32_t *bucket_lists;

@@ -112,6 +112,12 @@ def test_buckets_and_autotune(R, tmp_path):
     run = R.PathRun(wl, parts=[w.mesh for w in wls])
     cls = run.mesh.classes()
     assert cls["bucketed"] and cls["cells"][0] >= wls[0].mesh.n_cells and cls["cells"][1] > 0
+    # the library's class counts are the host's assignment (the small
+    # Voronoi cells leave the hexahedral class 0 of this union)
+    import bench
+    assert bench.mesh_hex0(wl.mesh)
+    assert cls["cells"] == np.bincount(bench.cell_classes(wl.mesh, np.arange(wl.mesh.n_cells)), minlength=4).tolist()
+    assert cls["cells"][0] == wls[0].mesh.n_cells
     ref = parity.oracle_path(wl)
     # the tuner's own pick (timing decides it: any flavour with a build)
     flavours = {3, 4} | {10 + g for g in (1, 2, 4, 8, 16)}
