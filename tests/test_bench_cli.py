@@ -53,3 +53,38 @@ def test_kernel_classes_and_footprint():
     b2 = bench.recon_bytes(hexm, cells[:2])
     assert 0 < b1 < b2 < 2 * b1
     assert bench.recon_bytes(hexm, cells[:2], learned=True) > b2
+
+
+def test_hexahedral_class_zero_rule_on_the_host():
+    """The bench assigns kernel classes as the library does: a union of a
+    hexahedral mesh and a small Voronoi box moves the Voronoi cells of
+    class 0 to class 1 (at most 1 % of class 0); a Voronoi box alone keeps
+    them."""
+    import bench
+    from synth import meshes
+    hexm = meshes.hex_mesh(12)
+    vor = meshes.voronoi_box_mesh(6, seed=3)
+    both = meshes.concat([hexm, vor])
+    cv = bench.cell_classes(vor, np.arange(vor.n_cells))
+    assert np.count_nonzero(cv == 0) > 0 and not bench.mesh_hex0(vor)
+    assert bench.mesh_hex0(both)
+    cb = bench.cell_classes(both, np.arange(both.n_cells))
+    assert np.all(cb[:hexm.n_cells] == 0)
+    assert np.all(cb[hexm.n_cells:] >= 1)
+    assert np.array_equal(cb[hexm.n_cells:][cv >= 1], cv[cv >= 1])
+
+
+def test_extrapolation_sweep_bytes_count():
+    """The sweep's algorithmic bytes: 92 B per domain cell and 12 B per
+    upwind slot, one upwind slot per face between two domain cells."""
+    import bench
+    from synth import meshes
+    m = meshes.hex_mesh(4)
+    dom = np.zeros(m.n_cells, bool)
+    dom[:16] = True          # the first 16 cells
+    inner = m.face_neigh >= 0
+    faces = int(np.count_nonzero(dom[m.face_owner[inner]] & dom[m.face_neigh[inner]]))
+    r = bench.extrap_sweep_bytes(m, dom, 1.0)
+    assert r["domain_cells"] == 16 and r["upwind_slots_est"] == faces
+    assert r["algorithmic_bytes"] == 16 * 92 + 12 * faces
+    assert abs(r["GBps"] - r["algorithmic_bytes"] / 1e-6 / 1e9) < 1e-9
